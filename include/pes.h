@@ -1,0 +1,125 @@
+/*
+ * libpes -- batched FP64 frequency-domain response and likelihood of
+ * massive-black-hole-binary signals in LISA-, Taiji- and TianQin-like
+ * detectors on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow arXiv:2602.12011:
+ *   Sec. 2.1  the single-link response eq. (eq_fd_resp) evaluated at the SPA
+ *             time-frequency map eq. (eq_tf), the FD TDI 1.5 / 2.0 combinations
+ *             and the A, E, T channels;
+ *   Sec. 2.2  the Whittle likelihood eq. (eq_ll_fd), joint over channels and
+ *             detectors, the inner product eq. (eq_inner_product) and the
+ *             Fisher matrix F_ij = <d_i s | d_j s>.
+ * The waveform is a closed-form post-Newtonian stand-in for PhenomXAS/XHM:
+ * TaylorF2 phase (3.5PN, aligned spins), leading-order mode amplitudes, SPA
+ * mode scaling, modes (2,2), (2,1), (3,3), (3,2), (4,4).
+ *
+ * Conventions shared by every entry point
+ *   - Parameter vector theta, 11 doubles per sample, row-major [B][11]:
+ *       [M_tot (Msun, detector frame), q = m2/m1 in (0,1], chi1, chi2,
+ *        D_L (Gpc), iota, phi_c, lambda, beta, psi, t_c (s from orbit epoch)].
+ *   - Frequency grid f_k = f0 + k df, k = 0 .. n_bins-1.
+ *   - Complex arrays are interleaved (re, im) doubles.
+ *   - Every pointer argument named "dev" is device memory owned by the
+ *     caller; the library never frees it and keeps no reference after the
+ *     call returns.  "stream" is a hipStream_t (NULL = default stream).
+ *   - All compute calls are asynchronous on the given stream and never
+ *     synchronize the host.  A context must not be used from two streams
+ *     at the same time.
+ *   - Return value: PES_OK or a negative pes_status; nothing is thrown.
+ *     A sample with an unphysical theta (non-finite, M_tot <= 0, q outside
+ *     (0,1], |chi| >= 1, D_L <= 0) gets log L = -inf and a zero gradient; the
+ *     call still returns PES_OK.
+ */
+#ifndef PES_H
+#define PES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PES_OK = 0,
+  PES_EINVAL = -1,  /* bad argument (null pointer, unknown mode, bad size) */
+  PES_ESHAPE = -2,  /* sizes inconsistent with the context */
+  PES_ENOMEM = -3,  /* device allocation failed */
+  PES_EHIP = -4,    /* a HIP runtime call failed */
+  PES_ESTATE = -5   /* call order violated (e.g. log L before data was set) */
+} pes_status;
+
+enum { PES_LISA = 0, PES_TAIJI = 1, PES_TIANQIN = 2 };
+
+typedef struct {
+  int kind;            /* PES_LISA / PES_TAIJI: heliocentric orbit; PES_TIANQIN: geocentric */
+  int tdi_gen;         /* 15 or 20 (TDI generation 1.5 or 2.0) */
+  double arm_m;        /* arm length L [m] */
+  double phase0;       /* initial revolution phase of the constellation centre [rad] */
+  double tq_period_s;  /* TianQin: rotation period of the constellation [s] */
+  double tq_lon;       /* TianQin: ecliptic longitude of the constellation-plane normal [rad] */
+  double tq_lat;       /* TianQin: ecliptic latitude of the plane normal [rad] */
+  double oms_asd;      /* optical-metrology noise ASD [m / sqrt(Hz)] */
+  double acc_asd;      /* test-mass acceleration noise ASD [m s^-2 / sqrt(Hz)] */
+} pes_detector;
+
+typedef struct {
+  int n_det;               /* 1..3 */
+  pes_detector det[3];
+  int64_t n_bins;          /* 1 .. 2^26 */
+  double f0;               /* first frequency [Hz], > 0 */
+  double df;               /* spacing [Hz], > 0; also 1/T in the likelihood weights */
+  int n_modes;             /* 1..5 */
+  int modes[5][2];         /* (l, m) pairs from {(2,2),(2,1),(3,3),(3,2),(4,4)} */
+} pes_config;
+
+typedef struct pes_ctx pes_ctx;
+
+/* Create a context on the current HIP device: copies the configuration,
+ * allocates the per-bin tables (frequency powers, TDI delay factors, noise
+ * weights 4 df / S_c(f) of the analytic PSD) and fills them on the device.
+ * Sec. 2.1 (response model) and Sec. 3.2 (noise: OMS + acceleration only).
+ * Errors: PES_EINVAL for an invalid config, PES_ENOMEM, PES_EHIP. */
+int pes_create(const pes_config* cfg, pes_ctx** out);
+
+/* Release all device memory of the context (synchronizes the device). */
+int pes_destroy(pes_ctx* ctx);
+
+/* Reserve workspace for batches of up to max_walkers samples so that later
+ * compute calls allocate nothing (needed before capturing them in a graph). */
+int pes_reserve(pes_ctx* ctx, int64_t max_walkers);
+
+/* Upload the observed data: d (dev) is [n_det][3][n_bins] complex, channels
+ * A, E, T of the configured TDI generation.  Precomputes the noise-weighted,
+ * TDI-factor-folded data and <d|d>.  The array is copied; it may be freed
+ * after the call's work completes on the stream. */
+int pes_set_data(pes_ctx* ctx, const double* d, void* stream);
+
+/* Noise-free response: out (dev) [B][n_det][3][n_bins] complex = A, E, T of
+ * h(theta_b) (eqs. eq_tf, eq_fd_resp, FD TDI, A/E/T). */
+int pes_response(pes_ctx* ctx, const double* theta, int64_t B, double* out, void* stream);
+
+/* log L(theta_b) = -1/2 sum_det sum_{A,E,T} sum_k 4 df |d - h|^2 / S
+ * (eq. eq_ll_fd joint over channels and detectors; constants dropped).
+ * theta (dev) [B][11], logl (dev) [B].  Requires pes_set_data. */
+int pes_loglike(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void* stream);
+
+/* Kernel timing for measurement: with enable != 0 every later pes_loglike
+ * records HIP events around its main (persistent log-likelihood) kernel on
+ * the call's stream, up to 4096 launches.  pes_timing_read waits for the
+ * recorded events, returns the summed kernel time [ms] and the number of
+ * launches, and clears the record.  Events are created and destroyed by the
+ * library. */
+int pes_timing(pes_ctx* ctx, int enable);
+int pes_timing_read(pes_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Human-readable message of a status code (static storage). */
+const char* pes_strerror(int status);
+
+/* Last HIP error text recorded by the context (static per context). */
+const char* pes_last_error(pes_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PES_H */

@@ -1,0 +1,349 @@
+// C-ABI of libpes: context management, argument validation and the launch
+// sequences of each entry point (declared in include/pes.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "../../include/pes.h"
+#include "pes_launch.hpp"
+
+using namespace pes;
+
+namespace {
+
+constexpr double kC = 299792458.0;
+constexpr double kAU = 149597870700.0;
+constexpr double kYear = 31557600.0;   // Julian year [s]
+
+}  // namespace
+
+struct pes_ctx {
+  pes_config cfg;
+  int device = 0;
+  int n_cu = 0;
+  DetTable dt;
+  ModeSpec modes[kMaxModes];
+  int64_t N = 0;
+  // tables
+  double* bins = nullptr;
+  double* tabs = nullptr;
+  double* dd_part = nullptr;
+  double* dd = nullptr;
+  bool has_data = false;
+  // tuning
+  int bpl = 1;
+  int wg = 16;
+  int blocks_per_cu = 2;
+  int tile = 256;
+  int ntmax = 0;
+  // workspace
+  int64_t cap = 0;
+  double* wtab = nullptr;
+  int* ntiles = nullptr;
+  int* perm = nullptr;
+  int* gstart = nullptr;
+  int* counters = nullptr;
+  double* partial = nullptr;
+  // measurement
+  bool timing = false;
+  int n_ev = 0;
+  hipEvent_t* ev = nullptr;   // [kMaxEv][2]
+  char err[256] = {0};
+};
+
+namespace {
+
+constexpr int kMaxEv = 4096;
+
+int fail_hip(pes_ctx* c, hipError_t e, const char* where) {
+  if (c) snprintf(c->err, sizeof(c->err), "%s: %s", where, hipGetErrorString(e));
+  return PES_EHIP;
+}
+
+#define PES_HIP(ctx, call)                                   \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return fail_hip((ctx), e_, #call); \
+  } while (0)
+
+bool mode_ok(int l, int m) {
+  return (l == 2 && (m == 2 || m == 1)) || (l == 3 && (m == 3 || m == 2)) || (l == 4 && m == 4);
+}
+
+void free_workspace(pes_ctx* c) {
+  (void)hipFree(c->wtab);
+  (void)hipFree(c->ntiles);
+  (void)hipFree(c->perm);
+  (void)hipFree(c->gstart);
+  (void)hipFree(c->counters);
+  (void)hipFree(c->partial);
+  c->wtab = nullptr;
+  c->ntiles = c->perm = c->gstart = c->counters = nullptr;
+  c->partial = nullptr;
+  c->cap = 0;
+}
+
+int ensure_workspace(pes_ctx* c, int64_t B) {
+  if (B <= c->cap) return PES_OK;
+  const int64_t cap = std::max<int64_t>(B, 64);
+  free_workspace(c);
+  const int64_t ng = (cap + 1) / 1 + 1;  // groups <= walkers
+  if (hipMalloc(&c->wtab, sizeof(double) * cap * W_STRIDE) != hipSuccess ||
+      hipMalloc(&c->ntiles, sizeof(int) * cap) != hipSuccess ||
+      hipMalloc(&c->perm, sizeof(int) * cap) != hipSuccess ||
+      hipMalloc(&c->gstart, sizeof(int) * (ng + 1)) != hipSuccess ||
+      hipMalloc(&c->counters, sizeof(int) * 4) != hipSuccess ||
+      hipMalloc(&c->partial, sizeof(double) * 2 * cap * (int64_t)c->ntmax) != hipSuccess) {
+    free_workspace(c);
+    snprintf(c->err, sizeof(c->err), "workspace allocation for %lld walkers failed", (long long)cap);
+    return PES_ENOMEM;
+  }
+  c->cap = cap;
+  return PES_OK;
+}
+
+void fill_geometry(const pes_detector& d, DetParams& p) {
+  memset(&p, 0, sizeof(p));
+  p.kind = d.kind;
+  p.tdi_gen = d.tdi_gen;
+  p.L = d.arm_m / kC;
+  p.inv_year = 1.0 / kYear;
+  p.inv_ptq = d.kind == PES_TIANQIN ? 1.0 / d.tq_period_s : 0.0;
+  p.phase0_cyc = d.phase0 / (2.0 * M_PI);
+  p.AUc = kAU / kC;
+  p.oms2 = d.oms_asd * d.oms_asd;
+  p.acc2 = d.acc_asd * d.acc_asd;
+  for (int s = 0; s < 3; ++s) {
+    const double b = 2.0 * M_PI * s / 3.0, cb = cos(b), sb = sin(b);
+    if (d.kind == PES_TIANQIN) {
+      // ring of radius L/sqrt3 in the plane normal to (lon, lat)
+      const double R = p.L / sqrt(3.0);
+      const double nh[3] = {cos(d.tq_lat) * cos(d.tq_lon), cos(d.tq_lat) * sin(d.tq_lon), sin(d.tq_lat)};
+      const double u[3] = {-sin(d.tq_lon), cos(d.tq_lon), 0.0};
+      const double w[3] = {nh[1] * u[2] - nh[2] * u[1], nh[2] * u[0] - nh[0] * u[2], nh[0] * u[1] - nh[1] * u[0]};
+      for (int c = 0; c < 3; ++c) {
+        p.G[s][c][0] = R * (cb * u[c] + sb * w[c]);     // x cos(phi)
+        p.G[s][c][1] = R * (-sb * u[c] + cb * w[c]);    // x sin(phi)
+      }
+    } else {
+      // first-order-in-eccentricity heliocentric orbit, rho = e AU / c = L / (2 sqrt3)
+      const double rho = p.L / (2.0 * sqrt(3.0));
+      p.G[s][0][0] = rho * 0.5 * cb;
+      p.G[s][0][1] = rho * 0.5 * sb;
+      p.G[s][0][4] = -rho * 1.5 * cb;
+      p.G[s][1][0] = -rho * 0.5 * sb;
+      p.G[s][1][1] = rho * 0.5 * cb;
+      p.G[s][1][4] = -rho * 1.5 * sb;
+      p.G[s][2][2] = -rho * sqrt(3.0) * cb;
+      p.G[s][2][3] = -rho * sqrt(3.0) * sb;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pes_strerror(int s) {
+  switch (s) {
+    case PES_OK: return "ok";
+    case PES_EINVAL: return "invalid argument";
+    case PES_ESHAPE: return "size inconsistent with the context";
+    case PES_ENOMEM: return "device allocation failed";
+    case PES_EHIP: return "HIP runtime error";
+    case PES_ESTATE: return "call order violated";
+    default: return "unknown status";
+  }
+}
+
+const char* pes_last_error(pes_ctx* ctx) { return ctx ? ctx->err : "null context"; }
+
+int pes_create(const pes_config* cfg, pes_ctx** out) {
+  if (!cfg || !out) return PES_EINVAL;
+  *out = nullptr;
+  if (cfg->n_det < 1 || cfg->n_det > 3 || cfg->n_bins < 1 || cfg->n_bins > (int64_t(1) << 26) ||
+      !(cfg->f0 > 0) || !(cfg->df > 0) || cfg->n_modes < 1 || cfg->n_modes > 5)
+    return PES_EINVAL;
+  for (int i = 0; i < cfg->n_modes; ++i)
+    if (!mode_ok(cfg->modes[i][0], cfg->modes[i][1])) return PES_EINVAL;
+  for (int i = 0; i < cfg->n_det; ++i) {
+    const pes_detector& d = cfg->det[i];
+    if (d.kind < 0 || d.kind > 2 || (d.tdi_gen != 15 && d.tdi_gen != 20) || !(d.arm_m > 0) ||
+        !(d.oms_asd >= 0) || !(d.acc_asd >= 0) || (d.kind == PES_TIANQIN && !(d.tq_period_s > 0)))
+      return PES_EINVAL;
+  }
+  pes_ctx* c = new (std::nothrow) pes_ctx();
+  if (!c) return PES_ENOMEM;
+  c->cfg = *cfg;
+  c->N = cfg->n_bins;
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+      c->n_cu < 1) {
+    delete c;
+    return PES_EHIP;
+  }
+  for (int i = 0; i < cfg->n_det; ++i) fill_geometry(cfg->det[i], c->dt.p[i]);
+  for (int i = 0; i < cfg->n_modes; ++i) c->modes[i] = ModeSpec{cfg->modes[i][0], cfg->modes[i][1]};
+  c->tile = 256 * c->bpl;
+  c->ntmax = (int)((c->N + c->tile - 1) / c->tile);
+  c->blocks_per_cu = std::max(1, loglike_blocks_per_cu(c->bpl));
+  const int64_t nb = (c->N + 255) / 256;
+  if (hipMalloc(&c->bins, sizeof(double) * B_NFIELDS * c->N) != hipSuccess ||
+      hipMalloc(&c->tabs, sizeof(double) * T_NFIELDS * c->N * cfg->n_det) != hipSuccess ||
+      hipMalloc(&c->dd_part, sizeof(double) * nb) != hipSuccess ||
+      hipMalloc(&c->dd, sizeof(double)) != hipSuccess) {
+    pes_destroy(c);
+    return PES_ENOMEM;
+  }
+  hipError_t e = launch_bin_tables(c->bins, c->tabs, c->N, cfg->f0, cfg->df, cfg->n_det, c->dt, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    pes_destroy(c);
+    return PES_EHIP;
+  }
+  *out = c;
+  return PES_OK;
+}
+
+int pes_destroy(pes_ctx* c) {
+  if (!c) return PES_EINVAL;
+  (void)hipDeviceSynchronize();
+  pes_timing(c, 0);
+  free_workspace(c);
+  (void)hipFree(c->bins);
+  (void)hipFree(c->tabs);
+  (void)hipFree(c->dd_part);
+  (void)hipFree(c->dd);
+  delete c;
+  return PES_OK;
+}
+
+int pes_timing(pes_ctx* c, int enable) {
+  if (!c) return PES_EINVAL;
+  if (enable && !c->ev) {
+    c->ev = new (std::nothrow) hipEvent_t[2 * kMaxEv];
+    if (!c->ev) return PES_ENOMEM;
+    for (int i = 0; i < 2 * kMaxEv; ++i) {
+      if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+        for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
+        delete[] c->ev;
+        c->ev = nullptr;
+        return PES_EHIP;
+      }
+    }
+  }
+  if (!enable && c->ev) {
+    (void)hipDeviceSynchronize();
+    for (int i = 0; i < 2 * kMaxEv; ++i) (void)hipEventDestroy(c->ev[i]);
+    delete[] c->ev;
+    c->ev = nullptr;
+  }
+  c->timing = enable != 0;
+  c->n_ev = 0;
+  return PES_OK;
+}
+
+int pes_timing_read(pes_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return PES_EINVAL;
+  double sum = 0.0;
+  for (int i = 0; i < c->n_ev; ++i) {
+    float ms = 0.f;
+    PES_HIP(c, hipEventSynchronize(c->ev[2 * i + 1]));
+    PES_HIP(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = c->n_ev;
+  c->n_ev = 0;
+  return PES_OK;
+}
+
+int pes_reserve(pes_ctx* c, int64_t max_walkers) {
+  if (!c || max_walkers < 0) return PES_EINVAL;
+  return ensure_workspace(c, max_walkers);
+}
+
+int pes_set_data(pes_ctx* c, const double* d, void* stream) {
+  if (!c || !d) return PES_EINVAL;
+  PES_HIP(c, launch_set_data(d, c->tabs, c->dd_part, c->dd, c->N, c->cfg.n_det, (hipStream_t)stream));
+  c->has_data = true;
+  return PES_OK;
+}
+
+static SetupArgs setup_args(const pes_ctx* c) {
+  SetupArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.n_modes = c->cfg.n_modes;
+  sa.n_det = c->cfg.n_det;
+  for (int i = 0; i < sa.n_modes; ++i) sa.modes[i] = c->modes[i];
+  sa.dt = c->dt;
+  sa.f0 = c->cfg.f0;
+  sa.df = c->cfg.df;
+  sa.N = c->N;
+  sa.tile = c->tile;
+  return sa;
+}
+
+int pes_response(pes_ctx* c, const double* theta, int64_t B, double* out, void* stream) {
+  if (!c || (B > 0 && (!theta || !out)) || B < 0 || B > 65535) return PES_EINVAL;
+  if (B == 0) return PES_OK;
+  int st = ensure_workspace(c, B);
+  if (st != PES_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, setup_args(c), s));
+  ResponseArgs ra;
+  ra.bins = c->bins;
+  ra.tabs = c->tabs;
+  ra.wtab = c->wtab;
+  ra.out = out;
+  ra.N = c->N;
+  ra.n_modes = c->cfg.n_modes;
+  ra.n_det = c->cfg.n_det;
+  ra.dt = c->dt;
+  PES_HIP(c, launch_response(ra, B, s));
+  return PES_OK;
+}
+
+int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* stream) {
+  if (!c || B < 0 || (B > 0 && (!theta || !logl)) || B > (int64_t(1) << 24)) return PES_EINVAL;
+  if (!c->has_data) return PES_ESTATE;
+  if (B == 0) return PES_OK;
+  int st = ensure_workspace(c, B);
+  if (st != PES_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, setup_args(c), s));
+  PES_HIP(c, launch_plan(c->ntiles, (int)B, c->wg, c->ntmax, c->perm, c->gstart, c->counters, s));
+  LoglikeArgs a;
+  a.bins = c->bins;
+  a.tabs = c->tabs;
+  a.wtab = c->wtab;
+  a.ntiles = c->ntiles;
+  a.perm = c->perm;
+  a.gstart = c->gstart;
+  a.counters = c->counters;
+  a.partial = c->partial;
+  a.N = c->N;
+  a.B = (int)B;
+  a.wg = c->wg;
+  a.n_groups = (int)((B + c->wg - 1) / c->wg);
+  a.ntmax = c->ntmax;
+  a.n_modes = c->cfg.n_modes;
+  a.n_det = c->cfg.n_det;
+  a.dt = c->dt;
+  const int grid = c->n_cu * c->blocks_per_cu;
+  const bool rec = c->timing && c->n_ev < kMaxEv;
+  if (rec) PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev], s));
+  PES_HIP(c, launch_loglike(a, c->bpl, grid, s));
+  if (rec) {
+    PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev + 1], s));
+    ++c->n_ev;
+  }
+  PES_HIP(c, launch_finalize(c->partial, c->ntiles, c->wtab, c->dd, B, c->ntmax, logl, s));
+  return PES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,681 @@
+// Kernels of libpes (gfx950): per-bin tables, data folding, per-walker
+// setup, the (walker group, bin tile) work plan, the persistent log-likelihood
+// kernel, the deterministic per-walker reduction and the response kernel.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pes_eval.hpp"
+#include "pes_launch.hpp"
+
+namespace pes {
+
+// ---------------------------------------------------------------- constants
+// G M_sun / c^3 [s]; 1 Gpc / c [s]; Schwarzschild ISCO M f = 6^{-3/2} / pi.
+constexpr double kMsunS = 4.925490947641267e-6;
+constexpr double kGpcS = 3.085677581491367e25 / 299792458.0;
+constexpr double kMfIsco = 0.068041381743977169 / kPi;
+constexpr double kEulerGamma = 0.57721566490153286061;
+
+// ---------------------------------------------------------------- bin tables
+// Per bin: f, f^{1/3}, f^{-1/3}, f^{-7/6}, ln f.  Per detector: z, the common
+// channel factor G, the weights of the analytic PSD with the TDI factor
+// cancelled analytically, W_A = w_A |G|^2 / 2 = df a^2 / Q_A and
+// W_T = w_T |G|^2 / 3 = df a^2 / (3 Q_T), and the raw w_c = 4 df / S_c.
+// The PSD: S_A = S_E = 8 sin^2 x Q_A, S_T = 16 sin^2 x Q_T (TDI 1.5, x = 2 pi f L),
+// times 4 sin^2 2x for TDI 2.0, with Q_A = (2 + cos x) S_oms + 2 (3 + 2 cos x +
+// cos 2x) S_acc and Q_T = 2 sin^2(x/2) (S_oms + 4 sin^2(x/2) S_acc).
+__global__ void bin_tables_kernel(double* __restrict__ bins, double* __restrict__ tabs,
+                                  int64_t N, double f0, double df, int n_det, DetTable dt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const double f = fma((double)k, df, f0);
+  bins[B_F * N + k] = f;
+  const double f13 = cbrt(f);
+  bins[B_F13 * N + k] = f13;
+  bins[B_FM13 * N + k] = 1.0 / f13;
+  bins[B_FM76 * N + k] = 1.0 / (f * sqrt(f13));   // f^{-7/6} = 1 / (f f^{1/6})
+  bins[B_LNF * N + k] = log(f);
+  for (int d = 0; d < n_det; ++d) {
+    const DetParams& p = dt.p[d];
+    double* t = tabs + (int64_t)d * T_NFIELDS * N;
+    const double a = kPi * f * p.L;   // pi f L
+    const double x = 2.0 * a;
+    double sx, cx, s2x, c2x, sh, ch;
+    sincos(x, &sx, &cx);
+    sincos(2.0 * x, &s2x, &c2x);
+    sincos(0.5 * x, &sh, &ch);
+    const double twopif = 2.0 * kPi * f;
+    const double r1 = 2e-3 / f, r2 = 4e-4 / f, r3 = f / 8e-3;
+    const double c = 299792458.0;
+    const double Soms = p.oms2 * (1.0 + r1 * r1 * r1 * r1) * (twopif / c) * (twopif / c);
+    const double Sacc = p.acc2 * (1.0 + r2 * r2) * (1.0 + r3 * r3 * r3 * r3) /
+                        ((twopif * c) * (twopif * c));
+    const double QA = (2.0 + cx) * Soms + 2.0 * (3.0 + 2.0 * cx + c2x) * Sacc;
+    const double QT = 2.0 * sh * sh * (Soms + 4.0 * sh * sh * Sacc);
+    double SA = 8.0 * sx * sx * QA, ST = 16.0 * sx * sx * QT;
+    double Gr, Gi;
+    double ph;  // G = |G| e^{-i ph}
+    double gmag;
+    if (p.tdi_gen == 20) {
+      SA *= 4.0 * s2x * s2x;
+      ST *= 4.0 * s2x * s2x;
+      // G = (1 - z^2)(1 - z^4)(-i a) e^{-i a} = 4 i a sin x sin 2x e^{-3.5 i x}
+      gmag = 4.0 * a * sx * s2x;
+      ph = 3.5 * x - 0.5 * kPi;   // i = e^{+i pi/2}
+    } else {
+      // G = (1 - z^2)(-i a) e^{-i a} = 2 a sin x e^{-1.5 i x}
+      gmag = 2.0 * a * sx;
+      ph = 1.5 * x;
+    }
+    double sph, cph;
+    sincos(ph, &sph, &cph);
+    Gr = gmag * cph;
+    Gi = -gmag * sph;
+    double zs, zc;
+    sincos(x, &zs, &zc);
+    t[T_ZR * N + k] = zc;
+    t[T_ZI * N + k] = -zs;
+    const bool okA = SA != 0.0, okT = ST != 0.0;
+    t[T_WA * N + k] = okA ? df * a * a / QA : 0.0;
+    t[T_WT * N + k] = okT ? df * a * a / (3.0 * QT) : 0.0;
+    t[T_WAE * N + k] = okA ? 4.0 * df / SA : 0.0;
+    t[T_WTT * N + k] = okT ? 4.0 * df / ST : 0.0;
+    t[T_A * N + k] = a;
+    t[T_GR * N + k] = Gr;
+    t[T_GI * N + k] = Gi;
+    t[T_DAR * N + k] = 0.0;
+    t[T_DAI * N + k] = 0.0;
+    t[T_DER * N + k] = 0.0;
+    t[T_DEI * N + k] = 0.0;
+    t[T_DTR * N + k] = 0.0;
+    t[T_DTI * N + k] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- data
+// D_c = w_c n_c conj(G) d_c with n = (1/sqrt2, 1/sqrt6, 1/sqrt3), and per-block
+// partial sums of <d|d> = sum_c w_c |d_c|^2 (fixed-order reduction).
+__global__ void set_data_kernel(const double* __restrict__ d, double* __restrict__ tabs,
+                                double* __restrict__ dd_part, int64_t N, int n_det) {
+  __shared__ double red[256 / 64];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (k < N) {
+    for (int det = 0; det < n_det; ++det) {
+      double* t = tabs + (int64_t)det * T_NFIELDS * N;
+      const double Gr = t[T_GR * N + k], Gi = t[T_GI * N + k];
+      const double wA = t[T_WAE * N + k], wT = t[T_WTT * N + k];
+      const double nrm[3] = {0.70710678118654752440, 0.40824829046386301637,
+                             0.57735026918962576451};
+      const int fr[3] = {T_DAR, T_DER, T_DTR};
+      for (int c = 0; c < 3; ++c) {
+        const double w = (c == 2) ? wT : wA;
+        const double dr = d[2 * ((det * 3 + c) * N + k)];
+        const double di = d[2 * ((det * 3 + c) * N + k) + 1];
+        // conj(G) d
+        const double cr = Gr * dr + Gi * di, ci = Gr * di - Gi * dr;
+        t[fr[c] * N + k] = w * nrm[c] * cr;
+        t[(fr[c] + 1) * N + k] = w * nrm[c] * ci;
+        acc += w * (dr * dr + di * di);
+      }
+    }
+  }
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    dd_part[blockIdx.x] = s;
+  }
+}
+
+// Fixed-order sum of the block partials (one block).
+__global__ void sum_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double red[1024 / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    out[0] = s;
+  }
+}
+
+// ---------------------------------------------------------------- walker setup
+// theta -> per-walker constant table (TaylorF2 stand-in, leading-order mode
+// amplitudes, -2Y_lm closed forms, sky basis, orbit projection coefficients)
+// and the number of active bin tiles.
+__device__ void ylm_pair(int l, int m, double iota, double& yp, double& ym) {
+  // -2Y_{l,+m}(iota, 0) and -2Y_{l,-m}(iota, 0)
+  const double C = cos(0.5 * iota), S = sin(0.5 * iota), c = cos(iota);
+  const double C2 = C * C, S2 = S * S, C4 = C2 * C2, S4 = S2 * S2;
+  if (l == 2 && m == 2) {
+    yp = sqrt(5.0 / (64.0 * kPi)) * (1.0 + c) * (1.0 + c);
+    ym = sqrt(5.0 / (64.0 * kPi)) * (1.0 - c) * (1.0 - c);
+  } else if (l == 2 && m == 1) {
+    yp = sqrt(5.0 / (16.0 * kPi)) * sin(iota) * (1.0 + c);
+    ym = sqrt(5.0 / (16.0 * kPi)) * sin(iota) * (1.0 - c);
+  } else if (l == 3 && m == 3) {
+    yp = -sqrt(21.0 / (2.0 * kPi)) * C4 * C * S;
+    ym = sqrt(21.0 / (2.0 * kPi)) * C * S4 * S;
+  } else if (l == 3 && m == 2) {
+    yp = sqrt(7.0 / (4.0 * kPi)) * C4 * (3.0 * c - 2.0);
+    ym = sqrt(7.0 / (4.0 * kPi)) * S4 * (3.0 * c + 2.0);
+  } else {  // (4, 4)
+    yp = 3.0 * sqrt(7.0 / kPi) * C4 * C2 * S2;
+    ym = 3.0 * sqrt(7.0 / kPi) * C2 * S4 * S2;
+  }
+}
+
+__global__ void setup_kernel(const double* __restrict__ theta, int64_t B, double* __restrict__ wtab,
+                             int* __restrict__ ntiles, SetupArgs sa) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double* th = theta + 11 * b;
+  double* w = wtab + b * W_STRIDE;
+  bool ok = true;
+  for (int i = 0; i < 11; ++i) ok = ok && isfinite(th[i]);
+  ok = ok && th[0] > 0.0 && th[1] > 0.0 && th[1] <= 1.0 && fabs(th[2]) < 1.0 &&
+       fabs(th[3]) < 1.0 && th[4] > 0.0;
+  if (!ok) {
+    for (int i = 0; i < W_STRIDE; ++i) w[i] = 0.0;
+    ntiles[b] = 0;
+    return;
+  }
+  const double M = th[0] * kMsunS;
+  const double q = th[1];
+  const double eta = q / ((1.0 + q) * (1.0 + q));
+  const double delta = (1.0 - q) / (1.0 + q);
+  const double chi1 = th[2], chi2 = th[3];
+  const double chis = 0.5 * (chi1 + chi2), chia = 0.5 * (chi1 - chi2);
+  const double DL = th[4] * kGpcS;
+  const double iota = th[5], phic = th[6], lam = th[7], beta = th[8], psi = th[9], tc = th[10];
+  // TaylorF2 coefficients psi_k (+ ln v parts) -- 3.5PN, aligned spins
+  const double p0 = 1.0;
+  const double p2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
+  const double p3 = -16.0 * kPi + (113.0 / 3.0 - 76.0 / 3.0 * eta) * chis + 113.0 / 3.0 * delta * chia;
+  const double p4 = 15293365.0 / 508032.0 + 27145.0 / 504.0 * eta + 3085.0 / 72.0 * eta * eta -
+                    10.0 * (79.0 / 8.0) * eta * chi1 * chi2;
+  const double p5 = kPi * (38645.0 / 756.0 - 65.0 / 9.0 * eta);
+  const double p5l = 3.0 * p5;
+  const double p6 = 11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * kPi * kPi -
+                    6848.0 / 21.0 * kEulerGamma - 6848.0 / 21.0 * log(4.0) +
+                    (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * kPi * kPi) * eta +
+                    76055.0 / 1728.0 * eta * eta - 127825.0 / 1296.0 * eta * eta * eta;
+  const double p6l = -6848.0 / 21.0;
+  const double p7 = kPi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * eta * eta);
+  w[W_VALID] = 1.0;
+  w[W_TC] = tc;
+  double fmx = 0.0;
+  for (int j = 0; j < sa.n_modes; ++j) {
+    const int l = sa.modes[j].l, m = sa.modes[j].m;
+    double* wm = w + W_MODE0 + j * W_MODE_STRIDE;
+    const double mm = (double)m;
+    const double cm = cbrt(kTwoPi * M / mm);
+    wm[M_CM] = cm;
+    wm[M_CMI] = 1.0 / cm;
+    wm[M_LNCM] = log(cm);
+    // phase in cycles: (m/2) * 3/(128 eta) * sum_k psi_k v^{k-5} / (2 pi)
+    const double pref = 0.5 * mm * 3.0 / (128.0 * eta) / kTwoPi;
+    // constant phase: -(m/2) phi_c - pi/4 - arg(unit_lm), in cycles
+    double argu = 0.0;
+    if (l == 2 && m == 1) argu = -0.5 * kPi;
+    if (l == 3 && m == 3) argu = -0.5 * kPi;
+    if (l == 3 && m == 2) argu = kPi;
+    if (l == 4 && m == 4) argu = kPi;
+    wm[M_C0] = pref * p5 + (-0.5 * mm * phic - 0.25 * kPi - argu) / kTwoPi;
+    wm[M_A0] = pref * p0;
+    wm[M_A2] = pref * p2;
+    wm[M_A3] = pref * p3;
+    wm[M_A4] = pref * p4;
+    wm[M_B5] = pref * p5l;
+    wm[M_A6] = pref * p6;
+    wm[M_B6] = pref * p6l;
+    wm[M_A7] = pref * p7;
+    // t_f - t_c = M/(256 eta) sum_k [(k-5) psi_k + psi_k^{ln}] v^{k-8}, mode-scaled v
+    const double tpref = M / (256.0 * eta);
+    wm[M_T0] = tpref * (-5.0 * p0);
+    wm[M_T2] = tpref * (-3.0 * p2);
+    wm[M_T3] = tpref * (-2.0 * p3);
+    wm[M_T4] = tpref * (-p4);
+    wm[M_T5] = tpref * p5l;
+    wm[M_T6] = tpref * (p6 + p6l);
+    wm[M_T6L] = tpref * p6l;
+    wm[M_T7] = tpref * (2.0 * p7);
+    // amplitude sqrt(2/m) pi sqrt(2 eta/3) M^2 v^{-7/2} |H_lm(v)| / D_L, v^{-7/2} = cm^{-7/2} f^{-7/6}
+    const double apref = sqrt(2.0 / mm) * kPi * sqrt(2.0 * eta / 3.0) * M * M / DL /
+                         (cm * cm * cm * sqrt(cm));
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+    if (l == 2 && m == 2) h0 = 1.0;
+    if (l == 2 && m == 1) h1 = delta / 3.0;
+    if (l == 3 && m == 3) h1 = 0.75 * sqrt(15.0 / 14.0) * delta;
+    if (l == 3 && m == 2) h2 = sqrt(5.0 / 7.0) / 3.0 * (1.0 - 3.0 * eta);
+    if (l == 4 && m == 4) h2 = 8.0 / 9.0 * sqrt(5.0 / 7.0) * (1.0 - 3.0 * eta);
+    wm[M_AM0] = apref * h0;
+    wm[M_AM1] = apref * h1;
+    wm[M_AM2] = apref * h2;
+    double yp, ym;
+    ylm_pair(l, m, iota, yp, ym);
+    const double sgn = (l & 1) ? -1.0 : 1.0;
+    wm[M_KP] = 0.5 * (ym + sgn * yp);
+    wm[M_KC] = 0.5 * (ym - sgn * yp);
+    const double fcut = 0.5 * mm * kMfIsco / M;
+    wm[M_FCI] = 1.0 / fcut;
+    fmx = fmx > fcut ? fmx : fcut;
+  }
+  for (int j = sa.n_modes; j < kMaxModes; ++j)
+    for (int i = 0; i < W_MODE_STRIDE; ++i) w[W_MODE0 + j * W_MODE_STRIDE + i] = 0.0;
+  w[W_FMAX] = fmx;
+  // sky basis: source direction (lam, beta), k = -nhat, axes p, q rotated by psi
+  const double cl = cos(lam), sl = sin(lam), cb = cos(beta), sb = sin(beta);
+  const double cps = cos(psi), sps = sin(psi);
+  const double kv[3] = {-cb * cl, -cb * sl, -sb};
+  const double uu[3] = {-sl, cl, 0.0};
+  const double vv[3] = {-sb * cl, -sb * sl, cb};
+  double pv[3], qv[3];
+  for (int i = 0; i < 3; ++i) {
+    pv[i] = cps * uu[i] + sps * vv[i];
+    qv[i] = -sps * uu[i] + cps * vv[i];
+  }
+  for (int d = 0; d < sa.n_det; ++d) {
+    const DetParams& P = sa.dt.p[d];
+    double* wd = w + W_DET0 + d * W_DET_STRIDE;
+    wd[D_AO] = tc * P.inv_year + P.phase0_cyc;
+    wd[D_PO] = tc * P.inv_ptq;
+    for (int t = 0; t < 2; ++t) {
+      const int s1 = (t + 1) % 3, s2 = (t + 2) % 3;
+      for (int i = 0; i < 5; ++i) {
+        double kn = 0.0, np = 0.0, nq = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          const double n = (P.G[s2][c][i] - P.G[s1][c][i]) / P.L;
+          kn += kv[c] * n;
+          np += pv[c] * n;
+          nq += qv[c] * n;
+        }
+        wd[D_KN + 5 * t + i] = kn;
+        wd[D_NP + 5 * t + i] = np;
+        wd[D_NQ + 5 * t + i] = nq;
+        double kd = 0.0;
+        for (int c = 0; c < 3; ++c) kd += kv[c] * P.G[t][c][i];
+        wd[D_KD + 5 * t + i] = kd;
+      }
+    }
+    wd[D_KR] = P.AUc * kv[0];
+    wd[D_KR + 1] = P.AUc * kv[1];
+  }
+  // active bins: f_k < fmax (upper bound; the kernel tests each mode exactly)
+  double nb = ceil((fmx - sa.f0) / sa.df) + 1.0;
+  nb = fmin(fmax(nb, 0.0), (double)sa.N);
+  const int64_t nact = (int64_t)nb;
+  ntiles[b] = (int)((nact + sa.tile - 1) / sa.tile);
+}
+
+// ---------------------------------------------------------------- work plan
+// One block: counting sort of the walkers by active tile count (descending,
+// keys quantized to at most kPlanKeys buckets), walker groups of `wg`
+// consecutive sorted walkers, each group's tile count (its maximum), their
+// exclusive prefix sum (group-major work items), and the queue counters.
+constexpr int kPlanKeys = 8192;
+
+// Exclusive scan, in place, of n ints in global memory by one 1024-thread
+// block (each thread owns a contiguous chunk); returns the total to every thread.
+__device__ int block_exclusive_scan(int* __restrict__ a, int n, int* wsum) {
+  const int per = (n + 1023) / 1024;
+  const int base = threadIdx.x * per;
+  int local = 0;
+  for (int i = 0; i < per; ++i)
+    if (base + i < n) local += a[base + i];
+  int incl = local;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < 1024 / 64; ++i) {
+      const int t = wsum[i];
+      wsum[i] = run;
+      run += t;
+    }
+    wsum[16] = run;
+  }
+  __syncthreads();
+  int run = incl - local + wsum[wv];
+  for (int i = 0; i < per; ++i)
+    if (base + i < n) {
+      const int h = a[base + i];
+      a[base + i] = run;
+      run += h;
+    }
+  const int total = wsum[16];
+  __syncthreads();
+  return total;
+}
+
+__global__ void __launch_bounds__(1024) plan_kernel(const int* __restrict__ ntiles, int B, int wg,
+                                                    int ntmax, int* __restrict__ perm,
+                                                    int* __restrict__ gstart, int* __restrict__ counters) {
+  __shared__ int hist[kPlanKeys];
+  __shared__ int wsum[17];
+  int shift = 0;
+  while ((ntmax >> shift) >= kPlanKeys) ++shift;
+  for (int i = threadIdx.x; i < kPlanKeys; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    const int key = kPlanKeys - 1 - (ntiles[b] >> shift);   // descending tile counts
+    atomicAdd(&hist[key], 1);
+  }
+  __syncthreads();
+  {  // exclusive scan of the histogram in LDS (8 entries per thread)
+    const int per = kPlanKeys / 1024;
+    const int base = threadIdx.x * per;
+    int local = 0;
+    for (int i = 0; i < per; ++i) local += hist[base + i];
+    int incl = local;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int run = 0;
+      for (int i = 0; i < 1024 / 64; ++i) {
+        const int t = wsum[i];
+        wsum[i] = run;
+        run += t;
+      }
+    }
+    __syncthreads();
+    int run = incl - local + wsum[wv];
+    for (int i = 0; i < per; ++i) {
+      const int h = hist[base + i];
+      hist[base + i] = run;
+      run += h;
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    const int key = kPlanKeys - 1 - (ntiles[b] >> shift);
+    const int pos = atomicAdd(&hist[key], 1);
+    perm[pos] = b;
+  }
+  __syncthreads();
+  // each group's tile count (the maximum over its walkers), then the
+  // exclusive prefix over groups: work item i belongs to the group g with
+  // gstart[g] <= i < gstart[g + 1], tile i - gstart[g]
+  const int ng = (B + wg - 1) / wg;
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+    int mx = 0;
+    for (int s = 0; s < wg; ++s) {
+      const int idx = g * wg + s;
+      if (idx < B) {
+        const int nt = ntiles[perm[idx]];
+        mx = nt > mx ? nt : mx;
+      }
+    }
+    gstart[g] = mx;
+  }
+  __syncthreads();
+  const int total = block_exclusive_scan(gstart, ng, wsum);
+  if (threadIdx.x == 0) {
+    gstart[ng] = total;
+    counters[0] = 0;      // ticket
+    counters[1] = total;  // number of work items
+  }
+}
+
+// ---------------------------------------------------------------- log-likelihood
+// Persistent kernel: each block takes (group, tile) items from an atomic
+// ticket.  Lanes own bins; the walkers of the group are processed in turn,
+// each lane evaluating its bins, then a wavefront reduction and one LDS slot
+// per (walker, wave).  partial[w][tile] = (<d|h>, <h|h>) of that tile.
+template <int BPL>
+__global__ void __launch_bounds__(256)
+    loglike_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
+                   const double* __restrict__ wtab, const int* __restrict__ ntiles,
+                   const int* __restrict__ perm, const int* __restrict__ gstart,
+                   int* __restrict__ counters, double* __restrict__ partial, LoglikeArgs A) {
+  __shared__ double acc[kMaxGroup][4][2];
+  __shared__ int s_item[2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t N = A.N;
+  const int tile = 256 * BPL;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const int it = atomicAdd(&counters[0], 1);
+      int g = -1;
+      if (it < counters[1]) {
+        // group-major: largest g with gstart[g] <= it
+        int lo = 0, hi = A.n_groups;   // gstart[lo] <= it < gstart[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (gstart[mid] <= it) lo = mid; else hi = mid;
+        }
+        g = lo;
+      }
+      s_item[0] = it;
+      s_item[1] = g;
+    }
+    __syncthreads();
+    const int it = s_item[0];
+    const int g = __builtin_amdgcn_readfirstlane(s_item[1]);
+    if (g < 0) break;
+    const int t = __builtin_amdgcn_readfirstlane(it - gstart[g]);
+    const int64_t k0 = (int64_t)t * tile;
+    for (int det = 0; det < A.n_det; ++det) {
+      const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * N;
+      BinRegs br[BPL];
+      double zr[BPL], zi[BPL], dar[BPL], dai[BPL], der[BPL], dei[BPL], dtr[BPL], dti[BPL], wa[BPL],
+          wtt[BPL], aa[BPL];
+      bool in[BPL];
+#pragma unroll
+      for (int q = 0; q < BPL; ++q) {
+        const int64_t k = k0 + q * 256 + threadIdx.x;
+        in[q] = k < N;
+        const int64_t kk = in[q] ? k : N - 1;
+        br[q].f = bins[B_F * N + kk];
+        br[q].f13 = bins[B_F13 * N + kk];
+        br[q].fm13 = bins[B_FM13 * N + kk];
+        br[q].fm76 = bins[B_FM76 * N + kk];
+        br[q].lnf = bins[B_LNF * N + kk];
+        zr[q] = tb[T_ZR * N + kk];
+        zi[q] = tb[T_ZI * N + kk];
+        dar[q] = tb[T_DAR * N + kk];
+        dai[q] = tb[T_DAI * N + kk];
+        der[q] = tb[T_DER * N + kk];
+        dei[q] = tb[T_DEI * N + kk];
+        dtr[q] = tb[T_DTR * N + kk];
+        dti[q] = tb[T_DTI * N + kk];
+        wa[q] = in[q] ? tb[T_WA * N + kk] : 0.0;
+        wtt[q] = in[q] ? tb[T_WT * N + kk] : 0.0;
+        aa[q] = tb[T_A * N + kk];
+        if (!in[q]) { dar[q] = dai[q] = der[q] = dei[q] = dtr[q] = dti[q] = 0.0; }
+      }
+      const DetParams& P = A.dt.p[det];
+      for (int s = 0; s < A.wg; ++s) {
+        const int idx = g * A.wg + s;
+        if (idx >= A.B) break;
+        const int w = __builtin_amdgcn_readfirstlane(perm[idx]);
+        if (t >= ntiles[w]) continue;
+        const double* __restrict__ wt = wtab + (int64_t)w * W_STRIDE;
+        const double* __restrict__ wd = wt + W_DET0 + det * W_DET_STRIDE;
+        double dh = 0.0, hh = 0.0;
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+          const Chan c = (P.kind == 2)
+                             ? eval_channels<true>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
+                             : eval_channels<false>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
+          dh = fma(dar[q], c.ar, dh);
+          dh = fma(dai[q], c.ai, dh);
+          dh = fma(der[q], c.er, dh);
+          dh = fma(dei[q], c.ei, dh);
+          dh = fma(dtr[q], c.tr, dh);
+          dh = fma(dti[q], c.ti, dh);
+          const double a2 = fma(c.ar, c.ar, c.ai * c.ai) + (1.0 / 3.0) * fma(c.er, c.er, c.ei * c.ei);
+          const double t2 = fma(c.tr, c.tr, c.ti * c.ti);
+          hh = fma(wa[q], a2, fma(wtt[q], t2, hh));
+        }
+        dh = wave_sum(dh);
+        hh = wave_sum(hh);
+        if (lane == 0) {
+          if (det == 0) {
+            acc[s][wv][0] = dh;
+            acc[s][wv][1] = hh;
+          } else {
+            acc[s][wv][0] += dh;
+            acc[s][wv][1] += hh;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < A.wg) {
+      const int s = threadIdx.x;
+      const int idx = g * A.wg + s;
+      if (idx < A.B) {
+        const int w = perm[idx];
+        if (t < ntiles[w]) {
+          const double dh = (acc[s][0][0] + acc[s][1][0]) + (acc[s][2][0] + acc[s][3][0]);
+          const double hh = (acc[s][0][1] + acc[s][1][1]) + (acc[s][2][1] + acc[s][3][1]);
+          double* p = partial + ((int64_t)w * A.ntmax + t) * 2;
+          p[0] = dh;
+          p[1] = hh;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// log L = <d|h> - <h|h>/2 - <d|d>/2, tiles summed in order.
+__global__ void finalize_kernel(const double* __restrict__ partial, const int* __restrict__ ntiles,
+                                const double* __restrict__ wtab, const double* __restrict__ dd,
+                                int64_t B, int ntmax, double* __restrict__ logl) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  if (wtab[b * W_STRIDE + W_VALID] == 0.0) {
+    logl[b] = -INFINITY;
+    return;
+  }
+  const int nt = ntiles[b];
+  const double* p = partial + b * (int64_t)ntmax * 2;
+  double dh = 0.0, hh = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    dh += p[2 * t];
+    hh += p[2 * t + 1];
+  }
+  logl[b] = (dh - 0.5 * hh) - 0.5 * dd[0];
+}
+
+// ---------------------------------------------------------------- response
+// out[b][det][c][k] = n_c G(f_k) C''_c for one walker per blockIdx.y.
+__global__ void response_kernel(ResponseArgs A) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = blockIdx.y;
+  if (k >= A.N) return;
+  const double* __restrict__ wt = A.wtab + b * W_STRIDE;
+  const int64_t N = A.N;
+  const bool valid = wt[W_VALID] != 0.0;
+  BinRegs br;
+  br.f = A.bins[B_F * N + k];
+  br.f13 = A.bins[B_F13 * N + k];
+  br.fm13 = A.bins[B_FM13 * N + k];
+  br.fm76 = A.bins[B_FM76 * N + k];
+  br.lnf = A.bins[B_LNF * N + k];
+  for (int det = 0; det < A.n_det; ++det) {
+    const double* __restrict__ tb = A.tabs + (int64_t)det * T_NFIELDS * N;
+    const DetParams& P = A.dt.p[det];
+    const double* __restrict__ wd = wt + W_DET0 + det * W_DET_STRIDE;
+    Chan c = {0, 0, 0, 0, 0, 0};
+    if (valid) {
+      c = (P.kind == 2) ? eval_channels<true>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+                                              tb[T_ZR * N + k], tb[T_ZI * N + k])
+                        : eval_channels<false>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+                                               tb[T_ZR * N + k], tb[T_ZI * N + k]);
+    }
+    const double Gr = tb[T_GR * N + k], Gi = tb[T_GI * N + k];
+    const double nrm[3] = {0.70710678118654752440, 0.40824829046386301637, 0.57735026918962576451};
+    const double cr[3] = {c.ar, c.er, c.tr}, ci[3] = {c.ai, c.ei, c.ti};
+    for (int ch = 0; ch < 3; ++ch) {
+      double* o = A.out + 2 * (((b * A.n_det + det) * 3 + ch) * N + k);
+      o[0] = valid ? nrm[ch] * (Gr * cr[ch] - Gi * ci[ch]) : NAN;
+      o[1] = valid ? nrm[ch] * (Gr * ci[ch] + Gi * cr[ch]) : NAN;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_bin_tables(double* bins, double* tabs, int64_t N, double f0, double df, int n_det,
+                             const DetTable& dt, hipStream_t s) {
+  const int bs = 256;
+  hipLaunchKernelGGL(bin_tables_kernel, dim3((unsigned)((N + bs - 1) / bs)), dim3(bs), 0, s, bins, tabs,
+                     N, f0, df, n_det, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_data(const double* d, double* tabs, double* dd_part, double* dd, int64_t N,
+                           int n_det, hipStream_t s) {
+  const int bs = 256;
+  const int nb = (int)((N + bs - 1) / bs);
+  hipLaunchKernelGGL(set_data_kernel, dim3(nb), dim3(bs), 0, s, d, tabs, dd_part, N, n_det);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1024), 0, s, dd_part, nb, dd);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup(const double* theta, int64_t B, double* wtab, int* ntiles, const SetupArgs& sa,
+                        hipStream_t s) {
+  const int bs = 64;
+  hipLaunchKernelGGL(setup_kernel, dim3((unsigned)((B + bs - 1) / bs)), dim3(bs), 0, s, theta, B, wtab,
+                     ntiles, sa);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, int* perm, int* gstart, int* counters,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, ntiles, B, wg, ntmax, perm, gstart, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_loglike(const LoglikeArgs& a, int bpl, int grid, hipStream_t s) {
+  if (bpl == 2)
+    hipLaunchKernelGGL(loglike_kernel<2>, dim3(grid), dim3(256), 0, s, a.bins, a.tabs, a.wtab, a.ntiles,
+                       a.perm, a.gstart, a.counters, a.partial, a);
+  else
+    hipLaunchKernelGGL(loglike_kernel<1>, dim3(grid), dim3(256), 0, s, a.bins, a.tabs, a.wtab, a.ntiles,
+                       a.perm, a.gstart, a.counters, a.partial, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
+                           int64_t B, int ntmax, double* logl, hipStream_t s) {
+  const int bs = 256;
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((B + bs - 1) / bs)), dim3(bs), 0, s, partial, ntiles,
+                     wtab, dd, B, ntmax, logl);
+  return hipGetLastError();
+}
+
+hipError_t launch_response(const ResponseArgs& a, int64_t B, hipStream_t s) {
+  const int bs = 256;
+  hipLaunchKernelGGL(response_kernel, dim3((unsigned)((a.N + bs - 1) / bs), (unsigned)B), dim3(bs), 0, s, a);
+  return hipGetLastError();
+}
+
+int loglike_blocks_per_cu(int bpl) {
+  int nb = 0;
+  hipError_t e = (bpl == 2) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2>, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1>, 256, 0);
+  return e == hipSuccess ? nb : 1;
+}
+
+}  // namespace pes

@@ -1,0 +1,63 @@
+// Kernel argument blocks and launchers (host side of the kernels TU).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pes_layout.hpp"
+
+namespace pes {
+
+constexpr int kMaxGroup = 64;   // walkers per work item, upper bound
+
+struct DetTable {
+  DetParams p[kMaxDet];
+};
+
+struct SetupArgs {
+  int n_modes, n_det;
+  ModeSpec modes[kMaxModes];
+  DetTable dt;
+  double f0, df;
+  int64_t N;
+  int tile;
+};
+
+struct LoglikeArgs {
+  const double* bins;
+  const double* tabs;
+  const double* wtab;
+  const int* ntiles;
+  const int* perm;
+  const int* gstart;
+  int* counters;
+  double* partial;
+  int64_t N;
+  int B, wg, n_groups, ntmax, n_modes, n_det;
+  DetTable dt;
+};
+
+struct ResponseArgs {
+  const double* bins;
+  const double* tabs;
+  const double* wtab;
+  double* out;
+  int64_t N;
+  int n_modes, n_det;
+  DetTable dt;
+};
+
+hipError_t launch_bin_tables(double* bins, double* tabs, int64_t N, double f0, double df, int n_det,
+                             const DetTable& dt, hipStream_t s);
+hipError_t launch_set_data(const double* d, double* tabs, double* dd_part, double* dd, int64_t N,
+                           int n_det, hipStream_t s);
+hipError_t launch_setup(const double* theta, int64_t B, double* wtab, int* ntiles, const SetupArgs& sa,
+                        hipStream_t s);
+hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, int* perm, int* gstart, int* counters,
+                       hipStream_t s);
+hipError_t launch_loglike(const LoglikeArgs& a, int bpl, int grid, hipStream_t s);
+hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
+                           int64_t B, int ntmax, double* logl, hipStream_t s);
+hipError_t launch_response(const ResponseArgs& a, int64_t B, hipStream_t s);
+int loglike_blocks_per_cu(int bpl);
+
+}  // namespace pes

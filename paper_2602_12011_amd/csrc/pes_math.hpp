@@ -1,0 +1,66 @@
+// FP64 device math for the response kernels.  Phases are carried in cycles and
+// reduced exactly (x - rint(x) is exact in binary floating point) before a
+// short polynomial, so no general-purpose transcendental with its
+// large-argument reduction sits in the hot loop.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pes_poly.hpp"
+
+namespace pes {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.141592653589793238462643383279503;
+
+template <int N>
+__device__ __forceinline__ double horner(const double (&c)[N], double t) {
+  double p = c[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) p = fma(p, t, c[i]);
+  return p;
+}
+
+// sin(2 pi x), cos(2 pi x) for any finite x given in cycles.
+// r = x - rint(x) in [-1/2, 1/2], quadrant q = rint(4 r), y = r - q/4 in
+// [-1/8, 1/8] (both exact), then the fitted polynomials and a quadrant swap.
+__device__ __forceinline__ void sincos_cycles(double x, double& s, double& c) {
+  const double r = x - rint(x);
+  const double q = rint(4.0 * r);
+  const double y = fma(-0.25, q, r);
+  const double t = y * y;
+  const double sy = y * horner(kSin2pi, t);
+  const double cy = horner(kCos2pi, t);
+  const int qi = static_cast<int>(q) & 3;
+  const double ss = (qi & 1) ? cy : sy;
+  const double cc = (qi & 1) ? sy : cy;
+  s = (qi & 2) ? -ss : ss;
+  c = ((qi + 1) & 2) ? -cc : cc;
+}
+
+// sin(b)/b.  Polynomial in b^2 on b^2 <= kSincTMax; beyond that (only for
+// grids above ~2.2 / (2 pi L)) the quotient of the cycle-reduced sine.
+__device__ __noinline__ double sinc_large(double b) {
+  double s, c;
+  sincos_cycles(b * (1.0 / kTwoPi), s, c);
+  return s / b;
+}
+__device__ __forceinline__ double sinc(double b) {
+  const double t = b * b;
+  if (t <= kSincTMax) return horner(kSinc, t);
+  return sinc_large(b);
+}
+
+// Exact split of a product: p + e == a * b exactly (e from one fused multiply-add).
+__device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
+  p = a * b;
+  e = fma(a, b, -p);
+}
+
+// 64-lane wavefront sum (butterfly over the full wave; every lane ends with the total).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace pes
