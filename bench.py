@@ -29,16 +29,19 @@ METRIC = "logL evals/s @2^20 bins, 5 modes (FP64); ESS/s learned vs plain propos
 PEAK_FP64_VECTOR_TFLOPS = 78.6     # MI355X FP64 vector peak (AMD specification)
 
 # FP64 operations (FMA counted as 2) of the kernel's formulation, counted from
-# its source: per active (walker, bin, detector, mode) unit and per active
-# (walker, bin, detector) for the TDI combination and the inner products.
-FLOPS_PER_MODE_UNIT = {"helio": 470, "geo": 500}
-FLOPS_PER_WBD_UNIT = 81
+# its source: per active (walker, bin, detector, mode) unit -- heliocentric or
+# geocentric orbit, short or long sinc fit -- and per active (walker, bin,
+# detector) for the TDI combination and the inner products.  The C^2 taper
+# (the last 10% below each cutoff) is not counted.
+FLOPS_PER_MODE_UNIT = {("helio", False): 459, ("geo", False): 485,
+                       ("helio", True): 487, ("geo", True): 513}
+FLOPS_PER_WBD_UNIT = 83
 MF_ISCO = 6.0 ** -1.5 / math.pi
 MSUN_S = 4.925490947641267e-6
 
 
 def active_units(cfg, theta):
-    """(mode units, walker-bin-detector units) that one pes_loglike evaluates."""
+    """(mode units, walker-bin units) per detector that one pes_loglike evaluates."""
     N, f0, df = cfg["n_bins"], cfg["f0"], cfg["df"]
     M = theta[:, 0] * MSUN_S
     n_mode = np.zeros(len(theta))
@@ -48,8 +51,20 @@ def active_units(cfg, theta):
         n = np.clip(np.ceil((fcut - f0) / df), 0, N)
         n_mode += n
         n_any = np.maximum(n_any, n)
+    return float(n_mode.sum()), float(n_any.sum())
+
+
+def algorithmic_flops(cfg, theta):
+    n_mode, n_wb = active_units(cfg, theta)
+    f_max = cfg["f0"] + (cfg["n_bins"] - 1) * cfg["df"]
+    total = 0.0
+    for d in cfg["detectors"]:
+        L = d["arm_m"] / 299792458.0
+        long_sinc = (2 * math.pi * f_max * L) ** 2 > 4.9
+        orbit = "geo" if d["kind"] == "tianqin" else "helio"
+        total += FLOPS_PER_MODE_UNIT[(orbit, long_sinc)] * n_mode + FLOPS_PER_WBD_UNIT * n_wb
     nd = len(cfg["detectors"])
-    return float(n_mode.sum()) * nd, float(n_any.sum()) * nd
+    return total, n_mode * nd, n_wb * nd
 
 
 def cpu_baseline(cfg, theta, n_sample, threads):
@@ -72,7 +87,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes=src.numel() * 8, launches=3)))
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(walkers are independent: N GPUs would each run their own batch).", file=sys.stderr)
@@ -111,9 +137,7 @@ def main():
     ms_per_step = total_ms / args.steps
     value = B / (ms_per_step * 1e-3)
 
-    n_mode, n_wbd = active_units(cfg, theta_np)
-    geo = all(d["kind"] == "tianqin" for d in cfg["detectors"])
-    flops = FLOPS_PER_MODE_UNIT["geo" if geo else "helio"] * n_mode + FLOPS_PER_WBD_UNIT * n_wbd
+    flops, n_mode, n_wbd = algorithmic_flops(cfg, theta_np)
     kern_s = kern_ms / launches * 1e-3
     achieved = flops / kern_s / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_VECTOR_TFLOPS,

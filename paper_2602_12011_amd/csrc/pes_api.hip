@@ -36,6 +36,7 @@ struct pes_ctx {
   bool has_data = false;
   // tuning
   int bpl = 1;
+  bool long_sinc = false;   // a detector's largest sinc argument exceeds the short fit
   int wg = 16;
   int blocks_per_cu = 2;
   int tile = 256;
@@ -187,10 +188,20 @@ int pes_create(const pes_config* cfg, pes_ctx** out) {
     return PES_EHIP;
   }
   for (int i = 0; i < cfg->n_det; ++i) fill_geometry(cfg->det[i], c->dt.p[i]);
+  // largest link sinc argument pi f L (1 + |k.n|) <= 2 pi f_max L per detector
+  const double fmax_grid = cfg->f0 + (double)(cfg->n_bins - 1) * cfg->df;
+  for (int i = 0; i < cfg->n_det; ++i) {
+    const double bmax = 2.0 * M_PI * fmax_grid * c->dt.p[i].L;
+    if (bmax * bmax > 16.0) {   // beyond the long sinc fit (f L > 0.64)
+      delete c;
+      return PES_EINVAL;
+    }
+    if (bmax * bmax > 4.9) c->long_sinc = true;
+  }
   for (int i = 0; i < cfg->n_modes; ++i) c->modes[i] = ModeSpec{cfg->modes[i][0], cfg->modes[i][1]};
   c->tile = 256 * c->bpl;
   c->ntmax = (int)((c->N + c->tile - 1) / c->tile);
-  c->blocks_per_cu = std::max(1, loglike_blocks_per_cu(c->bpl));
+  c->blocks_per_cu = std::max(1, loglike_blocks_per_cu(c->bpl, c->long_sinc));
   const int64_t nb = (c->N + 255) / 256;
   if (hipMalloc(&c->bins, sizeof(double) * B_NFIELDS * c->N) != hipSuccess ||
       hipMalloc(&c->tabs, sizeof(double) * T_NFIELDS * c->N * cfg->n_det) != hipSuccess ||
@@ -304,7 +315,7 @@ int pes_response(pes_ctx* c, const double* theta, int64_t B, double* out, void* 
   ra.n_modes = c->cfg.n_modes;
   ra.n_det = c->cfg.n_det;
   ra.dt = c->dt;
-  PES_HIP(c, launch_response(ra, B, s));
+  PES_HIP(c, launch_response(ra, B, c->long_sinc, s));
   return PES_OK;
 }
 
@@ -337,12 +348,12 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
   const int grid = c->n_cu * c->blocks_per_cu;
   const bool rec = c->timing && c->n_ev < kMaxEv;
   if (rec) PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev], s));
-  PES_HIP(c, launch_loglike(a, c->bpl, grid, s));
+  PES_HIP(c, launch_loglike(a, c->bpl, c->long_sinc, grid, s));
   if (rec) {
     PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev + 1], s));
     ++c->n_ev;
   }
-  PES_HIP(c, launch_finalize(c->partial, c->ntiles, c->wtab, c->dd, B, c->ntmax, logl, s));
+  PES_HIP(c, launch_finalize(c->partial, c->ntiles, c->wtab, c->dd, B, logl, s));
   return PES_OK;
 }
 

@@ -20,7 +20,7 @@ struct Chan {
 
 // wt: this walker's constant table (wavefront-uniform); wd: its detector block.
 // GEO selects the geocentric orbit.  a = pi f L, (zr, zi) = e^{-2 pi i f L}.
-template <bool GEO>
+template <bool GEO, bool LONG_SINC>
 __device__ __forceinline__ Chan eval_channels(const double* __restrict__ wt,
                                               const double* __restrict__ wd, int n_modes,
                                               double inv_year, double inv_ptq, const BinRegs& b,
@@ -33,47 +33,60 @@ __device__ __forceinline__ Chan eval_channels(const double* __restrict__ wt,
   two_prod(b.f, wt[W_TC], pt, et);
   const double ftc = (pt - rint(pt)) + et;
   const double half_f = 0.5 * b.f;
+  const double pi_f = kPi * b.f;
 
   for (int j = 0; j < n_modes; ++j) {
+    // Walker constants (wavefront-uniform, in scalar registers) enter as
+    // multiplicands or plain addends, never as the addend of a fused
+    // multiply-add, so no vector copy of a scalar operand is needed.
     const double* __restrict__ wm = wt + W_MODE0 + j * W_MODE_STRIDE;
     const double x = b.f * wm[M_FCI];
     if (!(x < 1.0)) continue;  // beyond this mode's cutoff (diverges only in the cutoff tile)
     const double v = wm[M_CM] * b.f13;
     const double w = wm[M_CMI] * b.fm13;
-    const double lnv = fma(b.lnf, 1.0 / 3.0, wm[M_LNCM]);
-    const double w2 = w * w;
+    const double lnv = b.lnf * (1.0 / 3.0) + wm[M_LNCM];
+    const double w2 = w * w, w3 = w2 * w, w4 = w2 * w2, w5 = w4 * w, w6 = w4 * w2, w8 = w4 * w4;
+    const double v2 = v * v, lv = lnv * v, lw2 = lnv * w2;
     // SPA phase of the mode, in cycles
-    double pw = fma(w2, wm[M_A0], wm[M_A2]);
-    pw = fma(pw, w, wm[M_A3]);
-    pw = fma(pw, w, wm[M_A4]);
-    pw *= w;
-    const double pv = fma(wm[M_A7], v, fma(wm[M_B6], lnv, wm[M_A6])) * v;
-    const double phase = ftc + (wm[M_C0] + fma(wm[M_B5], lnv, pw + pv));
+    double ph = wm[M_A4] * w;
+    ph = fma(wm[M_A3], w2, ph);
+    ph = fma(wm[M_A2], w3, ph);
+    ph = fma(wm[M_A0], w5, ph);
+    ph = fma(wm[M_B5], lnv, ph);
+    ph = fma(wm[M_A6], v, ph);
+    ph = fma(wm[M_B6], lv, ph);
+    ph = fma(wm[M_A7], v2, ph);
+    const double phase = ftc + (ph + wm[M_C0]);
     // t_f - t_c from the same series (eq. eq_tf)
-    double tp = fma(w2, wm[M_T0], wm[M_T2]);
-    tp = fma(tp, w, wm[M_T3]);
-    tp = fma(tp, w, wm[M_T4]);
-    tp = fma(tp, w, wm[M_T5]);
-    tp = fma(tp, w, fma(wm[M_T6L], lnv, wm[M_T6]));
-    tp = fma(tp, w, wm[M_T7]);
-    const double tau = tp * w;
-    // amplitude with the C^2 cutoff taper
-    const double u = fmin(fmax((x - 0.9) * 10.0, 0.0), 1.0);
-    const double taper = fma(-u * u * u, fma(u, fma(6.0, u, -15.0), 10.0), 1.0);
-    const double amp = b.fm76 * taper * fma(v, fma(v, wm[M_AM2], wm[M_AM1]), wm[M_AM0]);
+    double tau = wm[M_T7] * w;
+    tau = fma(wm[M_T6], w2, tau);
+    tau = fma(wm[M_T6L], lw2, tau);
+    tau = fma(wm[M_T5], w3, tau);
+    tau = fma(wm[M_T4], w4, tau);
+    tau = fma(wm[M_T3], w5, tau);
+    tau = fma(wm[M_T2], w6, tau);
+    tau = fma(wm[M_T0], w8, tau);
+    // amplitude with the C^2 cutoff taper (evaluated only where x > 0.9)
+    double amp = wm[M_AM1] * v;
+    amp = fma(wm[M_AM2], v2, amp) + wm[M_AM0];
+    amp *= b.fm76;
+    if (x > 0.9) {
+      const double u = (x - 0.9) * 10.0;
+      amp *= fma(-u * u * u, fma(u, fma(6.0, u, -15.0), 10.0), 1.0);
+    }
     const double aP = amp * wm[M_KP];
     const double aC = amp * wm[M_KC];
     // spacecraft geometry at t_f
     double sa, ca;
-    sincos_cycles(fma(tau, inv_year, wd[D_AO]), sa, ca);
+    sincos_cycles(tau * inv_year + wd[D_AO], sa, ca);
     double ua, ub;
     if (GEO) {
-      sincos_cycles(fma(tau, inv_ptq, wd[D_PO]), ub, ua);
+      sincos_cycles(tau * inv_ptq + wd[D_PO], ub, ua);
     } else {
       ua = fma(-2.0 * sa, sa, 1.0);
       ub = 2.0 * sa * ca;
     }
-#define PES_LIN(off) fma(wd[(off)], ua, fma(wd[(off) + 1], ub, fma(wd[(off) + 2], ca, fma(wd[(off) + 3], sa, wd[(off) + 4]))))
+#define PES_LIN(off) (fma(wd[(off) + 3], sa, fma(wd[(off) + 2], ca, fma(wd[(off) + 1], ub, wd[(off)] * ua))) + wd[(off) + 4])
     const double kn0 = PES_LIN(D_KN), kn1 = PES_LIN(D_KN + 5);
     const double np0 = PES_LIN(D_NP), np1 = PES_LIN(D_NP + 5);
     const double nq0 = PES_LIN(D_NQ), nq1 = PES_LIN(D_NQ + 5);
@@ -87,8 +100,13 @@ __device__ __forceinline__ Chan eval_channels(const double* __restrict__ wt,
     const double Er = cp, Ei = -sp;
     // per-arm phase e^{+i pi f k.Delta_t} of the spacecraft opposite arm t
     double s0, c0, s1, c1;
-    sincos_cycles(half_f * kd0, s0, c0);
-    sincos_cycles(half_f * kd1, s1, c1);
+    if (LONG_SINC) {
+      sincos_cycles(half_f * kd0, s0, c0);
+      sincos_cycles(half_f * kd1, s1, c1);
+    } else {  // |pi f k.Delta| <= pi f L / sqrt3 < 0.7 whenever the short sinc fit applies
+      sincos_small(pi_f * kd0, s0, c0);
+      sincos_small(pi_f * kd1, s1, c1);
+    }
     const double c2 = fma(c0, c1, -s0 * s1), s2 = -fma(s0, c1, c0 * s1);
 
 #define PES_ARM(er, ei, np, nq, kn, FR, FI, BR, BI)                    \
@@ -96,7 +114,7 @@ __device__ __forceinline__ Chan eval_channels(const double* __restrict__ wt,
     const double Qr = fma(Er, er, -Ei * ei), Qi = fma(Er, ei, Ei * er); \
     const double Pr = aP * fma(np, np, -nq * nq), Pi = aC * 2.0 * np * nq; \
     const double Gr = fma(Qr, Pr, -Qi * Pi), Gi = fma(Qr, Pi, Qi * Pr); \
-    const double sf = sinc(a * (1.0 - kn)), sb = sinc(a * (1.0 + kn));  \
+    const double sf = sinc<LONG_SINC>(a * (1.0 - kn)), sb = sinc<LONG_SINC>(a * (1.0 + kn)); \
     FR = fma(sf, Gr, FR);                                             \
     FI = fma(sf, Gi, FI);                                             \
     BR = fma(sb, Gr, BR);                                             \

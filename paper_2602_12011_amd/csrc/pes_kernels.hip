@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(1024) plan_kernel(const int* __restrict__ ntil
 // ticket.  Lanes own bins; the walkers of the group are processed in turn,
 // each lane evaluating its bins, then a wavefront reduction and one LDS slot
 // per (walker, wave).  partial[w][tile] = (<d|h>, <h|h>) of that tile.
-template <int BPL>
+template <int BPL, bool LS>
 __global__ void __launch_bounds__(256)
     loglike_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                    const double* __restrict__ wtab, const int* __restrict__ ntiles,
@@ -514,8 +514,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int q = 0; q < BPL; ++q) {
           const Chan c = (P.kind == 2)
-                             ? eval_channels<true>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
-                             : eval_channels<false>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
+                             ? eval_channels<true, LS>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
+                             : eval_channels<false, LS>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
           dh = fma(dar[q], c.ar, dh);
           dh = fma(dai[q], c.ai, dh);
           dh = fma(der[q], c.er, dh);
@@ -548,7 +548,8 @@ __global__ void __launch_bounds__(256)
         if (t < ntiles[w]) {
           const double dh = (acc[s][0][0] + acc[s][1][0]) + (acc[s][2][0] + acc[s][3][0]);
           const double hh = (acc[s][0][1] + acc[s][1][1]) + (acc[s][2][1] + acc[s][3][1]);
-          double* p = partial + ((int64_t)w * A.ntmax + t) * 2;
+          // tile-major: partial[t][w] (coalesced for the per-walker reduction)
+          double* p = partial + ((int64_t)t * A.B + w) * 2;
           p[0] = dh;
           p[1] = hh;
         }
@@ -558,10 +559,11 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// log L = <d|h> - <h|h>/2 - <d|d>/2, tiles summed in order.
+// log L = <d|h> - <h|h>/2 - <d|d>/2, tiles summed in order (partial is
+// tile-major, [tile][walker][2], so neighbouring threads read neighbouring data).
 __global__ void finalize_kernel(const double* __restrict__ partial, const int* __restrict__ ntiles,
                                 const double* __restrict__ wtab, const double* __restrict__ dd,
-                                int64_t B, int ntmax, double* __restrict__ logl) {
+                                int64_t B, double* __restrict__ logl) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   if (wtab[b * W_STRIDE + W_VALID] == 0.0) {
@@ -569,17 +571,18 @@ __global__ void finalize_kernel(const double* __restrict__ partial, const int* _
     return;
   }
   const int nt = ntiles[b];
-  const double* p = partial + b * (int64_t)ntmax * 2;
   double dh = 0.0, hh = 0.0;
   for (int t = 0; t < nt; ++t) {
-    dh += p[2 * t];
-    hh += p[2 * t + 1];
+    const double* p = partial + ((int64_t)t * B + b) * 2;
+    dh += p[0];
+    hh += p[1];
   }
   logl[b] = (dh - 0.5 * hh) - 0.5 * dd[0];
 }
 
 // ---------------------------------------------------------------- response
 // out[b][det][c][k] = n_c G(f_k) C''_c for one walker per blockIdx.y.
+template <bool LS>
 __global__ void response_kernel(ResponseArgs A) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t b = blockIdx.y;
@@ -599,9 +602,9 @@ __global__ void response_kernel(ResponseArgs A) {
     const double* __restrict__ wd = wt + W_DET0 + det * W_DET_STRIDE;
     Chan c = {0, 0, 0, 0, 0, 0};
     if (valid) {
-      c = (P.kind == 2) ? eval_channels<true>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+      c = (P.kind == 2) ? eval_channels<true, LS>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
                                               tb[T_ZR * N + k], tb[T_ZI * N + k])
-                        : eval_channels<false>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+                        : eval_channels<false, LS>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
                                                tb[T_ZR * N + k], tb[T_ZI * N + k]);
     }
     const double Gr = tb[T_GR * N + k], Gi = tb[T_GI * N + k];
@@ -647,34 +650,47 @@ hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, int* perm, i
   return hipGetLastError();
 }
 
-hipError_t launch_loglike(const LoglikeArgs& a, int bpl, int grid, hipStream_t s) {
+template <int BPL, bool LS>
+static void launch_ll(const LoglikeArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((loglike_kernel<BPL, LS>), dim3(grid), dim3(256), 0, s, a.bins, a.tabs, a.wtab,
+                     a.ntiles, a.perm, a.gstart, a.counters, a.partial, a);
+}
+
+hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, int grid, hipStream_t s) {
   if (bpl == 2)
-    hipLaunchKernelGGL(loglike_kernel<2>, dim3(grid), dim3(256), 0, s, a.bins, a.tabs, a.wtab, a.ntiles,
-                       a.perm, a.gstart, a.counters, a.partial, a);
+    long_sinc ? launch_ll<2, true>(a, grid, s) : launch_ll<2, false>(a, grid, s);
   else
-    hipLaunchKernelGGL(loglike_kernel<1>, dim3(grid), dim3(256), 0, s, a.bins, a.tabs, a.wtab, a.ntiles,
-                       a.perm, a.gstart, a.counters, a.partial, a);
+    long_sinc ? launch_ll<1, true>(a, grid, s) : launch_ll<1, false>(a, grid, s);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
-                           int64_t B, int ntmax, double* logl, hipStream_t s) {
+                           int64_t B, double* logl, hipStream_t s) {
   const int bs = 256;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((B + bs - 1) / bs)), dim3(bs), 0, s, partial, ntiles,
-                     wtab, dd, B, ntmax, logl);
+                     wtab, dd, B, logl);
   return hipGetLastError();
 }
 
-hipError_t launch_response(const ResponseArgs& a, int64_t B, hipStream_t s) {
+hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, hipStream_t s) {
   const int bs = 256;
-  hipLaunchKernelGGL(response_kernel, dim3((unsigned)((a.N + bs - 1) / bs), (unsigned)B), dim3(bs), 0, s, a);
+  const dim3 grid((unsigned)((a.N + bs - 1) / bs), (unsigned)B);
+  if (long_sinc)
+    hipLaunchKernelGGL(response_kernel<true>, grid, dim3(bs), 0, s, a);
+  else
+    hipLaunchKernelGGL(response_kernel<false>, grid, dim3(bs), 0, s, a);
   return hipGetLastError();
 }
 
-int loglike_blocks_per_cu(int bpl) {
+int loglike_blocks_per_cu(int bpl, bool long_sinc) {
   int nb = 0;
-  hipError_t e = (bpl == 2) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2>, 256, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1>, 256, 0);
+  hipError_t e;
+  if (bpl == 2)
+    e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2, true>, 256, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2, false>, 256, 0);
+  else
+    e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, true>, 256, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, false>, 256, 0);
   return e == hipSuccess ? nb : 1;
 }
 

@@ -54,10 +54,10 @@ hipError_t launch_setup(const double* theta, int64_t B, double* wtab, int* ntile
                         hipStream_t s);
 hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, int* perm, int* gstart, int* counters,
                        hipStream_t s);
-hipError_t launch_loglike(const LoglikeArgs& a, int bpl, int grid, hipStream_t s);
+hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, int grid, hipStream_t s);
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
-                           int64_t B, int ntmax, double* logl, hipStream_t s);
-hipError_t launch_response(const ResponseArgs& a, int64_t B, hipStream_t s);
-int loglike_blocks_per_cu(int bpl);
+                           int64_t B, double* logl, hipStream_t s);
+hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, hipStream_t s);
+int loglike_blocks_per_cu(int bpl, bool long_sinc);
 
 }  // namespace pes

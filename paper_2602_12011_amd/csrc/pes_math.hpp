@@ -37,17 +37,20 @@ __device__ __forceinline__ void sincos_cycles(double x, double& s, double& c) {
   c = ((qi + 1) & 2) ? -cc : cc;
 }
 
-// sin(b)/b.  Polynomial in b^2 on b^2 <= kSincTMax; beyond that (only for
-// grids above ~2.2 / (2 pi L)) the quotient of the cycle-reduced sine.
-__device__ __noinline__ double sinc_large(double b) {
-  double s, c;
-  sincos_cycles(b * (1.0 / kTwoPi), s, c);
-  return s / b;
-}
+// sin(b)/b as a polynomial in b^2.  LONG selects the fit valid to b = 4
+// (12 terms) instead of b^2 <= 4.9 (10 terms); the host picks the short one
+// whenever every detector's largest argument 2 pi f_max L allows it.
+template <bool LONG>
 __device__ __forceinline__ double sinc(double b) {
   const double t = b * b;
-  if (t <= kSincTMax) return horner(kSinc, t);
-  return sinc_large(b);
+  return LONG ? horner(kSincLong, t) : horner(kSincShort, t);
+}
+
+// sin(x), cos(x) for |x| <= 0.7 without argument reduction.
+__device__ __forceinline__ void sincos_small(double x, double& s, double& c) {
+  const double t = x * x;
+  s = x * horner(kSinSmall, t);
+  c = horner(kCosSmall, t);
 }
 
 // Exact split of a product: p + e == a * b exactly (e from one fused multiply-add).
