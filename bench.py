@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -118,6 +119,9 @@ def main():
     ctx.set_data(data)
     theta = torch.from_numpy(theta_np).to(dev)
     out = torch.empty(B, dtype=torch.float64, device=dev)
+    tuning = ctx.get_tuning()
+    if not args.no_autotune:
+        _, tuning = ctx.autotune(theta)      # untimed: picks the kernel tuning for this shape
     for _ in range(args.warmup):
         ctx.loglike(theta, out)
     torch.cuda.synchronize()
@@ -153,7 +157,7 @@ def main():
                                     "noise-free injection",
                            walkers=B, n_bins=cfg["n_bins"], modes=len(cfg["modes"]),
                            detectors=[d["kind"] for d in cfg["detectors"]],
-                           mode_units=n_mode, wbd_units=n_wbd),
+                           mode_units=n_mode, wbd_units=n_wbd, tuning=tuning),
                roofline=roofline)
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)

@@ -104,6 +104,20 @@ int pes_response(pes_ctx* ctx, const double* theta, int64_t B, double* out, void
  * theta (dev) [B][11], logl (dev) [B].  Requires pes_set_data. */
 int pes_loglike(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void* stream);
 
+/* Tuning of the persistent log-likelihood kernel: bins per lane (1 or 2),
+ * walkers per work item (1..64) and resident blocks per compute unit
+ * (0 = the occupancy limit, else at most that limit).  Defaults 1, 16, 0.
+ * Applies to later calls on the context. */
+int pes_set_tuning(pes_ctx* ctx, int bins_per_lane, int walkers_per_group, int blocks_per_cu);
+int pes_get_tuning(pes_ctx* ctx, int* bins_per_lane, int* walkers_per_group, int* blocks_per_cu);
+
+/* Autotuner: runs pes_loglike on the given batch (theta dev [B][11], logl
+ * dev [B] receives the results) for every tuning candidate, keeps the
+ * fastest and returns its time per call [ms] in *best_ms.  Synchronizes the
+ * stream; the results do not depend on the tuning. */
+int pes_autotune(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double* best_ms,
+                 void* stream);
+
 /* Kernel timing for measurement: with enable != 0 every later pes_loglike
  * records HIP events around its main (persistent log-likelihood) kernel on
  * the call's stream, up to 4096 launches.  pes_timing_read waits for the

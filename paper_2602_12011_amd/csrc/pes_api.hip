@@ -35,12 +35,14 @@ struct pes_ctx {
   double* dd = nullptr;
   bool has_data = false;
   // tuning
-  int bpl = 1;
+  int bpl = 1;              // bins per lane (1 or 2)
   bool long_sinc = false;   // a detector's largest sinc argument exceeds the short fit
-  int wg = 16;
-  int blocks_per_cu = 2;
+  int wg = 16;              // walkers per work item
+  int bpc = 0;              // resident blocks per CU requested (0: occupancy limit)
+  int occ[3] = {1, 1, 1};   // occupancy limit per bins-per-lane variant
   int tile = 256;
-  int ntmax = 0;
+  int ntmax = 0;            // tiles per walker at the current tile size
+  int ntmax_alloc = 0;      // tiles at the smallest tile (partial-buffer sizing)
   // workspace
   int64_t cap = 0;
   double* wtab = nullptr;
@@ -98,7 +100,7 @@ int ensure_workspace(pes_ctx* c, int64_t B) {
       hipMalloc(&c->perm, sizeof(int) * cap) != hipSuccess ||
       hipMalloc(&c->gstart, sizeof(int) * (ng + 1)) != hipSuccess ||
       hipMalloc(&c->counters, sizeof(int) * 4) != hipSuccess ||
-      hipMalloc(&c->partial, sizeof(double) * 2 * cap * (int64_t)c->ntmax) != hipSuccess) {
+      hipMalloc(&c->partial, sizeof(double) * 2 * cap * (int64_t)c->ntmax_alloc) != hipSuccess) {
     free_workspace(c);
     snprintf(c->err, sizeof(c->err), "workspace allocation for %lld walkers failed", (long long)cap);
     return PES_ENOMEM;
@@ -201,7 +203,9 @@ int pes_create(const pes_config* cfg, pes_ctx** out) {
   for (int i = 0; i < cfg->n_modes; ++i) c->modes[i] = ModeSpec{cfg->modes[i][0], cfg->modes[i][1]};
   c->tile = 256 * c->bpl;
   c->ntmax = (int)((c->N + c->tile - 1) / c->tile);
-  c->blocks_per_cu = std::max(1, loglike_blocks_per_cu(c->bpl, c->long_sinc));
+  c->ntmax_alloc = (int)((c->N + 255) / 256);
+  c->occ[1] = std::max(1, loglike_blocks_per_cu(1, c->long_sinc));
+  c->occ[2] = std::max(1, loglike_blocks_per_cu(2, c->long_sinc));
   const int64_t nb = (c->N + 255) / 256;
   if (hipMalloc(&c->bins, sizeof(double) * B_NFIELDS * c->N) != hipSuccess ||
       hipMalloc(&c->tabs, sizeof(double) * T_NFIELDS * c->N * cfg->n_det) != hipSuccess ||
@@ -270,6 +274,71 @@ int pes_timing_read(pes_ctx* c, double* total_ms, int64_t* launches) {
   *total_ms = sum;
   *launches = c->n_ev;
   c->n_ev = 0;
+  return PES_OK;
+}
+
+int pes_set_tuning(pes_ctx* c, int bins_per_lane, int walkers_per_group, int blocks_per_cu) {
+  if (!c || (bins_per_lane != 1 && bins_per_lane != 2) || walkers_per_group < 1 ||
+      walkers_per_group > kMaxGroup || blocks_per_cu < 0 || blocks_per_cu > 16)
+    return PES_EINVAL;
+  c->bpl = bins_per_lane;
+  c->wg = walkers_per_group;
+  c->bpc = blocks_per_cu;
+  c->tile = 256 * c->bpl;
+  c->ntmax = (int)((c->N + c->tile - 1) / c->tile);
+  return PES_OK;
+}
+
+int pes_get_tuning(pes_ctx* c, int* bins_per_lane, int* walkers_per_group, int* blocks_per_cu) {
+  if (!c || !bins_per_lane || !walkers_per_group || !blocks_per_cu) return PES_EINVAL;
+  *bins_per_lane = c->bpl;
+  *walkers_per_group = c->wg;
+  *blocks_per_cu = c->bpc > 0 ? std::min(c->bpc, c->occ[c->bpl]) : c->occ[c->bpl];
+  return PES_OK;
+}
+
+int pes_autotune(pes_ctx* c, const double* theta, int64_t B, double* logl, double* best_ms, void* stream) {
+  if (!c || !theta || !logl || !best_ms || B < 1) return PES_EINVAL;
+  if (!c->has_data) return PES_ESTATE;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  PES_HIP(c, hipEventCreate(&e0));
+  PES_HIP(c, hipEventCreate(&e1));
+  const int bpls[2] = {1, 2};
+  const int wgs[4] = {8, 16, 32, 64};
+  double best = 1e300;
+  int bb = c->bpl, bw = c->wg, bc = c->bpc;
+  int st = PES_OK;
+  for (int ib = 0; ib < 2 && st == PES_OK; ++ib)
+    for (int iw = 0; iw < 4 && st == PES_OK; ++iw)
+      for (int half = 0; half < 2 && st == PES_OK; ++half) {
+        const int occ = c->occ[bpls[ib]];
+        const int bpc = half ? std::max(1, occ / 2) : 0;
+        if (half && bpc == occ) continue;
+        pes_set_tuning(c, bpls[ib], wgs[iw], bpc);
+        st = pes_loglike(c, theta, B, logl, stream);   // warm-up
+        if (st != PES_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = PES_EHIP; break; }
+        for (int r = 0; r < 2 && st == PES_OK; ++r) st = pes_loglike(c, theta, B, logl, stream);
+        if (st != PES_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          st = PES_EHIP;
+          break;
+        }
+        if (ms * 0.5 < best) {
+          best = ms * 0.5;
+          bb = bpls[ib];
+          bw = wgs[iw];
+          bc = bpc;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  pes_set_tuning(c, bb, bw, bc);
+  if (st != PES_OK) return st;
+  *best_ms = best;
   return PES_OK;
 }
 
@@ -345,7 +414,8 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
   a.n_modes = c->cfg.n_modes;
   a.n_det = c->cfg.n_det;
   a.dt = c->dt;
-  const int grid = c->n_cu * c->blocks_per_cu;
+  const int bpc = c->bpc > 0 ? std::min(c->bpc, c->occ[c->bpl]) : c->occ[c->bpl];
+  const int grid = c->n_cu * bpc;
   const bool rec = c->timing && c->n_ev < kMaxEv;
   if (rec) PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev], s));
   PES_HIP(c, launch_loglike(a, c->bpl, c->long_sinc, grid, s));

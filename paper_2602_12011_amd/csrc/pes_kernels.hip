@@ -526,8 +526,8 @@ __global__ void __launch_bounds__(256)
           const double t2 = fma(c.tr, c.tr, c.ti * c.ti);
           hh = fma(wa[q], a2, fma(wtt[q], t2, hh));
         }
-        dh = wave_sum(dh);
-        hh = wave_sum(hh);
+        dh = wave_sum_dpp(dh);
+        hh = wave_sum_dpp(hh);
         if (lane == 0) {
           if (det == 0) {
             acc[s][wv][0] = dh;

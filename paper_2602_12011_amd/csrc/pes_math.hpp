@@ -66,4 +66,31 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// One DPP lane permutation of a double (two 32-bit moves).  Rows outside
+// ROW_MASK receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// 64-lane wavefront sum with data-parallel-primitive moves: pairs, quads
+// (quad_perm), 8 lanes (row_half_mirror), rows of 16 (row_mirror), then the
+// row broadcasts of lanes 15 and 31; lane 63 holds the total, returned to the
+// whole wave.  Fixed order, so results are bitwise repeatable.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141, 0xf>(v);   // row_half_mirror
+  v += dpp_f64<0x140, 0xf>(v);   // row_mirror
+  v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 }  // namespace pes

@@ -50,6 +50,10 @@ def lib():
         L.pes_set_data.argtypes = [vp, vp, vp]
         L.pes_response.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.pes_loglike.argtypes = [vp, vp, C.c_int64, vp, vp]
+        ip = C.POINTER(C.c_int)
+        L.pes_set_tuning.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        L.pes_get_tuning.argtypes = [vp, ip, ip, ip]
+        L.pes_autotune.argtypes = [vp, vp, C.c_int64, vp, C.POINTER(C.c_double), vp]
         L.pes_timing.argtypes = [vp, C.c_int]
         L.pes_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.pes_strerror.argtypes = [C.c_int]
@@ -57,7 +61,8 @@ def lib():
         L.pes_last_error.argtypes = [vp]
         L.pes_last_error.restype = C.c_char_p
         for name in ("pes_create", "pes_destroy", "pes_reserve", "pes_set_data",
-                     "pes_response", "pes_loglike", "pes_timing", "pes_timing_read"):
+                     "pes_response", "pes_loglike", "pes_timing", "pes_timing_read",
+                     "pes_set_tuning", "pes_get_tuning", "pes_autotune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -135,6 +140,27 @@ class Context:
         n = C.c_int64()
         self._check(lib().pes_timing_read(self.h, C.byref(ms), C.byref(n)), "pes_timing_read")
         return ms.value, n.value
+
+    def set_tuning(self, bins_per_lane, walkers_per_group, blocks_per_cu=0):
+        self._check(lib().pes_set_tuning(self.h, int(bins_per_lane), int(walkers_per_group),
+                                         int(blocks_per_cu)), "pes_set_tuning")
+
+    def get_tuning(self):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        self._check(lib().pes_get_tuning(self.h, C.byref(a), C.byref(b), C.byref(c)),
+                    "pes_get_tuning")
+        return dict(bins_per_lane=a.value, walkers_per_group=b.value, blocks_per_cu=c.value)
+
+    def autotune(self, theta, stream=None):
+        """Time every tuning candidate on this batch, keep the fastest; returns
+        (ms per call, tuning dict)."""
+        theta = theta.contiguous()
+        out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
+        ms = C.c_double()
+        self._check(lib().pes_autotune(self.h, _dev_f64(theta, "theta"), theta.shape[0],
+                                       _dev_f64(out, "logl"), C.byref(ms), _stream(stream)),
+                    "pes_autotune")
+        return ms.value, self.get_tuning()
 
     def reserve(self, max_walkers):
         self._check(lib().pes_reserve(self.h, int(max_walkers)), "pes_reserve")

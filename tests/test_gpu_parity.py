@@ -196,3 +196,30 @@ def test_full_size_sampled(orc, torch_dev, pes, name):
     idx = np.unique(np.concatenate([[np.argmin(th[:, 0]), np.argmax(th[:, 0])],
                                     rng.choice(B, n_check, replace=False)]))
     _check_loglike(orc, cfg, d, L[idx], th[idx], f"{name} sampled")
+
+
+@pytest.mark.parametrize("bpl", [1, 2])
+def test_every_tuning_matches_oracle(orc, torch_dev, pes, bpl):
+    """Results do not depend on the kernel tuning: every (bins per lane,
+    walkers per item, blocks per CU) matches the oracle, and for a fixed tile
+    size the walker grouping does not change a single bit."""
+    torch = torch_dev
+    cfg = _cfg("cfg2", n_bins=7000 + 3)
+    d = orc.response(cfg, W.THETA0)
+    th = W.draw_walkers(100, stream=60)
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(d).to("cuda"))
+    tht = torch.from_numpy(th).to("cuda")
+    ref = None
+    for wg, bpc in ((1, 0), (7, 1), (16, 0), (64, 2)):
+        ctx.set_tuning(bpl, wg, bpc)
+        L = ctx.loglike(tht).cpu().numpy()
+        _check_loglike(orc, cfg, d, L, th, f"bpl={bpl} wg={wg} bpc={bpc}")
+        if ref is None:
+            ref = L
+        assert np.array_equal(L, ref)
+    ms, tun = ctx.autotune(tht)
+    assert ms > 0 and tun["bins_per_lane"] in (1, 2)
+    L = ctx.loglike(tht).cpu().numpy()
+    _check_loglike(orc, cfg, d, L, th, f"autotuned {tun}")
+    ctx.close()
