@@ -67,6 +67,39 @@ def algorithmic_flops(cfg, theta):
     return total, n_mode * nd, n_wb * nd
 
 
+KERNEL_SOURCES = ("pes_eval.hpp", "pes_kernels.hip", "pes_math.hpp", "pes_poly.hpp",
+                  "pes_layout.hpp", "pes_launch.hpp")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "loglike_kernel_cfg1_counters.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2602_12011_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tuning):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources with the same tuning; else None."""
+    try:
+        text = open(COUNTER_SUMMARY).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.split(":")[0].strip() in (
+                "traffic_bytes_per_launch", "kernel_sources_sha256_16", "tuning"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    tun = f"{tuning['bins_per_lane']},{tuning['walkers_per_group']},{tuning['blocks_per_cu']}"
+    if vals.get("kernel_sources_sha256_16") != kernel_source_hash() or vals.get("tuning") != tun:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(cfg, theta, n_sample, threads):
     import oracle
     d = oracle.response(cfg, W.THETA0)
@@ -88,6 +121,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="bins_per_lane,walkers_per_group,blocks_per_cu (skips the autotuner)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -120,7 +155,10 @@ def main():
     theta = torch.from_numpy(theta_np).to(dev)
     out = torch.empty(B, dtype=torch.float64, device=dev)
     tuning = ctx.get_tuning()
-    if not args.no_autotune:
+    if args.tuning:
+        ctx.set_tuning(*[int(x) for x in args.tuning.split(",")])
+        tuning = ctx.get_tuning()
+    elif not args.no_autotune:
         _, tuning = ctx.autotune(theta)      # untimed: picks the kernel tuning for this shape
     for _ in range(args.warmup):
         ctx.loglike(theta, out)
@@ -145,7 +183,8 @@ def main():
     kern_s = kern_ms / launches * 1e-3
     achieved = flops / kern_s / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_VECTOR_TFLOPS,
-                    unit="TFLOP/s", frac=round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4), traffic=None,
+                    unit="TFLOP/s", frac=round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4),
+                    traffic=measured_traffic(tuning),
                     kernel="loglike_kernel", kernel_ms=round(kern_ms / launches, 4),
                     flops_per_launch=flops)
 
