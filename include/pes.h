@@ -104,6 +104,87 @@ int pes_response(pes_ctx* ctx, const double* theta, int64_t B, double* out, void
  * theta (dev) [B][11], logl (dev) [B].  Requires pes_set_data. */
 int pes_loglike(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void* stream);
 
+/* Gradient of log L with respect to theta (forward-mode tangents of the
+ * response, one parameter direction per pass; Sec. 2.3 uses reverse mode for
+ * gradients, the values agree to rounding): logl (dev) [B] (may be NULL),
+ * grad (dev) [B][11] in the units of theta.  Requires pes_set_data.
+ * Unphysical samples: logl = -inf, grad = 0.  B <= 65535. */
+int pes_grad(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double* grad, void* stream);
+
+/* Fisher matrix F_ij = <d_i h | d_j h> (Sec. 2.2, eqs. eq_ll_fisher and
+ * eq_inner_product) from the forward-mode Jacobian of the A/E/T response, the
+ * J^T W J contraction on FP64 matrix cores: F (dev) [B][11][11], symmetric,
+ * in the units of theta.  Independent of the data.  Unphysical samples: NaN.
+ * B <= 65535. */
+int pes_fisher(pes_ctx* ctx, const double* theta, int64_t B, double* F, void* stream);
+
+/* ---- Sampler.  Bayes' theorem splits the posterior into prior and
+ * likelihood (Sec. 2.2); the sampler combines a box prior with pes_loglike. */
+enum {
+  PES_PRIOR_UNIFORM = 0,     /* flat on [lo, hi] */
+  PES_PRIOR_LOGUNIFORM = 1,  /* proportional to 1/x on [lo, hi], lo > 0 */
+  PES_PRIOR_SIN = 2,         /* proportional to sin x on (lo, hi) within [0, pi] */
+  PES_PRIOR_COS = 3,         /* proportional to cos x on (lo, hi) within [-pi/2, pi/2] */
+  PES_PRIOR_PERIODIC = 4,    /* flat, proposals wrapped into [lo, hi) */
+  PES_PRIOR_FIXED = 5        /* held at its initial value */
+};
+typedef struct {
+  int kind[11];
+  double lo[11];
+  double hi[11];
+} pes_prior;
+
+typedef struct pes_sampler pes_sampler;
+
+/* Ensemble of n_walkers (>= 4) chains on the context's likelihood.  Every step
+ * updates the two halves of the ensemble in turn with differential-evolution
+ * proposals drawn against the other half (ter Braak's DE-MC: gamma =
+ * 2.38/sqrt(2 d), gamma = 1 with probability 0.1, jitter 1e-6 of the prior
+ * width) and Metropolis-Hastings acceptance with the exact FP64 log L.  All
+ * random numbers are Philox4x32-10 blocks keyed by seed with counter (walker,
+ * step, purpose), so runs are reproducible and graph replays advance by the
+ * step counter kept in device memory.  chain_len > 0 keeps a ring of the last
+ * chain_len states ([chain_len][n_walkers][11], device).  Reserves the
+ * context's workspace for half the ensemble.  Requires pes_set_data. */
+int pes_sampler_create(pes_ctx* ctx, const pes_prior* prior, int64_t n_walkers, uint64_t seed,
+                       int64_t chain_len, pes_sampler** out);
+int pes_sampler_destroy(pes_sampler* s);
+
+/* Set the walkers (theta dev [n_walkers][11]), evaluate their log L and log
+ * prior, zero the acceptance counts and the step counter.  Synchronizes. */
+int pes_sampler_set_state(pes_sampler* s, const double* theta, void* stream);
+
+/* Advance n_steps steps (asynchronous). */
+int pes_sampler_step(pes_sampler* s, int64_t n_steps, void* stream);
+
+/* Capture one step in a HIP graph (kernels only, no allocation or memset) and
+ * replay it n_steps times; the replay is bitwise identical to
+ * pes_sampler_step.  The graph stays valid until pes_sampler_destroy. */
+int pes_sampler_capture(pes_sampler* s, void* stream);
+int pes_sampler_launch(pes_sampler* s, int64_t n_steps, void* stream);
+
+/* Copy the state into caller buffers (dev; any may be NULL): theta
+ * [n_walkers][11], logl [n_walkers], accepts [n_walkers] (int64); *steps
+ * (host) receives the completed step count.  Synchronizes the stream. */
+int pes_sampler_state(pes_sampler* s, double* theta, double* logl, int64_t* accepts, uint64_t* steps,
+                      void* stream);
+
+/* Device pointer of the chain ring (NULL without one). */
+int pes_sampler_chain(pes_sampler* s, const double** chain);
+
+/* One proposal for half `half` (0 or 1) of the ensemble from the current
+ * state: theta_prop (dev) [half size][11], log_qratio (dev) [half size]
+ * (log q(theta|theta') - log q(theta'|theta); 0 for the symmetric DE move).
+ * kind: PES_PROPOSE_DE. */
+enum { PES_PROPOSE_DE = 0 };
+int pes_propose(pes_sampler* s, int kind, int half, double* theta_prop, double* log_qratio, void* stream);
+
+/* Philox4x32-10 (Salmon et al., SC'11) blocks for the counters
+ * (c0 + i, c1, c2, c3), i = 0..n-1 (first word wraps modulo 2^32), with the
+ * 64-bit key split into two words (low first): out (dev) [n][4] uint32. */
+int pes_philox(uint64_t key, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t* out,
+               void* stream);
+
 /* Tuning of the persistent log-likelihood kernel: bins per lane (1 or 2),
  * walkers per work item (1..64) and resident blocks per compute unit
  * (0 = the occupancy limit, else at most that limit).  Defaults 1, 16, 0.

@@ -10,6 +10,7 @@
 
 #include "../../include/pes.h"
 #include "pes_launch.hpp"
+#include "pes_sampler.hpp"
 
 using namespace pes;
 
@@ -51,6 +52,11 @@ struct pes_ctx {
   int* gstart = nullptr;
   int* counters = nullptr;
   double* partial = nullptr;
+  // derivative workspace
+  int64_t jcap = 0;
+  double* wtan = nullptr;      // [jcap][W_STRIDE][11]
+  double* jpart = nullptr;     // per-tile partial sums of the derivative kernels
+  int64_t jpart_n = 0;
   // measurement
   bool timing = false;
   int n_ev = 0;
@@ -106,6 +112,36 @@ int ensure_workspace(pes_ctx* c, int64_t B) {
     return PES_ENOMEM;
   }
   c->cap = cap;
+  return PES_OK;
+}
+
+constexpr int kGradTile = 1024;
+constexpr int kFisherTile = 4096;
+
+void free_jac(pes_ctx* c) {
+  (void)hipFree(c->wtan);
+  (void)hipFree(c->jpart);
+  c->wtan = c->jpart = nullptr;
+  c->jcap = 0;
+  c->jpart_n = 0;
+}
+
+int ensure_jac(pes_ctx* c, int64_t B) {
+  int st = ensure_workspace(c, B);
+  if (st != PES_OK) return st;
+  const int64_t ng = (c->N + kGradTile - 1) / kGradTile, nf = (c->N + kFisherTile - 1) / kFisherTile;
+  const int64_t cap = std::max<int64_t>(B, 16);
+  const int64_t need = std::max(ng * cap * (kNParams + 2), nf * cap * 256);
+  if (B <= c->jcap && need <= c->jpart_n) return PES_OK;
+  free_jac(c);
+  if (hipMalloc(&c->wtan, sizeof(double) * cap * W_STRIDE * kNParams) != hipSuccess ||
+      hipMalloc(&c->jpart, sizeof(double) * need) != hipSuccess) {
+    free_jac(c);
+    snprintf(c->err, sizeof(c->err), "derivative workspace for %lld walkers failed", (long long)cap);
+    return PES_ENOMEM;
+  }
+  c->jcap = cap;
+  c->jpart_n = need;
   return PES_OK;
 }
 
@@ -229,6 +265,7 @@ int pes_destroy(pes_ctx* c) {
   (void)hipDeviceSynchronize();
   pes_timing(c, 0);
   free_workspace(c);
+  free_jac(c);
   (void)hipFree(c->bins);
   (void)hipFree(c->tabs);
   (void)hipFree(c->dd_part);
@@ -424,6 +461,267 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
     ++c->n_ev;
   }
   PES_HIP(c, launch_finalize(c->partial, c->ntiles, c->wtab, c->dd, B, logl, s));
+  return PES_OK;
+}
+
+static JacArgs jac_args(const pes_ctx* c, int64_t B, int tile) {
+  JacArgs A;
+  A.N = c->N;
+  A.B = (int)B;
+  A.n_modes = c->cfg.n_modes;
+  A.n_det = c->cfg.n_det;
+  A.tile = tile;
+  A.f0 = c->cfg.f0;
+  A.df = c->cfg.df;
+  A.dt = c->dt;
+  return A;
+}
+
+int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* grad, void* stream) {
+  if (!c || B < 0 || B > 65535 || (B > 0 && (!theta || !grad))) return PES_EINVAL;
+  if (!c->has_data) return PES_ESTATE;
+  if (B == 0) return PES_OK;
+  int st = ensure_jac(c, B);
+  if (st != PES_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  PES_HIP(c, launch_setup_tan(theta, B, c->wtab, c->wtan, c->ntiles, setup_args(c), s));
+  PES_HIP(c, launch_grad(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, c->dd, jac_args(c, B, kGradTile),
+                         c->long_sinc, logl, grad, s));
+  return PES_OK;
+}
+
+int pes_fisher(pes_ctx* c, const double* theta, int64_t B, double* F, void* stream) {
+  if (!c || B < 0 || B > 65535 || (B > 0 && (!theta || !F))) return PES_EINVAL;
+  if (B == 0) return PES_OK;
+  int st = ensure_jac(c, B);
+  if (st != PES_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  PES_HIP(c, launch_setup_tan(theta, B, c->wtab, c->wtan, c->ntiles, setup_args(c), s));
+  PES_HIP(c, launch_fisher(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, jac_args(c, B, kFisherTile),
+                           c->long_sinc, F, s));
+  return PES_OK;
+}
+
+}  // extern "C"
+
+struct pes_sampler {
+  pes_ctx* ctx = nullptr;
+  int64_t B = 0, H0 = 0, H1 = 0;   // walkers, half sizes
+  uint64_t seed = 0;
+  int64_t chain_len = 0;
+  PriorArgs prior;
+  double width[kNParams];
+  double gamma = 0.0;
+  double *theta = nullptr, *logl = nullptr, *logp = nullptr;
+  double *prop = nullptr, *prop_logl = nullptr, *qratio = nullptr, *chain = nullptr;
+  int64_t* accepts = nullptr;
+  uint64_t* step = nullptr;   // [2]: current step, next step
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+DeArgs de_args(const pes_sampler* s, int half) {
+  DeArgs a;
+  memset(&a, 0, sizeof(a));
+  a.upd0 = half ? s->H0 : 0;
+  a.n_upd = half ? s->H1 : s->H0;
+  a.ref0 = half ? 0 : s->H0;
+  a.n_ref = half ? s->H0 : s->H1;
+  a.half = half;
+  a.gamma = s->gamma;
+  a.seed = s->seed;
+  for (int k = 0; k < kNParams; ++k) a.width[k] = s->width[k];
+  a.prior = s->prior;
+  return a;
+}
+
+int sampler_one_step(pes_sampler* s, hipStream_t st) {
+  for (int half = 0; half < 2; ++half) {
+    const DeArgs a = de_args(s, half);
+    PES_HIP(s->ctx, launch_de_propose(s->theta, s->prop, s->qratio, s->step, a, st));
+    const int rc = pes_loglike(s->ctx, s->prop, a.n_upd, s->prop_logl, st);
+    if (rc != PES_OK) return rc;
+    PES_HIP(s->ctx, launch_accept(s->theta, s->logl, s->logp, s->prop, s->prop_logl, s->qratio, s->accepts,
+                                  s->step, a, st));
+  }
+  PES_HIP(s->ctx, launch_end_step(s->theta, s->step, s->chain, s->chain_len, s->B, st));
+  return PES_OK;
+}
+
+void sampler_free(pes_sampler* s) {
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  (void)hipFree(s->theta);
+  (void)hipFree(s->logl);
+  (void)hipFree(s->logp);
+  (void)hipFree(s->prop);
+  (void)hipFree(s->prop_logl);
+  (void)hipFree(s->qratio);
+  (void)hipFree(s->chain);
+  (void)hipFree(s->accepts);
+  (void)hipFree(s->step);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pes_philox(uint64_t key, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t* out,
+               void* stream) {
+  if (n < 0 || (n > 0 && !out)) return PES_EINVAL;
+  if (n == 0) return PES_OK;
+  return launch_philox(key, c0, c1, c2, c3, n, out, (hipStream_t)stream) == hipSuccess ? PES_OK : PES_EHIP;
+}
+
+int pes_sampler_create(pes_ctx* ctx, const pes_prior* prior, int64_t n_walkers, uint64_t seed,
+                       int64_t chain_len, pes_sampler** out) {
+  if (!ctx || !prior || !out || n_walkers < 4 || n_walkers > (int64_t(1) << 24) || chain_len < 0) return PES_EINVAL;
+  *out = nullptr;
+  int n_free = 0;
+  for (int k = 0; k < kNParams; ++k) {
+    const int kind = prior->kind[k];
+    if (kind < PES_PRIOR_UNIFORM || kind > PES_PRIOR_FIXED) return PES_EINVAL;
+    if (kind != PES_PRIOR_FIXED && !(prior->hi[k] > prior->lo[k])) return PES_EINVAL;
+    if (kind == PES_PRIOR_LOGUNIFORM && !(prior->lo[k] > 0)) return PES_EINVAL;
+    if (kind != PES_PRIOR_FIXED) ++n_free;
+  }
+  if (n_free == 0) return PES_EINVAL;
+  if (!ctx->has_data) return PES_ESTATE;
+  pes_sampler* s = new (std::nothrow) pes_sampler();
+  if (!s) return PES_ENOMEM;
+  s->ctx = ctx;
+  s->B = n_walkers;
+  s->H0 = n_walkers / 2;
+  s->H1 = n_walkers - s->H0;
+  s->seed = seed;
+  s->chain_len = chain_len;
+  for (int k = 0; k < kNParams; ++k) {
+    s->prior.kind[k] = prior->kind[k];
+    s->prior.lo[k] = prior->lo[k];
+    s->prior.hi[k] = prior->hi[k];
+    s->width[k] = prior->kind[k] == PES_PRIOR_FIXED ? 0.0 : prior->hi[k] - prior->lo[k];
+  }
+  s->gamma = 2.38 / sqrt(2.0 * n_free);
+  const int64_t B = n_walkers, H = s->H1;
+  if (hipMalloc(&s->theta, sizeof(double) * B * 11) != hipSuccess ||
+      hipMalloc(&s->logl, sizeof(double) * B) != hipSuccess ||
+      hipMalloc(&s->logp, sizeof(double) * B) != hipSuccess ||
+      hipMalloc(&s->prop, sizeof(double) * H * 11) != hipSuccess ||
+      hipMalloc(&s->prop_logl, sizeof(double) * H) != hipSuccess ||
+      hipMalloc(&s->qratio, sizeof(double) * H) != hipSuccess ||
+      hipMalloc(&s->accepts, sizeof(int64_t) * B) != hipSuccess ||
+      hipMalloc(&s->step, sizeof(uint64_t) * 2) != hipSuccess ||
+      (chain_len > 0 && hipMalloc(&s->chain, sizeof(double) * chain_len * B * 11) != hipSuccess)) {
+    sampler_free(s);
+    delete s;
+    return PES_ENOMEM;
+  }
+  const int rc = pes_reserve(ctx, std::max(B, H));
+  if (rc != PES_OK) {
+    sampler_free(s);
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return PES_OK;
+}
+
+int pes_sampler_destroy(pes_sampler* s) {
+  if (!s) return PES_EINVAL;
+  (void)hipDeviceSynchronize();
+  sampler_free(s);
+  delete s;
+  return PES_OK;
+}
+
+int pes_sampler_set_state(pes_sampler* s, const double* theta, void* stream) {
+  if (!s || !theta) return PES_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  PES_HIP(s->ctx, hipMemcpyAsync(s->theta, theta, sizeof(double) * s->B * 11, hipMemcpyDeviceToDevice, st));
+  const int rc = pes_loglike(s->ctx, s->theta, s->B, s->logl, st);
+  if (rc != PES_OK) return rc;
+  PES_HIP(s->ctx, launch_init_state(s->theta, s->logp, s->B, s->prior, st));
+  PES_HIP(s->ctx, hipStreamSynchronize(st));
+  const uint64_t zero2[2] = {0, 0};
+  PES_HIP(s->ctx, hipMemcpy(s->step, zero2, sizeof(zero2), hipMemcpyHostToDevice));
+  int64_t* z = new (std::nothrow) int64_t[s->B]();
+  if (!z) return PES_ENOMEM;
+  const hipError_t e = hipMemcpy(s->accepts, z, sizeof(int64_t) * s->B, hipMemcpyHostToDevice);
+  delete[] z;
+  PES_HIP(s->ctx, e);
+  return PES_OK;
+}
+
+int pes_sampler_step(pes_sampler* s, int64_t n_steps, void* stream) {
+  if (!s || n_steps < 0) return PES_EINVAL;
+  for (int64_t n = 0; n < n_steps; ++n) {
+    const int rc = sampler_one_step(s, (hipStream_t)stream);
+    if (rc != PES_OK) return rc;
+  }
+  return PES_OK;
+}
+
+int pes_sampler_capture(pes_sampler* s, void* stream) {
+  if (!s) return PES_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (!st) return PES_EINVAL;   // capture needs a non-default stream
+  if (s->exec) {
+    (void)hipGraphExecDestroy(s->exec);
+    s->exec = nullptr;
+  }
+  if (s->graph) {
+    (void)hipGraphDestroy(s->graph);
+    s->graph = nullptr;
+  }
+  const bool timing = s->ctx->timing;
+  s->ctx->timing = false;
+  PES_HIP(s->ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  const int rc = sampler_one_step(s, st);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  s->ctx->timing = timing;
+  if (rc != PES_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  PES_HIP(s->ctx, e);
+  s->graph = g;
+  PES_HIP(s->ctx, hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+  return PES_OK;
+}
+
+int pes_sampler_launch(pes_sampler* s, int64_t n_steps, void* stream) {
+  if (!s || n_steps < 0) return PES_EINVAL;
+  if (!s->exec) return PES_ESTATE;
+  for (int64_t n = 0; n < n_steps; ++n) PES_HIP(s->ctx, hipGraphLaunch(s->exec, (hipStream_t)stream));
+  return PES_OK;
+}
+
+int pes_sampler_state(pes_sampler* s, double* theta, double* logl, int64_t* accepts, uint64_t* steps,
+                      void* stream) {
+  if (!s) return PES_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (theta) PES_HIP(s->ctx, hipMemcpyAsync(theta, s->theta, sizeof(double) * s->B * 11, hipMemcpyDeviceToDevice, st));
+  if (logl) PES_HIP(s->ctx, hipMemcpyAsync(logl, s->logl, sizeof(double) * s->B, hipMemcpyDeviceToDevice, st));
+  if (accepts)
+    PES_HIP(s->ctx, hipMemcpyAsync(accepts, s->accepts, sizeof(int64_t) * s->B, hipMemcpyDeviceToDevice, st));
+  PES_HIP(s->ctx, hipStreamSynchronize(st));
+  if (steps) PES_HIP(s->ctx, hipMemcpy(steps, s->step, sizeof(uint64_t), hipMemcpyDeviceToHost));
+  return PES_OK;
+}
+
+int pes_sampler_chain(pes_sampler* s, const double** chain) {
+  if (!s || !chain) return PES_EINVAL;
+  *chain = s->chain;
+  return PES_OK;
+}
+
+int pes_propose(pes_sampler* s, int kind, int half, double* theta_prop, double* log_qratio, void* stream) {
+  if (!s || !theta_prop || !log_qratio || (half != 0 && half != 1) || kind != PES_PROPOSE_DE) return PES_EINVAL;
+  PES_HIP(s->ctx, launch_de_propose(s->theta, theta_prop, log_qratio, s->step, de_args(s, half),
+                                    (hipStream_t)stream));
   return PES_OK;
 }
 

@@ -149,28 +149,186 @@ __global__ void sum_kernel(const double* __restrict__ part, int n, double* __res
 
 // ---------------------------------------------------------------- walker setup
 // theta -> per-walker constant table (TaylorF2 stand-in, leading-order mode
-// amplitudes, -2Y_lm closed forms, sky basis, orbit projection coefficients)
-// and the number of active bin tiles.
-__device__ void ylm_pair(int l, int m, double iota, double& yp, double& ym) {
+// amplitudes, -2Y_lm closed forms, sky basis, orbit projection coefficients).
+// Written once over a scalar type T: double for the values, Dual<11> for their
+// derivatives with respect to theta.
+template <class T>
+__device__ void ylm_pair(int l, int m, const T& iota, T& yp, T& ym) {
   // -2Y_{l,+m}(iota, 0) and -2Y_{l,-m}(iota, 0)
-  const double C = cos(0.5 * iota), S = sin(0.5 * iota), c = cos(iota);
-  const double C2 = C * C, S2 = S * S, C4 = C2 * C2, S4 = S2 * S2;
+  const T C = cos(0.5 * iota), S = sin(0.5 * iota), c = cos(iota);
+  const T C2 = C * C, S2 = S * S, C4 = C2 * C2, S4 = S2 * S2;
   if (l == 2 && m == 2) {
-    yp = sqrt(5.0 / (64.0 * kPi)) * (1.0 + c) * (1.0 + c);
-    ym = sqrt(5.0 / (64.0 * kPi)) * (1.0 - c) * (1.0 - c);
+    yp = sqrt(5.0 / (64.0 * kPi)) * ((1.0 + c) * (1.0 + c));
+    ym = sqrt(5.0 / (64.0 * kPi)) * ((1.0 - c) * (1.0 - c));
   } else if (l == 2 && m == 1) {
-    yp = sqrt(5.0 / (16.0 * kPi)) * sin(iota) * (1.0 + c);
-    ym = sqrt(5.0 / (16.0 * kPi)) * sin(iota) * (1.0 - c);
+    yp = sqrt(5.0 / (16.0 * kPi)) * (sin(iota) * (1.0 + c));
+    ym = sqrt(5.0 / (16.0 * kPi)) * (sin(iota) * (1.0 - c));
   } else if (l == 3 && m == 3) {
-    yp = -sqrt(21.0 / (2.0 * kPi)) * C4 * C * S;
-    ym = sqrt(21.0 / (2.0 * kPi)) * C * S4 * S;
+    yp = -sqrt(21.0 / (2.0 * kPi)) * (C4 * C * S);
+    ym = sqrt(21.0 / (2.0 * kPi)) * (C * S4 * S);
   } else if (l == 3 && m == 2) {
-    yp = sqrt(7.0 / (4.0 * kPi)) * C4 * (3.0 * c - 2.0);
-    ym = sqrt(7.0 / (4.0 * kPi)) * S4 * (3.0 * c + 2.0);
+    yp = sqrt(7.0 / (4.0 * kPi)) * (C4 * (3.0 * c - 2.0));
+    ym = sqrt(7.0 / (4.0 * kPi)) * (S4 * (3.0 * c + 2.0));
   } else {  // (4, 4)
-    yp = 3.0 * sqrt(7.0 / kPi) * C4 * C2 * S2;
-    ym = 3.0 * sqrt(7.0 / kPi) * C2 * S4 * S2;
+    yp = 3.0 * sqrt(7.0 / kPi) * (C4 * C2 * S2);
+    ym = 3.0 * sqrt(7.0 / kPi) * (C2 * S4 * S2);
   }
+}
+
+__device__ bool theta_valid(const double* th) {
+  bool ok = true;
+  for (int i = 0; i < 11; ++i) ok = ok && isfinite(th[i]);
+  return ok && th[0] > 0.0 && th[1] > 0.0 && th[1] <= 1.0 && fabs(th[2]) < 1.0 &&
+         fabs(th[3]) < 1.0 && th[4] > 0.0;
+}
+
+// Output of the setup: plain values, or value and one tangent per entry.
+struct ValOut {
+  double* w;
+  __device__ void operator()(int i, double x) const { w[i] = x; }
+};
+struct TanOut {
+  double* w;    // values, written by the k == 0 thread
+  double* t;    // tangents [W_STRIDE][kNParams]
+  int k;
+  __device__ void operator()(int i, const Dual<1>& x) const {
+    if (k == 0) w[i] = x.v;
+    t[i * kNParams + k] = x.d[0];
+  }
+};
+
+// Writes the W_STRIDE entries of a physical theta's table through `put`;
+// returns the highest mode cutoff [Hz].
+template <class T, class Out>
+__device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put) {
+  for (int i = 0; i < W_STRIDE; ++i) put(i, T(0.0));
+  const T M = th[0] * kMsunS;
+  const T q = th[1];
+  const T eta = q / ((1.0 + q) * (1.0 + q));
+  const T delta = (1.0 - q) / (1.0 + q);
+  const T chi1 = th[2], chi2 = th[3];
+  const T chis = 0.5 * (chi1 + chi2), chia = 0.5 * (chi1 - chi2);
+  const T DL = th[4] * kGpcS;
+  const T iota = th[5], phic = th[6], lam = th[7], beta = th[8], psi = th[9], tc = th[10];
+  // TaylorF2 coefficients psi_k (+ ln v parts) -- 3.5PN, aligned spins
+  const double p0 = 1.0;
+  const T p2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
+  const T p3 = -16.0 * kPi + (113.0 / 3.0 - 76.0 / 3.0 * eta) * chis + 113.0 / 3.0 * (delta * chia);
+  const T p4 = 15293365.0 / 508032.0 + 27145.0 / 504.0 * eta + 3085.0 / 72.0 * (eta * eta) -
+               10.0 * (79.0 / 8.0) * (eta * chi1 * chi2);
+  const T p5 = kPi * (38645.0 / 756.0 - 65.0 / 9.0 * eta);
+  const T p5l = 3.0 * p5;
+  const T p6 = (11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * kPi * kPi -
+                6848.0 / 21.0 * kEulerGamma - 6848.0 / 21.0 * log(4.0)) +
+               (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * kPi * kPi) * eta +
+               76055.0 / 1728.0 * (eta * eta) - 127825.0 / 1296.0 * (eta * eta * eta);
+  const double p6l = -6848.0 / 21.0;
+  const T p7 = kPi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * (eta * eta));
+  put(W_VALID, T(1.0));
+  put(W_TC, tc);
+  double fmx = 0.0;
+  for (int j = 0; j < sa.n_modes; ++j) {
+    const int l = sa.modes[j].l, m = sa.modes[j].m;
+    const int M0 = W_MODE0 + j * W_MODE_STRIDE;
+    const double mm = (double)m;
+    const T cm = cbrt(M * (kTwoPi / mm));
+    put(M0 + M_CM, cm);
+    put(M0 + M_CMI, 1.0 / cm);
+    put(M0 + M_LNCM, log(cm));
+    // phase in cycles: (m/2) * 3/(128 eta) * sum_k psi_k v^{k-5} / (2 pi)
+    const T pref = (0.5 * mm * 3.0 / 128.0 / kTwoPi) / eta;
+    // constant phase: -(m/2) phi_c - pi/4 - arg(unit_lm), in cycles
+    double argu = 0.0;
+    if (l == 2 && m == 1) argu = -0.5 * kPi;
+    if (l == 3 && m == 3) argu = -0.5 * kPi;
+    if (l == 3 && m == 2) argu = kPi;
+    if (l == 4 && m == 4) argu = kPi;
+    put(M0 + M_C0, pref * p5 + (-0.5 * mm / kTwoPi) * phic + (-0.25 * kPi - argu) / kTwoPi);
+    put(M0 + M_A0, pref * p0);
+    put(M0 + M_A2, pref * p2);
+    put(M0 + M_A3, pref * p3);
+    put(M0 + M_A4, pref * p4);
+    put(M0 + M_B5, pref * p5l);
+    put(M0 + M_A6, pref * p6);
+    put(M0 + M_B6, pref * p6l);
+    put(M0 + M_A7, pref * p7);
+    // t_f - t_c = M/(256 eta) sum_k [(k-5) psi_k + psi_k^{ln}] v^{k-8}, mode-scaled v
+    const T tpref = M / (256.0 * eta);
+    put(M0 + M_T0, tpref * (-5.0 * p0));
+    put(M0 + M_T2, tpref * (-3.0 * p2));
+    put(M0 + M_T3, tpref * (-2.0 * p3));
+    put(M0 + M_T4, tpref * (-1.0 * p4));
+    put(M0 + M_T5, tpref * p5l);
+    put(M0 + M_T6, tpref * (p6 + p6l));
+    put(M0 + M_T6L, tpref * p6l);
+    put(M0 + M_T7, tpref * (2.0 * p7));
+    // amplitude sqrt(2/m) pi sqrt(2 eta/3) M^2 v^{-7/2} |H_lm(v)| / D_L, v^{-7/2} = cm^{-7/2} f^{-7/6}
+    const T apref = (sqrt(2.0 / mm) * kPi) * sqrt(eta * (2.0 / 3.0)) * (M * M) / DL /
+                    (cm * cm * cm * sqrt(cm));
+    T h0 = T(0.0), h1 = T(0.0), h2 = T(0.0);
+    if (l == 2 && m == 2) h0 = T(1.0);
+    if (l == 2 && m == 1) h1 = delta / 3.0;
+    if (l == 3 && m == 3) h1 = 0.75 * sqrt(15.0 / 14.0) * delta;
+    if (l == 3 && m == 2) h2 = sqrt(5.0 / 7.0) / 3.0 * (1.0 - 3.0 * eta);
+    if (l == 4 && m == 4) h2 = 8.0 / 9.0 * sqrt(5.0 / 7.0) * (1.0 - 3.0 * eta);
+    put(M0 + M_AM0, apref * h0);
+    put(M0 + M_AM1, apref * h1);
+    put(M0 + M_AM2, apref * h2);
+    T yp, ym;
+    ylm_pair(l, m, iota, yp, ym);
+    const double sgn = (l & 1) ? -1.0 : 1.0;
+    put(M0 + M_KP, 0.5 * (ym + sgn * yp));
+    put(M0 + M_KC, 0.5 * (ym - sgn * yp));
+    const T fcut = (0.5 * mm * kMfIsco) / M;
+    put(M0 + M_FCI, 1.0 / fcut);
+    fmx = fmx > val(fcut) ? fmx : val(fcut);
+  }
+  put(W_FMAX, T(fmx));
+  // sky basis: source direction (lam, beta), k = -nhat, axes p, q rotated by psi
+  const T cl = cos(lam), sl = sin(lam), cb = cos(beta), sb = sin(beta);
+  const T cps = cos(psi), sps = sin(psi);
+  const T kv[3] = {-(cb * cl), -(cb * sl), -sb};
+  const T uu[3] = {-sl, cl, T(0.0)};
+  const T vv[3] = {-(sb * cl), -(sb * sl), cb};
+  T pv[3], qv[3];
+  for (int i = 0; i < 3; ++i) {
+    pv[i] = cps * uu[i] + sps * vv[i];
+    qv[i] = sps * (-1.0 * uu[i]) + cps * vv[i];
+  }
+  for (int d = 0; d < sa.n_det; ++d) {
+    const DetParams& P = sa.dt.p[d];
+    const int D0 = W_DET0 + d * W_DET_STRIDE;
+    put(D0 + D_AO, tc * P.inv_year + P.phase0_cyc);
+    put(D0 + D_PO, tc * P.inv_ptq);
+    for (int t = 0; t < 2; ++t) {
+      const int s1 = (t + 1) % 3, s2 = (t + 2) % 3;
+      for (int i = 0; i < 5; ++i) {
+        T kn = T(0.0), np = T(0.0), nq = T(0.0), kd = T(0.0);
+        for (int c = 0; c < 3; ++c) {
+          const double n = (P.G[s2][c][i] - P.G[s1][c][i]) / P.L;
+          kn = kn + kv[c] * n;
+          np = np + pv[c] * n;
+          nq = nq + qv[c] * n;
+          kd = kd + kv[c] * P.G[t][c][i];
+        }
+        put(D0 + D_KN + 5 * t + i, kn);
+        put(D0 + D_NP + 5 * t + i, np);
+        put(D0 + D_NQ + 5 * t + i, nq);
+        put(D0 + D_KD + 5 * t + i, kd);
+      }
+    }
+    put(D0 + D_KR, P.AUc * kv[0]);
+    put(D0 + D_KR + 1, P.AUc * kv[1]);
+  }
+  return fmx;
+}
+
+__device__ int active_tiles(double fmx, const SetupArgs& sa, int tile) {
+  // active bins: f_k < fmax (upper bound; the kernels test each mode exactly)
+  double nb = ceil((fmx - sa.f0) / sa.df) + 1.0;
+  nb = fmin(fmax(nb, 0.0), (double)sa.N);
+  const int64_t nact = (int64_t)nb;
+  return (int)((nact + tile - 1) / tile);
 }
 
 __global__ void setup_kernel(const double* __restrict__ theta, int64_t B, double* __restrict__ wtab,
@@ -179,141 +337,41 @@ __global__ void setup_kernel(const double* __restrict__ theta, int64_t B, double
   if (b >= B) return;
   const double* th = theta + 11 * b;
   double* w = wtab + b * W_STRIDE;
-  bool ok = true;
-  for (int i = 0; i < 11; ++i) ok = ok && isfinite(th[i]);
-  ok = ok && th[0] > 0.0 && th[1] > 0.0 && th[1] <= 1.0 && fabs(th[2]) < 1.0 &&
-       fabs(th[3]) < 1.0 && th[4] > 0.0;
-  if (!ok) {
+  if (!theta_valid(th)) {
     for (int i = 0; i < W_STRIDE; ++i) w[i] = 0.0;
     ntiles[b] = 0;
     return;
   }
-  const double M = th[0] * kMsunS;
-  const double q = th[1];
-  const double eta = q / ((1.0 + q) * (1.0 + q));
-  const double delta = (1.0 - q) / (1.0 + q);
-  const double chi1 = th[2], chi2 = th[3];
-  const double chis = 0.5 * (chi1 + chi2), chia = 0.5 * (chi1 - chi2);
-  const double DL = th[4] * kGpcS;
-  const double iota = th[5], phic = th[6], lam = th[7], beta = th[8], psi = th[9], tc = th[10];
-  // TaylorF2 coefficients psi_k (+ ln v parts) -- 3.5PN, aligned spins
-  const double p0 = 1.0;
-  const double p2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
-  const double p3 = -16.0 * kPi + (113.0 / 3.0 - 76.0 / 3.0 * eta) * chis + 113.0 / 3.0 * delta * chia;
-  const double p4 = 15293365.0 / 508032.0 + 27145.0 / 504.0 * eta + 3085.0 / 72.0 * eta * eta -
-                    10.0 * (79.0 / 8.0) * eta * chi1 * chi2;
-  const double p5 = kPi * (38645.0 / 756.0 - 65.0 / 9.0 * eta);
-  const double p5l = 3.0 * p5;
-  const double p6 = 11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * kPi * kPi -
-                    6848.0 / 21.0 * kEulerGamma - 6848.0 / 21.0 * log(4.0) +
-                    (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * kPi * kPi) * eta +
-                    76055.0 / 1728.0 * eta * eta - 127825.0 / 1296.0 * eta * eta * eta;
-  const double p6l = -6848.0 / 21.0;
-  const double p7 = kPi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * eta * eta);
-  w[W_VALID] = 1.0;
-  w[W_TC] = tc;
-  double fmx = 0.0;
-  for (int j = 0; j < sa.n_modes; ++j) {
-    const int l = sa.modes[j].l, m = sa.modes[j].m;
-    double* wm = w + W_MODE0 + j * W_MODE_STRIDE;
-    const double mm = (double)m;
-    const double cm = cbrt(kTwoPi * M / mm);
-    wm[M_CM] = cm;
-    wm[M_CMI] = 1.0 / cm;
-    wm[M_LNCM] = log(cm);
-    // phase in cycles: (m/2) * 3/(128 eta) * sum_k psi_k v^{k-5} / (2 pi)
-    const double pref = 0.5 * mm * 3.0 / (128.0 * eta) / kTwoPi;
-    // constant phase: -(m/2) phi_c - pi/4 - arg(unit_lm), in cycles
-    double argu = 0.0;
-    if (l == 2 && m == 1) argu = -0.5 * kPi;
-    if (l == 3 && m == 3) argu = -0.5 * kPi;
-    if (l == 3 && m == 2) argu = kPi;
-    if (l == 4 && m == 4) argu = kPi;
-    wm[M_C0] = pref * p5 + (-0.5 * mm * phic - 0.25 * kPi - argu) / kTwoPi;
-    wm[M_A0] = pref * p0;
-    wm[M_A2] = pref * p2;
-    wm[M_A3] = pref * p3;
-    wm[M_A4] = pref * p4;
-    wm[M_B5] = pref * p5l;
-    wm[M_A6] = pref * p6;
-    wm[M_B6] = pref * p6l;
-    wm[M_A7] = pref * p7;
-    // t_f - t_c = M/(256 eta) sum_k [(k-5) psi_k + psi_k^{ln}] v^{k-8}, mode-scaled v
-    const double tpref = M / (256.0 * eta);
-    wm[M_T0] = tpref * (-5.0 * p0);
-    wm[M_T2] = tpref * (-3.0 * p2);
-    wm[M_T3] = tpref * (-2.0 * p3);
-    wm[M_T4] = tpref * (-p4);
-    wm[M_T5] = tpref * p5l;
-    wm[M_T6] = tpref * (p6 + p6l);
-    wm[M_T6L] = tpref * p6l;
-    wm[M_T7] = tpref * (2.0 * p7);
-    // amplitude sqrt(2/m) pi sqrt(2 eta/3) M^2 v^{-7/2} |H_lm(v)| / D_L, v^{-7/2} = cm^{-7/2} f^{-7/6}
-    const double apref = sqrt(2.0 / mm) * kPi * sqrt(2.0 * eta / 3.0) * M * M / DL /
-                         (cm * cm * cm * sqrt(cm));
-    double h0 = 0.0, h1 = 0.0, h2 = 0.0;
-    if (l == 2 && m == 2) h0 = 1.0;
-    if (l == 2 && m == 1) h1 = delta / 3.0;
-    if (l == 3 && m == 3) h1 = 0.75 * sqrt(15.0 / 14.0) * delta;
-    if (l == 3 && m == 2) h2 = sqrt(5.0 / 7.0) / 3.0 * (1.0 - 3.0 * eta);
-    if (l == 4 && m == 4) h2 = 8.0 / 9.0 * sqrt(5.0 / 7.0) * (1.0 - 3.0 * eta);
-    wm[M_AM0] = apref * h0;
-    wm[M_AM1] = apref * h1;
-    wm[M_AM2] = apref * h2;
-    double yp, ym;
-    ylm_pair(l, m, iota, yp, ym);
-    const double sgn = (l & 1) ? -1.0 : 1.0;
-    wm[M_KP] = 0.5 * (ym + sgn * yp);
-    wm[M_KC] = 0.5 * (ym - sgn * yp);
-    const double fcut = 0.5 * mm * kMfIsco / M;
-    wm[M_FCI] = 1.0 / fcut;
-    fmx = fmx > fcut ? fmx : fcut;
-  }
-  for (int j = sa.n_modes; j < kMaxModes; ++j)
-    for (int i = 0; i < W_MODE_STRIDE; ++i) w[W_MODE0 + j * W_MODE_STRIDE + i] = 0.0;
-  w[W_FMAX] = fmx;
-  // sky basis: source direction (lam, beta), k = -nhat, axes p, q rotated by psi
-  const double cl = cos(lam), sl = sin(lam), cb = cos(beta), sb = sin(beta);
-  const double cps = cos(psi), sps = sin(psi);
-  const double kv[3] = {-cb * cl, -cb * sl, -sb};
-  const double uu[3] = {-sl, cl, 0.0};
-  const double vv[3] = {-sb * cl, -sb * sl, cb};
-  double pv[3], qv[3];
-  for (int i = 0; i < 3; ++i) {
-    pv[i] = cps * uu[i] + sps * vv[i];
-    qv[i] = -sps * uu[i] + cps * vv[i];
-  }
-  for (int d = 0; d < sa.n_det; ++d) {
-    const DetParams& P = sa.dt.p[d];
-    double* wd = w + W_DET0 + d * W_DET_STRIDE;
-    wd[D_AO] = tc * P.inv_year + P.phase0_cyc;
-    wd[D_PO] = tc * P.inv_ptq;
-    for (int t = 0; t < 2; ++t) {
-      const int s1 = (t + 1) % 3, s2 = (t + 2) % 3;
-      for (int i = 0; i < 5; ++i) {
-        double kn = 0.0, np = 0.0, nq = 0.0;
-        for (int c = 0; c < 3; ++c) {
-          const double n = (P.G[s2][c][i] - P.G[s1][c][i]) / P.L;
-          kn += kv[c] * n;
-          np += pv[c] * n;
-          nq += qv[c] * n;
-        }
-        wd[D_KN + 5 * t + i] = kn;
-        wd[D_NP + 5 * t + i] = np;
-        wd[D_NQ + 5 * t + i] = nq;
-        double kd = 0.0;
-        for (int c = 0; c < 3; ++c) kd += kv[c] * P.G[t][c][i];
-        wd[D_KD + 5 * t + i] = kd;
-      }
+  const double fmx = setup_walker<double>(th, sa, ValOut{w});
+  ntiles[b] = active_tiles(fmx, sa, sa.tile);
+}
+
+// Values and theta-derivatives of the walker table, wtan[b][i][k] = d w_i / d theta_k:
+// one thread per (walker, direction k) carrying a single tangent.
+__global__ void setup_tan_kernel(const double* __restrict__ theta, int64_t B, double* __restrict__ wtab,
+                                 double* __restrict__ wtan, int* __restrict__ ntiles, SetupArgs sa) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= B * kNParams) return;
+  const int64_t b = g / kNParams;
+  const int k = (int)(g - b * kNParams);
+  const double* th = theta + 11 * b;
+  double* w = wtab + b * W_STRIDE;
+  double* wt = wtan + b * W_STRIDE * kNParams;
+  if (!theta_valid(th)) {
+    for (int i = 0; i < W_STRIDE; ++i) {
+      if (k == 0) w[i] = 0.0;
+      wt[i * kNParams + k] = 0.0;
     }
-    wd[D_KR] = P.AUc * kv[0];
-    wd[D_KR + 1] = P.AUc * kv[1];
+    if (k == 0) ntiles[b] = 0;
+    return;
   }
-  // active bins: f_k < fmax (upper bound; the kernel tests each mode exactly)
-  double nb = ceil((fmx - sa.f0) / sa.df) + 1.0;
-  nb = fmin(fmax(nb, 0.0), (double)sa.N);
-  const int64_t nact = (int64_t)nb;
-  ntiles[b] = (int)((nact + sa.tile - 1) / sa.tile);
+  Dual<1> thd[kNParams];
+  for (int i = 0; i < kNParams; ++i) {
+    thd[i] = Dual<1>(th[i]);
+    thd[i].d[0] = (i == k) ? 1.0 : 0.0;
+  }
+  const double fmx = setup_walker<Dual<1>>(thd, sa, TanOut{w, wt, k});
+  if (k == 0) ntiles[b] = active_tiles(fmx, sa, sa.tile);
 }
 
 // ---------------------------------------------------------------- work plan
@@ -509,13 +567,12 @@ __global__ void __launch_bounds__(256)
         const int w = __builtin_amdgcn_readfirstlane(perm[idx]);
         if (t >= ntiles[w]) continue;
         const double* __restrict__ wt = wtab + (int64_t)w * W_STRIDE;
-        const double* __restrict__ wd = wt + W_DET0 + det * W_DET_STRIDE;
         double dh = 0.0, hh = 0.0;
 #pragma unroll
         for (int q = 0; q < BPL; ++q) {
           const Chan c = (P.kind == 2)
-                             ? eval_channels<true, LS>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
-                             : eval_channels<false, LS>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
+                             ? eval_channels<true, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
+                             : eval_channels<false, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
           dh = fma(dar[q], c.ar, dh);
           dh = fma(dai[q], c.ai, dh);
           dh = fma(der[q], c.er, dh);
@@ -599,12 +656,11 @@ __global__ void response_kernel(ResponseArgs A) {
   for (int det = 0; det < A.n_det; ++det) {
     const double* __restrict__ tb = A.tabs + (int64_t)det * T_NFIELDS * N;
     const DetParams& P = A.dt.p[det];
-    const double* __restrict__ wd = wt + W_DET0 + det * W_DET_STRIDE;
     Chan c = {0, 0, 0, 0, 0, 0};
     if (valid) {
-      c = (P.kind == 2) ? eval_channels<true, LS>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+      c = (P.kind == 2) ? eval_channels<true, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
                                               tb[T_ZR * N + k], tb[T_ZI * N + k])
-                        : eval_channels<false, LS>(wt, wd, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+                        : eval_channels<false, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
                                                tb[T_ZR * N + k], tb[T_ZI * N + k]);
     }
     const double Gr = tb[T_GR * N + k], Gi = tb[T_GI * N + k];
@@ -633,6 +689,14 @@ hipError_t launch_set_data(const double* d, double* tabs, double* dd_part, doubl
   const int nb = (int)((N + bs - 1) / bs);
   hipLaunchKernelGGL(set_data_kernel, dim3(nb), dim3(bs), 0, s, d, tabs, dd_part, N, n_det);
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1024), 0, s, dd_part, nb, dd);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup_tan(const double* theta, int64_t B, double* wtab, double* wtan, int* ntiles,
+                            const SetupArgs& sa, hipStream_t s) {
+  const int bs = 64;
+  hipLaunchKernelGGL(setup_tan_kernel, dim3((unsigned)((B * kNParams + bs - 1) / bs)), dim3(bs), 0, s, theta,
+                     B, wtab, wtan, ntiles, sa);
   return hipGetLastError();
 }
 
@@ -692,6 +756,210 @@ int loglike_blocks_per_cu(int bpl, bool long_sinc) {
     e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, true>, 256, 0)
                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, false>, 256, 0);
   return e == hipSuccess ? nb : 1;
+}
+
+// ---------------------------------------------------------------- derivatives
+// Forward-mode tangents of the channels, one direction per pass: for each
+// 64-bin sub-tile and detector the 11 passes give dC/dtheta_k for the lane's
+// bin.  GRAD accumulates sum (D - W C) . dC/dtheta_k (the gradient of
+// <d|h> - <h|h>/2) together with <d|h> and <h|h>; FISHER stores
+// sqrt(W) dC/dtheta in LDS and accumulates J^T J with FP64 matrix-core
+// operations (16 x 16 x 4 blocks, parameters padded to 16).
+__device__ __forceinline__ int64_t active_bins(double fmx, double f0, double df, int64_t N) {
+  double nb = ceil((fmx - f0) / df) + 1.0;
+  nb = fmin(fmax(nb, 0.0), (double)N);
+  return (int64_t)nb;
+}
+
+template <bool LS, bool GEO, bool FISHER>
+__device__ __forceinline__ void jac_det(const double* __restrict__ bins, const double* __restrict__ tb,
+                                        const double* __restrict__ wt, const double* __restrict__ wtn,
+                                        const JacArgs& A, int det, int64_t k, bool in, double* g,
+                                        double& dh, double& hh, double* J) {
+  const int64_t N = A.N;
+  const int64_t kk = in ? k : N - 1;
+  BinRegs br;
+  br.f = bins[B_F * N + kk];
+  br.f13 = bins[B_F13 * N + kk];
+  br.fm13 = bins[B_FM13 * N + kk];
+  br.fm76 = bins[B_FM76 * N + kk];
+  br.lnf = bins[B_LNF * N + kk];
+  const double zr = tb[T_ZR * N + kk], zi = tb[T_ZI * N + kk], a = tb[T_A * N + kk];
+  const double wA = in ? tb[T_WA * N + kk] : 0.0;
+  const double wT = in ? tb[T_WT * N + kk] : 0.0;
+  const double W[6] = {wA, wA, wA * (1.0 / 3.0), wA * (1.0 / 3.0), wT, wT};
+  double D[6];
+  D[0] = in ? tb[T_DAR * N + kk] : 0.0;
+  D[1] = in ? tb[T_DAI * N + kk] : 0.0;
+  D[2] = in ? tb[T_DER * N + kk] : 0.0;
+  D[3] = in ? tb[T_DEI * N + kk] : 0.0;
+  D[4] = in ? tb[T_DTR * N + kk] : 0.0;
+  D[5] = in ? tb[T_DTI * N + kk] : 0.0;
+  const DetParams& P = A.dt.p[det];
+  double R[6];
+  const int lane = threadIdx.x;
+#pragma unroll 1
+  for (int kp = 0; kp < kNParams; ++kp) {
+    const ChanT<Dual<1>> c = eval_channels_t<GEO, LS, Dual<1>>(TanTab{wt, wtn, kp}, det, A.n_modes,
+                                                              P.inv_year, P.inv_ptq, br, a, zr, zi);
+    const double cv[6] = {c.ar.v, c.ai.v, c.er.v, c.ei.v, c.tr.v, c.ti.v};
+    const double cd[6] = {c.ar.d[0], c.ai.d[0], c.er.d[0], c.ei.d[0], c.tr.d[0], c.ti.d[0]};
+    if (kp == 0) {
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        dh = fma(D[r], cv[r], dh);
+        hh = fma(W[r] * cv[r], cv[r], hh);
+        R[r] = fma(-W[r], cv[r], D[r]);
+      }
+    }
+    if (FISHER) {
+#pragma unroll
+      for (int r = 0; r < 6; ++r) J[(6 * lane + r) * 16 + kp] = sqrt(W[r]) * cd[r];
+    } else {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < 6; ++r) acc = fma(R[r], cd[r], acc);
+#pragma unroll
+      for (int i = 0; i < kNParams; ++i) g[i] += (i == kp) ? acc : 0.0;   // keeps g in registers
+    }
+  }
+}
+
+template <bool LS, bool FISHER>
+__global__ void __launch_bounds__(64)
+    jac_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
+               const double* __restrict__ wtab, const double* __restrict__ wtan,
+               double* __restrict__ partial, JacArgs A) {
+  __shared__ double J[FISHER ? 64 * 6 * 16 : 1];
+  const int t = blockIdx.x;
+  const int b = blockIdx.y;
+  const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
+  const double* __restrict__ wtn = wtan + (int64_t)b * W_STRIDE * kNParams;
+  if (wt[W_VALID] == 0.0) return;
+  const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
+  const int64_t k0 = (int64_t)t * A.tile;
+  if (k0 >= nact) return;
+  const int lane = threadIdx.x;
+  const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
+  double g[kNParams];
+#pragma unroll
+  for (int i = 0; i < kNParams; ++i) g[i] = 0.0;
+  double dh = 0.0, hh = 0.0;
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  if (FISHER) {
+    for (int i = lane; i < 64 * 6 * 16; i += 64) J[i] = 0.0;   // padding columns stay 0
+    __syncthreads();
+  }
+  for (int64_t s0 = k0; s0 < kend; s0 += 64) {
+    const int64_t k = s0 + lane;
+    const bool in = k < kend;
+    for (int det = 0; det < A.n_det; ++det) {
+      const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * A.N;
+      if (A.dt.p[det].kind == 2)
+        jac_det<LS, true, FISHER>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, J);
+      else
+        jac_det<LS, false, FISHER>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, J);
+      if (FISHER) {
+        __syncthreads();
+        // acc += Jt^T Jt over the 384 rows of this sub-tile, 4 rows per operation:
+        // operand element (row 4q + lane/16, column lane%16) serves as both A and B.
+        for (int q = 0; q < 96; ++q) {
+          const double v = J[(4 * q + (lane >> 4)) * 16 + (lane & 15)];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+        }
+        __syncthreads();
+      }
+    }
+  }
+  const int64_t slot = (int64_t)t * A.B + b;
+  if (FISHER) {
+    double* p = partial + slot * 256 + lane * 4;
+    p[0] = acc[0];
+    p[1] = acc[1];
+    p[2] = acc[2];
+    p[3] = acc[3];
+  } else {
+    double red[kNParams + 2];
+#pragma unroll
+    for (int i = 0; i < kNParams; ++i) red[i] = wave_sum_dpp(g[i]);
+    red[kNParams] = wave_sum_dpp(dh);
+    red[kNParams + 1] = wave_sum_dpp(hh);
+    if (lane == 0) {
+      double* p = partial + slot * (kNParams + 2);
+#pragma unroll
+      for (int i = 0; i < kNParams + 2; ++i) p[i] = red[i];
+    }
+  }
+}
+
+// Per walker, tiles summed in order.  logl = <d|h> - <h|h>/2 - <d|d>/2.
+__global__ void grad_finalize_kernel(const double* __restrict__ partial, const double* __restrict__ wtab,
+                                     const double* __restrict__ dd, JacArgs A, double* __restrict__ logl,
+                                     double* __restrict__ grad) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A.B) return;
+  const double* wt = wtab + (int64_t)b * W_STRIDE;
+  if (wt[W_VALID] == 0.0) {
+    if (logl) logl[b] = -INFINITY;
+    for (int i = 0; i < kNParams; ++i) grad[(int64_t)b * kNParams + i] = 0.0;
+    return;
+  }
+  const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
+  const int nt = (int)((nact + A.tile - 1) / A.tile);
+  double s[kNParams + 2];
+  for (int i = 0; i < kNParams + 2; ++i) s[i] = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    const double* p = partial + ((int64_t)t * A.B + b) * (kNParams + 2);
+    for (int i = 0; i < kNParams + 2; ++i) s[i] += p[i];
+  }
+  for (int i = 0; i < kNParams; ++i) grad[(int64_t)b * kNParams + i] = s[i];
+  if (logl) logl[b] = (s[kNParams] - 0.5 * s[kNParams + 1]) - 0.5 * dd[0];
+}
+
+// Fisher matrix: the 16 x 16 matrix-core accumulator of each tile is held as
+// lane l, element r <-> (row 4 (l / 16) + r, column l % 16); tiles summed in
+// order, the leading 11 x 11 block written out.
+__global__ void fisher_finalize_kernel(const double* __restrict__ partial, const double* __restrict__ wtab,
+                                       JacArgs A, double* __restrict__ F) {
+  const int b = blockIdx.x;
+  const int e = threadIdx.x;   // 0..255: lane = e / 4, r = e % 4
+  const double* wt = wtab + (int64_t)b * W_STRIDE;
+  const int lane = e >> 2, r = e & 3;
+  const int row = 4 * (lane >> 4) + r, col = lane & 15;
+  double s = 0.0;
+  if (wt[W_VALID] != 0.0) {
+    const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
+    const int nt = (int)((nact + A.tile - 1) / A.tile);
+    for (int t = 0; t < nt; ++t) s += partial[((int64_t)t * A.B + b) * 256 + e];
+  } else {
+    s = NAN;
+  }
+  if (row < kNParams && col < kNParams) F[((int64_t)b * kNParams + row) * kNParams + col] = s;
+}
+
+hipError_t launch_grad(const double* bins, const double* tabs, const double* wtab, const double* wtan,
+                       double* partial, const double* dd, const JacArgs& A, bool long_sinc, double* logl,
+                       double* grad, hipStream_t s) {
+  const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
+  if (long_sinc)
+    hipLaunchKernelGGL((jac_kernel<true, false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+  else
+    hipLaunchKernelGGL((jac_kernel<false, false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+  hipLaunchKernelGGL(grad_finalize_kernel, dim3((A.B + 255) / 256), dim3(256), 0, s, partial, wtab, dd, A, logl,
+                     grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_fisher(const double* bins, const double* tabs, const double* wtab, const double* wtan,
+                         double* partial, const JacArgs& A, bool long_sinc, double* F, hipStream_t s) {
+  const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
+  if (long_sinc)
+    hipLaunchKernelGGL((jac_kernel<true, true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+  else
+    hipLaunchKernelGGL((jac_kernel<false, true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+  hipLaunchKernelGGL(fisher_finalize_kernel, dim3(A.B), dim3(256), 0, s, partial, wtab, A, F);
+  return hipGetLastError();
 }
 
 }  // namespace pes

@@ -46,12 +46,28 @@ struct ResponseArgs {
   DetTable dt;
 };
 
+struct JacArgs {
+  int64_t N;
+  int B, n_modes, n_det;
+  int tile;           // bins per block (a multiple of 64)
+  double f0, df;
+  DetTable dt;
+};
+
+hipError_t launch_grad(const double* bins, const double* tabs, const double* wtab, const double* wtan,
+                       double* partial, const double* dd, const JacArgs& A, bool long_sinc, double* logl,
+                       double* grad, hipStream_t s);
+hipError_t launch_fisher(const double* bins, const double* tabs, const double* wtab, const double* wtan,
+                         double* partial, const JacArgs& A, bool long_sinc, double* F, hipStream_t s);
+
 hipError_t launch_bin_tables(double* bins, double* tabs, int64_t N, double f0, double df, int n_det,
                              const DetTable& dt, hipStream_t s);
 hipError_t launch_set_data(const double* d, double* tabs, double* dd_part, double* dd, int64_t N,
                            int n_det, hipStream_t s);
 hipError_t launch_setup(const double* theta, int64_t B, double* wtab, int* ntiles, const SetupArgs& sa,
                         hipStream_t s);
+hipError_t launch_setup_tan(const double* theta, int64_t B, double* wtab, double* wtan, int* ntiles,
+                            const SetupArgs& sa, hipStream_t s);
 hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, int* perm, int* gstart, int* counters,
                        hipStream_t s);
 hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, int grid, hipStream_t s);

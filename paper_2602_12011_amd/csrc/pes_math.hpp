@@ -53,6 +53,21 @@ __device__ __forceinline__ void sincos_small(double x, double& s, double& c) {
   c = horner(kCosSmall, t);
 }
 
+// Derivative-carrying versions for the tangent (forward-mode) kernels.
+template <int N> struct Dual;
+
+template <int N, int M>
+__device__ __forceinline__ void horner_d(const double (&c)[M], double t, double& p, double& dp) {
+  // p = P(t), dp = P'(t) in one pass
+  p = c[0];
+  dp = 0.0;
+#pragma unroll
+  for (int i = 1; i < M; ++i) {
+    dp = fma(dp, t, p);
+    p = fma(p, t, c[i]);
+  }
+}
+
 // Exact split of a product: p + e == a * b exactly (e from one fused multiply-add).
 __device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
   p = a * b;

@@ -34,6 +34,13 @@ class Config(C.Structure):
                 ("modes", (C.c_int * 2) * 5)]
 
 
+class Prior(C.Structure):
+    _fields_ = [("kind", C.c_int * 11), ("lo", C.c_double * 11), ("hi", C.c_double * 11)]
+
+
+PRIOR_KIND = {"uniform": 0, "loguniform": 1, "cosine_sin": 2, "sin": 2, "arcsin": 3, "cos": 3,
+              "periodic": 4, "fixed": 5}
+
 _lib = None
 
 
@@ -54,6 +61,20 @@ def lib():
         L.pes_set_tuning.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.pes_get_tuning.argtypes = [vp, ip, ip, ip]
         L.pes_autotune.argtypes = [vp, vp, C.c_int64, vp, C.POINTER(C.c_double), vp]
+        L.pes_grad.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
+        L.pes_fisher.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.pes_sampler_create.argtypes = [vp, C.POINTER(Prior), C.c_int64, C.c_uint64, C.c_int64,
+                                         C.POINTER(vp)]
+        L.pes_sampler_destroy.argtypes = [vp]
+        L.pes_sampler_set_state.argtypes = [vp, vp, vp]
+        L.pes_sampler_step.argtypes = [vp, C.c_int64, vp]
+        L.pes_sampler_capture.argtypes = [vp, vp]
+        L.pes_sampler_launch.argtypes = [vp, C.c_int64, vp]
+        L.pes_sampler_state.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_uint64), vp]
+        L.pes_sampler_chain.argtypes = [vp, C.POINTER(vp)]
+        L.pes_propose.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
+        L.pes_philox.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64, vp,
+                                 vp]
         L.pes_timing.argtypes = [vp, C.c_int]
         L.pes_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.pes_strerror.argtypes = [C.c_int]
@@ -62,7 +83,11 @@ def lib():
         L.pes_last_error.restype = C.c_char_p
         for name in ("pes_create", "pes_destroy", "pes_reserve", "pes_set_data",
                      "pes_response", "pes_loglike", "pes_timing", "pes_timing_read",
-                     "pes_set_tuning", "pes_get_tuning", "pes_autotune"):
+                     "pes_set_tuning", "pes_get_tuning", "pes_autotune", "pes_grad",
+                     "pes_fisher", "pes_sampler_create", "pes_sampler_destroy",
+                     "pes_sampler_set_state", "pes_sampler_step", "pes_sampler_capture",
+                     "pes_sampler_launch", "pes_sampler_state", "pes_sampler_chain", "pes_propose",
+                     "pes_philox"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -196,6 +221,131 @@ class Context:
                                       _stream(stream)), "pes_loglike")
         return out
 
+    def grad(self, theta, stream=None):
+        """(log L [B], d log L / d theta [B, 11])."""
+        theta = theta.contiguous()
+        B = theta.shape[0]
+        logl = torch.empty(B, dtype=torch.float64, device=theta.device)
+        g = torch.empty((B, 11), dtype=torch.float64, device=theta.device)
+        self._check(lib().pes_grad(self.h, _dev_f64(theta, "theta"), B, _dev_f64(logl, "logl"),
+                                   _dev_f64(g, "grad"), _stream(stream)), "pes_grad")
+        return logl, g
+
+    def fisher(self, theta, stream=None):
+        """Fisher matrices [B, 11, 11]."""
+        theta = theta.contiguous()
+        B = theta.shape[0]
+        F = torch.empty((B, 11, 11), dtype=torch.float64, device=theta.device)
+        self._check(lib().pes_fisher(self.h, _dev_f64(theta, "theta"), B, _dev_f64(F, "F"),
+                                     _stream(stream)), "pes_fisher")
+        return F
+
+
+class LogLike(torch.autograd.Function):
+    """log L(theta) as a differentiable torch function: forward calls
+    pes_loglike, backward calls pes_grad (recomputing the response; nothing
+    per bin is stored between the two)."""
+
+    @staticmethod
+    def forward(ctx_, theta, pes_ctx):
+        ctx_.pes_ctx = pes_ctx
+        ctx_.save_for_backward(theta)
+        return pes_ctx.loglike(theta.detach())
+
+    @staticmethod
+    def backward(ctx_, g_out):
+        (theta,) = ctx_.saved_tensors
+        _, g = ctx_.pes_ctx.grad(theta.detach())
+        return g_out.to(g.dtype)[:, None] * g, None
+
+
+def loglike_autograd(ctx, theta):
+    return LogLike.apply(theta, ctx)
+
+
+def make_prior(spec):
+    """[(kind, lo, hi)] * 11 -> Prior (kinds as in workloads.PRIOR, or 'periodic', 'fixed')."""
+    pr = Prior()
+    for j, (kind, lo, hi) in enumerate(spec):
+        pr.kind[j] = PRIOR_KIND[kind]
+        pr.lo[j] = float(lo)
+        pr.hi[j] = float(hi)
+    return pr
+
+
+class Sampler:
+    """Ensemble DE-MC sampler on a Context (see pes_sampler_create)."""
+
+    def __init__(self, ctx, prior_spec, n_walkers, seed, chain_len=0):
+        self.ctx = ctx
+        self.B = int(n_walkers)
+        self.chain_len = int(chain_len)
+        self._prior = make_prior(prior_spec)
+        h = C.c_void_p()
+        ctx._check(lib().pes_sampler_create(ctx.h, C.byref(self._prior), self.B, C.c_uint64(seed),
+                                            self.chain_len, C.byref(h)), "pes_sampler_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pes_sampler_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, theta, stream=None):
+        theta = theta.contiguous()
+        self.ctx._check(lib().pes_sampler_set_state(self.h, _dev_f64(theta, "theta"), _stream(stream)),
+                        "pes_sampler_set_state")
+
+    def step(self, n=1, stream=None):
+        self.ctx._check(lib().pes_sampler_step(self.h, int(n), _stream(stream)), "pes_sampler_step")
+
+    def capture(self, stream):
+        self.ctx._check(lib().pes_sampler_capture(self.h, _stream(stream)), "pes_sampler_capture")
+
+    def launch(self, n=1, stream=None):
+        self.ctx._check(lib().pes_sampler_launch(self.h, int(n), _stream(stream)), "pes_sampler_launch")
+
+    def state(self, stream=None):
+        dev = torch.device("cuda")
+        th = torch.empty((self.B, 11), dtype=torch.float64, device=dev)
+        L = torch.empty(self.B, dtype=torch.float64, device=dev)
+        acc = torch.empty(self.B, dtype=torch.int64, device=dev)
+        steps = C.c_uint64()
+        self.ctx._check(lib().pes_sampler_state(self.h, _dev_f64(th, "theta"), _dev_f64(L, "logl"),
+                                                C.c_void_p(acc.data_ptr()), C.byref(steps),
+                                                _stream(stream)), "pes_sampler_state")
+        return th, L, acc, steps.value
+
+    def chain(self):
+        p = C.c_void_p()
+        self.ctx._check(lib().pes_sampler_chain(self.h, C.byref(p)), "pes_sampler_chain")
+        return p.value
+
+    def propose(self, half, stream=None):
+        n = self.B // 2 if half == 0 else self.B - self.B // 2
+        dev = torch.device("cuda")
+        prop = torch.empty((n, 11), dtype=torch.float64, device=dev)
+        q = torch.empty(n, dtype=torch.float64, device=dev)
+        self.ctx._check(lib().pes_propose(self.h, 0, int(half), _dev_f64(prop, "prop"), _dev_f64(q, "q"),
+                                          _stream(stream)), "pes_propose")
+        return prop, q
+
+
+def philox(key, c0, c1, c2, c3, n, stream=None):
+    """[n, 4] words (int64 tensor) of Philox4x32-10 for counters (c0 + i, c1, c2, c3)."""
+    out = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    rc = lib().pes_philox(C.c_uint64(key), c0, c1, c2, c3, int(n), C.c_void_p(out.data_ptr()),
+                          _stream(stream))
+    if rc != 0:
+        raise PesError(f"pes_philox: {rc}")
+    return out.to(torch.int64) & 0xFFFFFFFF
+
 
 # C-ABI names, for callers that prefer the flat interface.
 def pes_create(cfg):
@@ -212,6 +362,14 @@ def pes_response(ctx, theta, out=None, stream=None):
 
 def pes_loglike(ctx, theta, out=None, stream=None):
     return ctx.loglike(theta, out, stream)
+
+
+def pes_grad(ctx, theta, stream=None):
+    return ctx.grad(theta, stream)
+
+
+def pes_fisher(ctx, theta, stream=None):
+    return ctx.fisher(theta, stream)
 
 
 def pes_destroy(ctx):
