@@ -1,0 +1,221 @@
+"""TEST INFRASTRUCTURE ONLY -- plain reference of the learned proposal.
+
+A RealNVP-style flow of affine coupling layers on the 11 standardized
+parameters, the negative log-likelihood it is trained on, its gradient by
+plain back-propagation, and the Adam update (Kingma & Ba 2015).  FP64 numpy,
+one sample at a time conceptually (written with batch arrays for speed, no
+fusion).  The GPU library computes in BF16/FP32; this reference takes the
+same BF16-rounded weights and, with ``rnd=True``, rounds the three
+matrix-product inputs of every conditioner network to BF16 at the same
+points, so both sides evaluate the same function up to FP32 accumulation.
+Shares no code with the GPU library.
+
+Conventions (the paper gives none; these are the proposal's definition):
+  u = float32((theta - mu) / sigma); base density N(0, I_11).
+  8 layers.  Layer 2p conditions on C_p = {i : (i + 3p) mod 11 < 6} (6
+  entries) and transforms the other 5; layer 2p + 1 conditions on those 5
+  and transforms C_p.  Conditioner: x_C -> 256 (ReLU) -> 256 (ReLU) -> 2 n_T
+  (linear), first n_T outputs s_hat, last n_T outputs t;
+  s = 3 tanh(s_hat / 3).
+  Normalizing direction (u -> z), layers 0..7: y_T = x_T exp(s) + t,
+  y_C = x_C, log det += sum s.
+  log q_u(u) = -|z|^2 / 2 - (11/2) log(2 pi) + log det;
+  log q(theta) = log q_u(u) - sum log sigma.
+  Parameters per layer, y = x W + b: W1 [n_C, 256], b1 [256], W2 [256, 256],
+  b2 [256], W3 [256, 2 n_T], b3 [2 n_T]; stored flat in that order, layer
+  after layer (562264 numbers).
+"""
+import math
+
+import numpy as np
+
+D = 11
+HID = 256
+N_LAYERS = 8
+S_MAX = 3.0
+
+
+def cond_set(layer):
+    """Indices the layer conditions on (sorted)."""
+    p = layer // 2
+    c = [i for i in range(D) if (i + 3 * p) % D < 6]
+    if layer % 2:
+        c = [i for i in range(D) if i not in c]
+    return c
+
+
+def trans_set(layer):
+    c = cond_set(layer)
+    return [i for i in range(D) if i not in c]
+
+
+def shapes(layer):
+    nc, nt = len(cond_set(layer)), len(trans_set(layer))
+    return [("W1", (nc, HID)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)),
+            ("W3", (HID, 2 * nt)), ("b3", (2 * nt,))]
+
+
+def n_params():
+    return sum(int(np.prod(s)) for l in range(N_LAYERS) for _, s in shapes(l))
+
+
+def unflatten(flat):
+    """Flat parameter vector -> list of per-layer dicts (views)."""
+    out, o = [], 0
+    for l in range(N_LAYERS):
+        d = {}
+        for name, s in shapes(l):
+            n = int(np.prod(s))
+            d[name] = flat[o:o + n].reshape(s)
+            o += n
+        out.append(d)
+    assert o == flat.size
+    return out
+
+
+def bf16(x):
+    """Round to the nearest BF16 value (ties to even), returned as float64.
+    Works on the float32 bit pattern: keep the top 16 bits after adding
+    0x7FFF plus the lowest kept bit."""
+    f = np.asarray(x, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    r = ((b + 0x7FFF + lsb) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    nan = np.isnan(f)
+    if np.any(nan):
+        out = np.where(nan, np.nan, out)
+    return out
+
+
+def init_params(seed, scale_out=0.0):
+    """Float32 parameters: Kaiming-uniform hidden layers, output layer scaled
+    by scale_out (0 gives the identity map)."""
+    rng = np.random.default_rng(seed)
+    flat = np.zeros(n_params(), dtype=np.float32)
+    for d, l in zip(unflatten(flat), range(N_LAYERS)):
+        for name in ("W1", "W2"):
+            fan_in = d[name].shape[0]
+            bound = math.sqrt(6.0 / fan_in)
+            d[name][...] = rng.uniform(-bound, bound, size=d[name].shape)
+        d["W3"][...] = scale_out * rng.uniform(-1, 1, size=d["W3"].shape) / math.sqrt(HID)
+    return flat
+
+
+def _net(p, xc, rnd):
+    """Conditioner forward; returns (s, t, cache)."""
+    r = bf16 if rnd else (lambda a: np.asarray(a, dtype=np.float64))
+    W1, W2, W3 = (r(p[k]) for k in ("W1", "W2", "W3"))
+    b1, b2, b3 = (np.asarray(p[k], dtype=np.float64) for k in ("b1", "b2", "b3"))
+    a0 = r(xc)
+    a1 = r(np.maximum(a0 @ W1 + b1, 0.0))
+    a2 = r(np.maximum(a1 @ W2 + b2, 0.0))
+    o = a2 @ W3 + b3
+    nt = o.shape[1] // 2
+    th = np.tanh(o[:, :nt] / S_MAX)
+    s = S_MAX * th
+    t = o[:, nt:]
+    return s, t, (a0, a1, a2, W1, W2, W3, th)
+
+
+def forward(flat, u, rnd=True):
+    """Normalizing direction: u [n, 11] -> (z [n, 11], log det [n])."""
+    layers = unflatten(np.asarray(flat))
+    x = np.array(u, dtype=np.float64)
+    logdet = np.zeros(x.shape[0])
+    for l, p in enumerate(layers):
+        C, T = cond_set(l), trans_set(l)
+        s, t, _ = _net(p, x[:, C], rnd)
+        x[:, T] = x[:, T] * np.exp(s) + t
+        logdet += s.sum(axis=1)
+    return x, logdet
+
+
+def inverse(flat, z, rnd=True):
+    """Generative direction: z -> (u, log det of the normalizing map at u)."""
+    layers = unflatten(np.asarray(flat))
+    x = np.array(z, dtype=np.float64)
+    logdet = np.zeros(x.shape[0])
+    for l in reversed(range(N_LAYERS)):
+        C, T = cond_set(l), trans_set(l)
+        s, t, _ = _net(layers[l], x[:, C], rnd)
+        x[:, T] = (x[:, T] - t) * np.exp(-s)
+        logdet += s.sum(axis=1)
+    return x, logdet
+
+
+def log_prob_u(flat, u, rnd=True):
+    z, ld = forward(flat, u, rnd)
+    return -0.5 * (z * z).sum(axis=1) - 0.5 * D * math.log(2.0 * math.pi) + ld
+
+
+def standardize(theta, mu, sigma):
+    return ((np.asarray(theta, dtype=np.float64) - mu) / sigma).astype(np.float32).astype(np.float64)
+
+
+def log_prob(flat, theta, mu, sigma, rnd=True):
+    """log q(theta) of the proposal."""
+    return log_prob_u(flat, standardize(theta, mu, sigma), rnd) - np.log(sigma).sum()
+
+
+def nll_and_grad(flat, u, weight=None, rnd=True):
+    """NLL = sum_i w_i (|z_i|^2/2 + 11/2 log 2 pi - log det_i), w_i = 1/n by
+    default, and its gradient with respect to the flat parameters (the
+    BF16 roundings pass gradients unchanged)."""
+    layers = unflatten(np.asarray(flat))
+    n = u.shape[0]
+    w = np.full(n, 1.0 / n) if weight is None else np.asarray(weight, dtype=np.float64)
+    x = np.array(u, dtype=np.float64)
+    logdet = np.zeros(n)
+    tape = []
+    for l, p in enumerate(layers):
+        C, T = cond_set(l), trans_set(l)
+        xin = x.copy()
+        s, t, cache = _net(p, x[:, C], rnd)
+        x[:, T] = x[:, T] * np.exp(s) + t
+        logdet += s.sum(axis=1)
+        tape.append((xin, s, cache))
+    nll = float(np.sum(w * (0.5 * (x * x).sum(axis=1) + 0.5 * D * math.log(2.0 * math.pi) - logdet)))
+    grads = [dict() for _ in range(N_LAYERS)]
+    gy = w[:, None] * x                      # d NLL / d z
+    gld = -w                                 # d NLL / d log det
+    for l in reversed(range(N_LAYERS)):
+        C, T = cond_set(l), trans_set(l)
+        xin, s, (a0, a1, a2, W1, W2, W3, th) = tape[l]
+        es = np.exp(s)
+        gyT = gy[:, T]
+        gx = gy.copy()
+        gx[:, T] = gyT * es
+        gs = gyT * xin[:, T] * es + gld[:, None]
+        gt = gyT
+        gshat = gs * (1.0 - th * th)
+        go = np.concatenate([gshat, gt], axis=1)
+        g = grads[l]
+        g["W3"] = a2.T @ go
+        g["b3"] = go.sum(axis=0)
+        ga2 = (go @ W3.T) * (a2 > 0)
+        g["W2"] = a1.T @ ga2
+        g["b2"] = ga2.sum(axis=0)
+        ga1 = (ga2 @ W2.T) * (a1 > 0)
+        g["W1"] = a0.T @ ga1
+        g["b1"] = ga1.sum(axis=0)
+        gx[:, C] += ga1 @ W1.T
+        gy = gx
+    out = np.zeros(flat.size)
+    o = 0
+    for l in range(N_LAYERS):
+        for name, sh in shapes(l):
+            k = int(np.prod(sh))
+            out[o:o + k] = grads[l][name].ravel()
+            o += k
+    return nll, out
+
+
+def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (step number t >= 1) of p in place; returns (p, m, v)."""
+    m[...] = beta1 * m + (1.0 - beta1) * g
+    v[...] = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    p[...] = p - lr * mh / (np.sqrt(vh) + eps)
+    return p, m, v
