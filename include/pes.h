@@ -104,12 +104,21 @@ int pes_response(pes_ctx* ctx, const double* theta, int64_t B, double* out, void
  * theta (dev) [B][11], logl (dev) [B].  Requires pes_set_data. */
 int pes_loglike(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void* stream);
 
-/* Gradient of log L with respect to theta (forward-mode tangents of the
- * response, one parameter direction per pass; Sec. 2.3 uses reverse mode for
- * gradients, the values agree to rounding): logl (dev) [B] (may be NULL),
- * grad (dev) [B][11] in the units of theta.  Requires pes_set_data.
- * Unphysical samples: logl = -inf, grad = 0.  B <= 65535. */
+/* Gradient of log L with respect to theta (Sec. 2.3 differentiates the
+ * response in reverse mode): logl (dev) [B] (may be NULL), grad (dev) [B][11]
+ * in the units of theta.  Requires pes_set_data.  Unphysical samples:
+ * logl = -inf, grad = 0.  B <= 65535.  The method is chosen per context by
+ * pes_set_grad_method; both give the same values up to rounding. */
 int pes_grad(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double* grad, void* stream);
+
+/* Gradient method of pes_grad:
+ *   PES_GRAD_ADJOINT (default): hand-written reverse sweep per bin with the
+ *     forward values recomputed (no per-bin storage); adjoints of the walker
+ *     table contracted with its theta-derivatives.
+ *   PES_GRAD_FORWARD: forward-mode tangents, one parameter direction per pass.
+ * PES_EINVAL for another value. */
+enum { PES_GRAD_ADJOINT = 0, PES_GRAD_FORWARD = 1 };
+int pes_set_grad_method(pes_ctx* ctx, int method);
 
 /* Fisher matrix F_ij = <d_i h | d_j h> (Sec. 2.2, eqs. eq_ll_fisher and
  * eq_inner_product) from the forward-mode Jacobian of the A/E/T response, the
@@ -175,9 +184,61 @@ int pes_sampler_chain(pes_sampler* s, const double** chain);
 /* One proposal for half `half` (0 or 1) of the ensemble from the current
  * state: theta_prop (dev) [half size][11], log_qratio (dev) [half size]
  * (log q(theta|theta') - log q(theta'|theta); 0 for the symmetric DE move).
- * kind: PES_PROPOSE_DE. */
-enum { PES_PROPOSE_DE = 0 };
+ * kind: PES_PROPOSE_DE, or PES_PROPOSE_FLOW for the mixture set by
+ * pes_sampler_set_flow (PES_ESTATE without a flow). */
+enum { PES_PROPOSE_DE = 0, PES_PROPOSE_FLOW = 1 };
 int pes_propose(pes_sampler* s, int kind, int half, double* theta_prop, double* log_qratio, void* stream);
+
+/* ---- Learned proposal.  An affine-coupling normalizing flow q(theta) on the
+ * 11 parameters, trained on posterior samples and used as an independence
+ * Metropolis-Hastings proposal mixed with the DE move (the proposal is the
+ * sampler's choice, Sec. 2.2).  Definition: u = float((theta - mu) / sigma);
+ * 8 layers, layer 2p conditions on C_p = {i : (i + 3p) mod 11 < 6} and
+ * transforms the rest, layer 2p + 1 conditions on the rest and transforms
+ * C_p; conditioner networks n_C -> 256 (ReLU) -> 256 (ReLU) -> 2 n_T with
+ * outputs (s_hat, t), s = 3 tanh(s_hat / 3); normalizing map y_T = x_T e^s + t;
+ * base N(0, I); log q(theta) = log N(z) + sum s - sum log sigma.  Network
+ * products take BF16 operands (weights, inputs, hidden activations rounded to
+ * nearest even) with FP32 accumulation on the matrix cores; FP32 master
+ * weights; Adam (beta 0.9, 0.999, eps 1e-8).  Parameters: per layer W1
+ * [n_C][256], b1 [256], W2 [256][256], b2 [256], W3 [256][2 n_T], b3 [2 n_T]
+ * (y = x W + b), flat FP32 in that order, pes_flow_num_params() in total. */
+typedef struct pes_flow pes_flow;
+int pes_flow_create(uint64_t seed, pes_flow** out);   /* random init, near identity; mu 0, sigma 1 */
+int pes_flow_destroy(pes_flow* f);
+int64_t pes_flow_num_params(void);
+/* params (dev) FP32 [pes_flow_num_params()]; set also resets the Adam state. */
+int pes_flow_set_params(pes_flow* f, const float* params, void* stream);
+int pes_flow_get_params(pes_flow* f, float* params, void* stream);
+/* Standardization (host arrays [11]; sigma > 0, else PES_EINVAL). */
+int pes_flow_set_norm(pes_flow* f, const double* mu, const double* sigma);
+int pes_flow_get_norm(pes_flow* f, double* mu, double* sigma);
+/* log q(theta) for theta (dev) [n][11] -> logq (dev) [n]; z (dev) [n][11] or NULL. */
+int pes_flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double* logq, void* stream);
+/* theta = inverse map of z (dev) [n][11]; logdet (dev) [n] or NULL: sum s at theta. */
+int pes_flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, double* logdet, void* stream);
+/* Mean negative log-likelihood of the rows of theta (dev) [n][11] in the
+ * standardized space, -(1/n) sum log q_u(u_j), into nll (dev) [1] (may be
+ * NULL), and its gradient into grad (dev) FP32 [pes_flow_num_params()]. */
+int pes_flow_nll_grad(pes_flow* f, const double* theta, int64_t n, double* nll, float* grad, void* stream);
+/* One Adam update with grad (dev, FP32) or, when NULL, the last gradient. */
+int pes_flow_adam_step(pes_flow* f, const float* grad, float lr, void* stream);
+/* steps Adam updates on minibatches of `batch` rows of samples (dev) [n][11]
+ * (drawn with replacement; all rows in order when batch == n); standardize
+ * != 0 first sets mu, sigma to the samples' mean and standard deviation
+ * (synchronizes).  loss (dev) [steps] or NULL receives each step's NLL. */
+int pes_flow_fit(pes_flow* f, const double* samples, int64_t n, int64_t steps, int64_t batch, float lr,
+                 uint64_t seed, int standardize, double* loss, void* stream);
+const char* pes_flow_last_error(pes_flow* f);
+
+/* Use flow f in the sampler's steps: every walker of the half being updated
+ * takes the flow's independence proposal with probability p_flow (Philox
+ * purpose 19; latent draws purposes 20..30, Box-Muller) and the DE move
+ * otherwise; log q ratio = log q(current) - log q(proposal); a flow proposal
+ * outside [lo, hi) of a periodic parameter is rejected.  f = NULL returns to
+ * DE only.  Every prior must be free (PES_EINVAL with a fixed parameter).
+ * The flow must outlive its use; set it before pes_sampler_capture. */
+int pes_sampler_set_flow(pes_sampler* s, pes_flow* f, double p_flow);
 
 /* Philox4x32-10 (Salmon et al., SC'11) blocks for the counters
  * (c0 + i, c1, c2, c3), i = 0..n-1 (first word wraps modulo 2^32), with the

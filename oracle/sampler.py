@@ -16,6 +16,7 @@ W0, W1 = 0x9E3779B9, 0xBB67AE85
 MASK = 0xFFFFFFFF
 
 PURPOSE_PAIR, PURPOSE_GAMMA, PURPOSE_JITTER0, PURPOSE_ACCEPT = 0, 1, 2, 16
+PURPOSE_MIX, PURPOSE_LATENT0 = 19, 20
 
 
 def philox4x32_10(ctr, key):
@@ -71,11 +72,15 @@ def log_prior(th, prior):
 
 class DESampler:
     """Half-ensemble DE-MC: each step updates walkers [0, H) against [H, B),
-    then [H, B) against [0, H)."""
+    then [H, B) against [0, H).  With a flow (oracle.flow parameters, mu,
+    sigma, p_flow) every updated walker takes, with probability p_flow, the
+    flow's independence proposal instead (Metropolis-Hastings term
+    log q(current) - log q(proposal))."""
 
-    def __init__(self, loglike, prior, theta0, seed, tie_tol=1e-7):
+    def __init__(self, loglike, prior, theta0, seed, tie_tol=1e-7, flow=None):
         """tie_tol: |log u - Delta| below which an acceptance counts as a near tie
         (a decision another implementation could take the other way)."""
+        self.flow = flow
         self.loglike = loglike
         self.tie_tol = tie_tol
         self.prior = prior
@@ -121,15 +126,51 @@ class DESampler:
                         xk += hi - lo
                 x[k] = xk
             props.append(x)
-        return list(upd), np.array(props)
+        props = np.array(props)
+        qratio = np.zeros(len(props))
+        if self.flow is not None:
+            props, qratio = self._flow_mix(list(upd), step, props, qratio)
+        return list(upd), props, qratio
+
+    def _flow_mix(self, upd, step, props, qratio):
+        from oracle import flow as F
+        flat, mu, sigma, p_flow = self.flow
+        take, zs = [], []
+        for j, i in enumerate(upd):
+            r = draw(self.seed, i, step, PURPOSE_MIX)
+            if u01(r[0], r[1]) < p_flow:
+                z = []
+                for k in range(11):
+                    w = draw(self.seed, i, step, PURPOSE_LATENT0 + k)
+                    u1, u2 = u01(w[0], w[1]), u01(w[2], w[3])
+                    z.append(math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2))
+                take.append(j)
+                zs.append(z)
+        if not take:
+            return props, qratio
+        take = np.array(take)
+        z32 = np.array(zs, dtype=np.float32).astype(np.float64)   # the latent point enters in FP32
+        u, _ = F.inverse(flat, z32)
+        fprop = mu + sigma * u
+        lq_prop = F.log_prob(flat, fprop, mu, sigma)
+        lq_cur = F.log_prob(flat, self.theta[[upd[j] for j in take]], mu, sigma)
+        props = props.copy()
+        props[take] = fprop
+        qratio = qratio.copy()
+        qratio[take] = lq_cur - lq_prop
+        for jj, j in enumerate(take):
+            for k, (kind, lo, hi) in enumerate(self.prior):
+                if kind == "periodic" and not (lo <= fprop[jj, k] < hi):
+                    qratio[j] = -math.inf
+        return props, qratio
 
     def step(self):
         for half in (0, 1):
-            idx, props = self._propose(half)
+            idx, props, qratio = self._propose(half)
             Lp = np.asarray(self.loglike(props), dtype=np.float64)
             for j, i in enumerate(idx):
                 lp = log_prior(props[j], self.prior)
-                delta = (Lp[j] + lp) - (self.logl[i] + self.logp[i])
+                delta = (Lp[j] + lp) - (self.logl[i] + self.logp[i]) + qratio[j]
                 r = draw(self.seed, i, self.step_no * 2 + half, PURPOSE_ACCEPT)
                 lu = math.log(u01(r[0], r[1]))
                 if math.isfinite(delta) and abs(lu - delta) < self.tie_tol:

@@ -1,0 +1,300 @@
+// Reverse-mode (adjoint) gradient of the per-bin log-likelihood term,
+// written by hand (Sec. 2.3 differentiates the response in reverse mode).
+//
+// For one (walker, bin, detector) the term is
+//   l = sum_c D_c C_c - 1/2 sum_c W_c C_c^2
+// over the six real channel components C = (A'', E'', T'') of the folded
+// tables, so dl/dC_c = D_c - W_c C_c (the weighted residual).  That seed goes
+// back through A/E/T and the TDI combinations to the six complex links
+// (adj_links), then, for every active mode, through the link transfer
+// functions, the projections, the orbit at t_f, amplitude, phase and t_f to
+// the entries of the walker table (adj_unit).  Each table entry's adjoint is
+// contracted at once with its theta-derivatives (the tangent table of the
+// setup), so only 11 accumulators live across bins.  The forward values of a
+// unit are recomputed from the table, nothing is stored per bin.
+#pragma once
+#include "pes_eval.hpp"
+
+namespace pes {
+
+// g[J...] += cbar * d(entry)/d(theta_J) for the parameters J the entry depends
+// on (the setup makes every other derivative exactly zero).
+template <int... J>
+struct Deps {
+  __device__ __forceinline__ static void add(double* g, double cbar, const double* __restrict__ tan_row) {
+    ((g[J] = fma(cbar, tan_row[J], g[J])), ...);
+  }
+};
+// theta = (M, q, chi1, chi2, D_L, iota, phi_c, lambda, beta, psi, t_c)
+using DepM = Deps<0>;
+using DepQ = Deps<1>;
+using DepQPhi = Deps<1, 6>;
+using DepQChi = Deps<1, 2, 3>;
+using DepMQ = Deps<0, 1>;
+using DepMQChi = Deps<0, 1, 2, 3>;
+using DepMQD = Deps<0, 1, 4>;
+using DepIota = Deps<5>;
+using DepSky = Deps<7, 8>;
+using DepSkyPsi = Deps<7, 8, 9>;
+using DepTc = Deps<10>;
+
+// Link adjoints yb[arm][Fr, Fi, Br, Bi] from the channel values c and the
+// per-bin data D and weights (wA, wT).  Arm 0 carries y32 (F) / y23 (B),
+// arm 1 y13 / y31, arm 2 y21 / y12 (as in eval_channels_t).
+__device__ __forceinline__ void adj_links(const Chan& c, const double (&D)[6], double wA, double wT,
+                                          double zr, double zi, double (&yb)[3][4]) {
+  const double Ar = fma(-wA, c.ar, D[0]), Ai = fma(-wA, c.ai, D[1]);
+  const double wE = wA * (1.0 / 3.0);
+  const double Er = fma(-wE, c.er, D[2]), Ei = fma(-wE, c.ei, D[3]);
+  const double Tr = fma(-wT, c.tr, D[4]), Ti = fma(-wT, c.ti, D[5]);
+  // A'' = Z - X, E'' = X - 2Y + Z, T'' = X + Y + Z
+  const double Xr = (Er - Ar) + Tr, Xi = (Ei - Ai) + Ti;
+  const double Yr = fma(-2.0, Er, Tr), Yi = fma(-2.0, Ei, Ti);
+  const double Zr = (Ar + Er) + Tr, Zi = (Ai + Ei) + Ti;
+  // u = conj(z) * (adjoint of a z-multiplied difference)
+  const double uXr = fma(zr, Xr, zi * Xi), uXi = fma(zr, Xi, -(zi * Xr));
+  const double uYr = fma(zr, Yr, zi * Yi), uYi = fma(zr, Yi, -(zi * Yr));
+  const double uZr = fma(zr, Zr, zi * Zi), uZi = fma(zr, Zi, -(zi * Zr));
+  // X = y13 - y12 + z (y31 - y21); Y = y21 - y23 + z (y12 - y32);
+  // Z = y32 - y31 + z (y23 - y13)
+  yb[0][0] = Zr - uYr;  yb[0][1] = Zi - uYi;   // y32
+  yb[0][2] = uZr - Yr;  yb[0][3] = uZi - Yi;   // y23
+  yb[1][0] = Xr - uZr;  yb[1][1] = Xi - uZi;   // y13
+  yb[1][2] = uXr - Zr;  yb[1][3] = uXi - Zi;   // y31
+  yb[2][0] = Yr - uXr;  yb[2][1] = Yi - uXi;   // y21
+  yb[2][2] = uYr - Xr;  yb[2][3] = uYi - Xi;   // y12
+}
+
+// Adjoint of one arm's contribution y_F += sinc(a(1-kn)) G, y_B += sinc(a(1+kn)) G
+// with G = (E e) P, P = (aP (np^2 - nq^2), aC 2 np nq).  Accumulates the
+// adjoints of E, aP, aC and returns those of the arm's e = (c, s), kn, np, nq.
+template <bool LS>
+__device__ __forceinline__ void adj_arm(const double (&yb)[4], double a, double Er, double Ei, double c,
+                                        double s, double np, double nq, double kn, double aP, double aC,
+                                        double& Ebr, double& Ebi, double& aPb, double& aCb, double& cb,
+                                        double& sb, double& knb, double& npb, double& nqb) {
+  const double Qr = fma(Er, c, -(Ei * s)), Qi = fma(Er, s, Ei * c);
+  const double pp = fma(np, np, -(nq * nq)), pc = 2.0 * np * nq;
+  const double Pr = aP * pp, Pi = aC * pc;
+  const double Gr = fma(Qr, Pr, -(Qi * Pi)), Gi = fma(Qr, Pi, Qi * Pr);
+  const double bf = a * (1.0 - kn), bb = a * (1.0 + kn);
+  double sf, dsf, sbk, dsb;
+  if (LS) {
+    horner_d<1>(kSincLong, bf * bf, sf, dsf);
+    horner_d<1>(kSincLong, bb * bb, sbk, dsb);
+  } else {
+    horner_d<1>(kSincShort, bf * bf, sf, dsf);
+    horner_d<1>(kSincShort, bb * bb, sbk, dsb);
+  }
+  const double sfb = fma(yb[0], Gr, yb[1] * Gi), sbb = fma(yb[2], Gr, yb[3] * Gi);
+  const double Gbr = fma(sf, yb[0], sbk * yb[2]), Gbi = fma(sf, yb[1], sbk * yb[3]);
+  // d sinc(b)/db = 2 b P'(b^2)
+  knb = 2.0 * a * fma(sbb * bb, dsb, -(sfb * bf * dsf));
+  const double Qbr = fma(Gbr, Pr, Gbi * Pi), Qbi = fma(Gbi, Pr, -(Gbr * Pi));
+  const double Pbr = fma(Gbr, Qr, Gbi * Qi), Pbi = fma(Gbi, Qr, -(Gbr * Qi));
+  aPb = fma(Pbr, pp, aPb);
+  aCb = fma(Pbi, pc, aCb);
+  npb = 2.0 * fma(Pbr * aP, np, Pbi * aC * nq);
+  nqb = 2.0 * fma(Pbi * aC, np, -(Pbr * aP * nq));
+  Ebr = fma(Qbr, c, fma(Qbi, s, Ebr));
+  Ebi = fma(Qbi, c, fma(-Qbr, s, Ebi));
+  cb = fma(Qbr, Er, Qbi * Ei);
+  sb = fma(Qbi, Er, -(Qbr * Ei));
+}
+
+// Adjoint of mode j's unit of (walker, bin, detector) given the link adjoints
+// yb; accumulates d l / d theta into g.  wt: the walker's table; tn: its
+// tangent table [W_STRIDE][11]; ftc = f t_c mod 1.
+template <bool GEO, bool LS>
+__device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const double* __restrict__ tn, int det,
+                                         int j, double inv_year, double inv_ptq, const BinRegs& b, double a,
+                                         double ftc, const double (&yb)[3][4], double* g) {
+  const int M0 = W_MODE0 + j * W_MODE_STRIDE;
+  const int D0 = W_DET0 + det * W_DET_STRIDE;
+#define wm(i) wt[M0 + (i)]
+#define wd(i) wt[D0 + (i)]
+#define tm(i) (tn + (M0 + (i)) * kNParams)
+#define td(i) (tn + (D0 + (i)) * kNParams)
+  const double x = b.f * wm(M_FCI);
+  if (!(x < 1.0)) return;
+  // ---- forward values (the same arithmetic as eval_channels_t)
+  const double v = wm(M_CM) * b.f13;
+  const double w = wm(M_CMI) * b.fm13;
+  const double lnv = b.lnf * (1.0 / 3.0) + wm(M_LNCM);
+  const double w2 = w * w, w3 = w2 * w, w4 = w2 * w2, w5 = w4 * w, w6 = w4 * w2, w8 = w4 * w4;
+  const double v2 = v * v, lv = lnv * v, lw2 = lnv * w2;
+  double ph = wm(M_A4) * w;
+  ph = fma(wm(M_A3), w2, ph);
+  ph = fma(wm(M_A2), w3, ph);
+  ph = fma(wm(M_A0), w5, ph);
+  ph = fma(wm(M_B5), lnv, ph);
+  ph = fma(wm(M_A6), v, ph);
+  ph = fma(wm(M_B6), lv, ph);
+  ph = fma(wm(M_A7), v2, ph);
+  const double phase = ftc + (ph + wm(M_C0));
+  double tau = wm(M_T7) * w;
+  tau = fma(wm(M_T6), w2, tau);
+  tau = fma(wm(M_T6L), lw2, tau);
+  tau = fma(wm(M_T5), w3, tau);
+  tau = fma(wm(M_T4), w4, tau);
+  tau = fma(wm(M_T3), w5, tau);
+  tau = fma(wm(M_T2), w6, tau);
+  tau = fma(wm(M_T0), w8, tau);
+  const double amp0 = (fma(wm(M_AM2), v2, wm(M_AM1) * v) + wm(M_AM0)) * b.fm76;
+  double tap = 1.0, dtap = 0.0;   // taper and its derivative in x
+  if (x > 0.9) {
+    const double u = (x - 0.9) * 10.0;
+    tap = fma(-(u * u * u), fma(u, fma(6.0, u, -15.0), 10.0), 1.0);
+    const double um = u - 1.0;
+    dtap = -300.0 * (u * u) * (um * um);
+  }
+  const double amp = amp0 * tap;
+  const double aP = amp * wm(M_KP), aC = amp * wm(M_KC);
+  double sa, ca, ua, ub;
+  sincos_cycles(tau * inv_year + wd(D_AO), sa, ca);
+  if (GEO) {
+    sincos_cycles(tau * inv_ptq + wd(D_PO), ub, ua);
+  } else {
+    ua = fma(-2.0 * sa, sa, 1.0);
+    ub = 2.0 * sa * ca;
+  }
+#define PES_LIN(off) (fma(wd((off) + 3), sa, fma(wd((off) + 2), ca, fma(wd((off) + 1), ub, wd((off)) * ua))) + wd((off) + 4))
+  const double kn0 = PES_LIN(D_KN), kn1 = PES_LIN(D_KN + 5);
+  const double np0 = PES_LIN(D_NP), np1 = PES_LIN(D_NP + 5);
+  const double nq0 = PES_LIN(D_NQ), nq1 = PES_LIN(D_NQ + 5);
+  const double kd0 = PES_LIN(D_KD), kd1 = PES_LIN(D_KD + 5);
+#undef PES_LIN
+  const double kn2 = -(kn0 + kn1), np2 = -(np0 + np1), nq2 = -(nq0 + nq1);
+  const double kR = fma(wd(D_KR), ca, wd(D_KR + 1) * sa);
+  double sp, cp;
+  sincos_cycles(fma(b.f, kR, phase), sp, cp);
+  const double Er = cp, Ei = -sp;
+  double s0, c0, s1, c1;
+  const double pi_f = kPi * b.f;
+  if (LS) {
+    sincos_cycles(0.5 * b.f * kd0, s0, c0);
+    sincos_cycles(0.5 * b.f * kd1, s1, c1);
+  } else {
+    sincos_small(pi_f * kd0, s0, c0);
+    sincos_small(pi_f * kd1, s1, c1);
+  }
+  const double c2 = fma(c0, c1, -(s0 * s1)), s2 = -fma(s0, c1, c0 * s1);
+
+  // ---- reverse: arms
+  double Ebr = 0.0, Ebi = 0.0, aPb = 0.0, aCb = 0.0;
+  double cb0, sb0, knb0, npb0, nqb0, cb1, sb1, knb1, npb1, nqb1, cb2, sb2, knb2, npb2, nqb2;
+  adj_arm<LS>(yb[0], a, Er, Ei, c0, s0, np0, nq0, kn0, aP, aC, Ebr, Ebi, aPb, aCb, cb0, sb0, knb0, npb0, nqb0);
+  adj_arm<LS>(yb[1], a, Er, Ei, c1, s1, np1, nq1, kn1, aP, aC, Ebr, Ebi, aPb, aCb, cb1, sb1, knb1, npb1, nqb1);
+  adj_arm<LS>(yb[2], a, Er, Ei, c2, s2, np2, nq2, kn2, aP, aC, Ebr, Ebi, aPb, aCb, cb2, sb2, knb2, npb2, nqb2);
+  // the third arm follows from the other two
+  knb0 -= knb2;
+  knb1 -= knb2;
+  npb0 -= npb2;
+  npb1 -= npb2;
+  nqb0 -= nqb2;
+  nqb1 -= nqb2;
+  cb0 = fma(cb2, c1, fma(-sb2, s1, cb0));
+  sb0 = fma(-cb2, s1, fma(-sb2, c1, sb0));
+  cb1 = fma(cb2, c0, fma(-sb2, s0, cb1));
+  sb1 = fma(-cb2, s0, fma(-sb2, c0, sb1));
+  // arm phases pi f kd_t (radians)
+  const double kdb0 = pi_f * fma(sb0, c0, -(cb0 * s0));
+  const double kdb1 = pi_f * fma(sb1, c1, -(cb1 * s1));
+  // common phase (cycles): E = (cos, -sin)(2 pi Phi), Phi = f kR + phase
+  const double Phib = -kTwoPi * fma(Ebi, cp, Ebr * sp);
+  const double kRb = b.f * Phib;
+  // ---- projections: P = c0 ua + c1 ub + c2 ca + c3 sa + c4
+  double uab = 0.0, ubb = 0.0, cab = kRb * wd(D_KR), sab = kRb * wd(D_KR + 1);
+  DepSky::add(g, kRb * ca, td(D_KR));
+  DepSky::add(g, kRb * sa, td(D_KR + 1));
+#define PES_LIN_ADJ(off, pb, DEP)              \
+  {                                            \
+    uab = fma(pb, wd((off)), uab);             \
+    ubb = fma(pb, wd((off) + 1), ubb);         \
+    cab = fma(pb, wd((off) + 2), cab);         \
+    sab = fma(pb, wd((off) + 3), sab);         \
+    DEP::add(g, (pb) * ua, td((off)));         \
+    DEP::add(g, (pb) * ub, td((off) + 1));     \
+    DEP::add(g, (pb) * ca, td((off) + 2));     \
+    DEP::add(g, (pb) * sa, td((off) + 3));     \
+    DEP::add(g, (pb), td((off) + 4));          \
+  }
+  PES_LIN_ADJ(D_KN, knb0, DepSky)
+  PES_LIN_ADJ(D_KN + 5, knb1, DepSky)
+  PES_LIN_ADJ(D_NP, npb0, DepSkyPsi)
+  PES_LIN_ADJ(D_NP + 5, npb1, DepSkyPsi)
+  PES_LIN_ADJ(D_NQ, nqb0, DepSkyPsi)
+  PES_LIN_ADJ(D_NQ + 5, nqb1, DepSkyPsi)
+  PES_LIN_ADJ(D_KD, kdb0, DepSky)
+  PES_LIN_ADJ(D_KD + 5, kdb1, DepSky)
+#undef PES_LIN_ADJ
+  // ---- orbit at t_f
+  double taub = 0.0;
+  if (GEO) {
+    const double betab = kTwoPi * fma(ubb, ua, -(uab * ub));
+    taub = betab * inv_ptq;
+    DepTc::add(g, betab, td(D_PO));
+  } else {
+    sab = fma(-4.0 * sa, uab, fma(2.0 * ca, ubb, sab));
+    cab = fma(2.0 * sa, ubb, cab);
+  }
+  const double alphab = kTwoPi * fma(sab, ca, -(cab * sa));
+  taub = fma(alphab, inv_year, taub);
+  DepTc::add(g, alphab, td(D_AO));
+  // ---- amplitude, polarization, taper
+  DepIota::add(g, aPb * amp, tm(M_KP));
+  DepIota::add(g, aCb * amp, tm(M_KC));
+  const double ampb = fma(aPb, wm(M_KP), aCb * wm(M_KC));
+  const double xb = ampb * amp0 * dtap;
+  const double qa = ampb * tap * b.fm76;
+  DepMQD::add(g, qa, tm(M_AM0));
+  DepMQD::add(g, qa * v, tm(M_AM1));
+  DepMQD::add(g, qa * v2, tm(M_AM2));
+  double vb = qa * fma(2.0 * wm(M_AM2), v, wm(M_AM1));
+  DepM::add(g, xb * b.f, tm(M_FCI));
+  // ---- t_f - t_c
+  DepMQ::add(g, taub * w, tm(M_T7));
+  DepMQ::add(g, taub * w2, tm(M_T6));
+  DepMQ::add(g, taub * lw2, tm(M_T6L));
+  DepMQ::add(g, taub * w3, tm(M_T5));
+  DepMQChi::add(g, taub * w4, tm(M_T4));
+  DepMQChi::add(g, taub * w5, tm(M_T3));
+  DepMQ::add(g, taub * w6, tm(M_T2));
+  DepMQ::add(g, taub * w8, tm(M_T0));
+  // d tau / d w
+  double dtw = 8.0 * wm(M_T0) * w;
+  dtw = fma(dtw, w, 6.0 * wm(M_T2));
+  dtw = fma(dtw, w, 5.0 * wm(M_T3));
+  dtw = fma(dtw, w, 4.0 * wm(M_T4));
+  dtw = fma(dtw, w, 3.0 * wm(M_T5));
+  dtw = fma(dtw, w, 2.0 * fma(wm(M_T6L), lnv, wm(M_T6)));
+  dtw = fma(dtw, w, wm(M_T7));
+  double wb = taub * dtw;
+  double lnvb = taub * wm(M_T6L) * w2;
+  // ---- phase
+  const double phb = Phib;
+  DepTc::add(g, phb * b.f, tn + W_TC * kNParams);
+  DepQPhi::add(g, phb, tm(M_C0));
+  DepQ::add(g, phb * w5, tm(M_A0));
+  DepQ::add(g, phb * w3, tm(M_A2));
+  DepQChi::add(g, phb * w2, tm(M_A3));
+  DepQChi::add(g, phb * w, tm(M_A4));
+  DepQ::add(g, phb * lnv, tm(M_B5));
+  DepQ::add(g, phb * v, tm(M_A6));
+  DepQ::add(g, phb * lv, tm(M_B6));
+  DepQ::add(g, phb * v2, tm(M_A7));
+  const double dpw = fma(fma(5.0 * wm(M_A0), w2, 3.0 * wm(M_A2)), w2, fma(2.0 * wm(M_A3), w, wm(M_A4)));
+  wb = fma(phb, dpw, wb);
+  lnvb = fma(phb, fma(wm(M_B6), v, wm(M_B5)), lnvb);
+  vb = fma(phb, fma(2.0 * wm(M_A7), v, fma(wm(M_B6), lnv, wm(M_A6))), vb);
+  // ---- v = CM f^{1/3}, w = CMI f^{-1/3}, ln v = LNCM + ln(f)/3
+  DepM::add(g, vb * b.f13, tm(M_CM));
+  DepM::add(g, wb * b.fm13, tm(M_CMI));
+  DepM::add(g, lnvb, tm(M_LNCM));
+#undef wm
+#undef wd
+#undef tm
+#undef td
+}
+
+}  // namespace pes

@@ -10,6 +10,7 @@
 
 #include "../../include/pes.h"
 #include "pes_launch.hpp"
+#include "pes_flow.hpp"
 #include "pes_sampler.hpp"
 
 using namespace pes;
@@ -42,6 +43,7 @@ struct pes_ctx {
   int bpc = 0;              // resident blocks per CU requested (0: occupancy limit)
   int occ[3] = {1, 1, 1};   // occupancy limit per bins-per-lane variant
   int tile = 256;
+  int grad_method = PES_GRAD_ADJOINT;
   int ntmax = 0;            // tiles per walker at the current tile size
   int ntmax_alloc = 0;      // tiles at the smallest tile (partial-buffer sizing)
   // workspace
@@ -486,7 +488,13 @@ int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* g
   hipStream_t s = (hipStream_t)stream;
   PES_HIP(c, launch_setup_tan(theta, B, c->wtab, c->wtan, c->ntiles, setup_args(c), s));
   PES_HIP(c, launch_grad(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, c->dd, jac_args(c, B, kGradTile),
-                         c->long_sinc, logl, grad, s));
+                         c->long_sinc, c->grad_method == PES_GRAD_ADJOINT, logl, grad, s));
+  return PES_OK;
+}
+
+int pes_set_grad_method(pes_ctx* c, int method) {
+  if (!c || (method != PES_GRAD_ADJOINT && method != PES_GRAD_FORWARD)) return PES_EINVAL;
+  c->grad_method = method;
   return PES_OK;
 }
 
@@ -516,6 +524,10 @@ struct pes_sampler {
   double *prop = nullptr, *prop_logl = nullptr, *qratio = nullptr, *chain = nullptr;
   int64_t* accepts = nullptr;
   uint64_t* step = nullptr;   // [2]: current step, next step
+  // learned proposal (mixture with DE)
+  pes_flow* flow = nullptr;
+  double p_flow = 0.0;
+  double *zbuf = nullptr, *fprop = nullptr, *lq_prop = nullptr, *lq_cur = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -537,11 +549,30 @@ DeArgs de_args(const pes_sampler* s, int half) {
   return a;
 }
 
+// Proposals for one half into s->prop / s->qratio: DE, then (with a flow)
+// the per-walker mixture with the flow's independence proposal.
+int sampler_propose(pes_sampler* s, const DeArgs& a, bool use_flow, double* prop, double* qratio,
+                    hipStream_t st) {
+  PES_HIP(s->ctx, launch_de_propose(s->theta, prop, qratio, s->step, a, st));
+  if (!use_flow) return PES_OK;
+  PES_HIP(s->ctx, launch_flow_latent(s->zbuf, s->step, a, st));
+  int rc = flow_inverse(s->flow, s->zbuf, a.n_upd, s->fprop, nullptr, st);
+  if (rc == PES_OK) rc = flow_forward(s->flow, s->fprop, a.n_upd, nullptr, s->lq_prop, st);
+  if (rc == PES_OK) rc = flow_forward(s->flow, s->theta + 11 * a.upd0, a.n_upd, nullptr, s->lq_cur, st);
+  if (rc != PES_OK) {
+    snprintf(s->ctx->err, sizeof(s->ctx->err), "flow proposal: %s", pes_flow_last_error(s->flow));
+    return rc;
+  }
+  PES_HIP(s->ctx, launch_flow_mix(s->fprop, s->lq_prop, s->lq_cur, prop, qratio, s->step, a, s->p_flow, st));
+  return PES_OK;
+}
+
 int sampler_one_step(pes_sampler* s, hipStream_t st) {
   for (int half = 0; half < 2; ++half) {
     const DeArgs a = de_args(s, half);
-    PES_HIP(s->ctx, launch_de_propose(s->theta, s->prop, s->qratio, s->step, a, st));
-    const int rc = pes_loglike(s->ctx, s->prop, a.n_upd, s->prop_logl, st);
+    int rc = sampler_propose(s, a, s->flow != nullptr, s->prop, s->qratio, st);
+    if (rc != PES_OK) return rc;
+    rc = pes_loglike(s->ctx, s->prop, a.n_upd, s->prop_logl, st);
     if (rc != PES_OK) return rc;
     PES_HIP(s->ctx, launch_accept(s->theta, s->logl, s->logp, s->prop, s->prop_logl, s->qratio, s->accepts,
                                   s->step, a, st));
@@ -562,6 +593,10 @@ void sampler_free(pes_sampler* s) {
   (void)hipFree(s->chain);
   (void)hipFree(s->accepts);
   (void)hipFree(s->step);
+  (void)hipFree(s->zbuf);
+  (void)hipFree(s->fprop);
+  (void)hipFree(s->lq_prop);
+  (void)hipFree(s->lq_cur);
 }
 
 }  // namespace
@@ -719,9 +754,35 @@ int pes_sampler_chain(pes_sampler* s, const double** chain) {
 }
 
 int pes_propose(pes_sampler* s, int kind, int half, double* theta_prop, double* log_qratio, void* stream) {
-  if (!s || !theta_prop || !log_qratio || (half != 0 && half != 1) || kind != PES_PROPOSE_DE) return PES_EINVAL;
-  PES_HIP(s->ctx, launch_de_propose(s->theta, theta_prop, log_qratio, s->step, de_args(s, half),
-                                    (hipStream_t)stream));
+  if (!s || !theta_prop || !log_qratio || (half != 0 && half != 1) ||
+      (kind != PES_PROPOSE_DE && kind != PES_PROPOSE_FLOW))
+    return PES_EINVAL;
+  if (kind == PES_PROPOSE_FLOW && !s->flow) return PES_ESTATE;
+  return sampler_propose(s, de_args(s, half), kind == PES_PROPOSE_FLOW, theta_prop, log_qratio,
+                         (hipStream_t)stream);
+}
+
+int pes_sampler_set_flow(pes_sampler* s, pes_flow* f, double p_flow) {
+  if (!s || (f && !(p_flow >= 0.0 && p_flow <= 1.0))) return PES_EINVAL;
+  if (!f) {
+    s->flow = nullptr;
+    s->p_flow = 0.0;
+    return PES_OK;
+  }
+  for (int k = 0; k < kNParams; ++k)
+    if (s->prior.kind[k] == PES_PRIOR_FIXED) return PES_EINVAL;
+  const int64_t H = s->H1;
+  if (!s->zbuf) {
+    if (hipMalloc(&s->zbuf, sizeof(double) * H * 11) != hipSuccess ||
+        hipMalloc(&s->fprop, sizeof(double) * H * 11) != hipSuccess ||
+        hipMalloc(&s->lq_prop, sizeof(double) * H) != hipSuccess ||
+        hipMalloc(&s->lq_cur, sizeof(double) * H) != hipSuccess)
+      return PES_ENOMEM;
+  }
+  const int rc = flow_reserve(f, H);
+  if (rc != PES_OK) return rc;
+  s->flow = f;
+  s->p_flow = p_flow;
   return PES_OK;
 }
 

@@ -1,0 +1,877 @@
+// Learned proposal on the device: an affine-coupling normalizing flow on the
+// 11 standardized parameters (8 coupling layers, conditioner networks
+// n_C -> 256 -> 256 -> 2 n_T), evaluated and trained with BF16 operands and
+// FP32 accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16), the
+// coupling arithmetic in FP32, and Adam on FP32 master weights.  Its samples
+// feed an independence Metropolis-Hastings proposal whose acceptance uses the
+// exact FP64 likelihood; Sec. 2.2 leaves the proposal to the sampler.
+//
+// Conventions (the flow's definition): u = float((theta - mu) / sigma);
+// layer 2p conditions on C_p = {i : (i + 3p) mod 11 < 6} and transforms the
+// other 5 coordinates, layer 2p + 1 conditions on those 5 and transforms C_p;
+// s = 3 tanh(s_hat / 3); normalizing direction y_T = x_T e^s + t, log det +=
+// sum s; base N(0, I).  Parameters per layer (y = x W + b): W1 [n_C][256],
+// b1, W2 [256][256], b2, W3 [256][2 n_T], b3, flat in that order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <random>
+
+#include "../../include/pes.h"
+#include "pes_flow.hpp"
+
+namespace pes {
+namespace fl {
+
+constexpr int kD = 11;
+constexpr int kHid = 256;
+constexpr int kLayers = 8;
+constexpr int kPad = 32;            // padded conditioner input and output width
+constexpr int kTensors = 6 * kLayers;
+constexpr int kLayerW = kPad * kHid + kHid * kHid + kHid * kPad;   // bf16 weights per layer
+constexpr int kLayerB = kHid + kHid + kPad;                          // padded biases per layer
+constexpr float kSMax = 3.0f;
+constexpr int64_t kRowAlign = 64;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct LayerSpec {
+  int nc, nt;
+  int cond[6], trans[6];
+};
+
+struct TensorDesc {
+  int64_t off;    // in the flat FP32 parameters
+  int rows, cols;
+  int64_t woff;   // bf16 copy (weights) or -1
+  int64_t boff;   // padded FP32 copy (biases) or -1
+  int ldw;
+};
+struct TensorTable {
+  TensorDesc t[kTensors];
+};
+
+struct Norm {
+  double mu[kD], sigma[kD];
+};
+
+// ------------------------------------------------------------------ GEMM
+// C[m][n] = sum_k A(m, k) B(n, k) with BF16 operands and FP32 accumulation.
+// A(m, k) = A[m lda + k] (A_ROW) or A[k lda + m]; B(n, k) = B[n ldb + k]
+// (B_ROW) or B[k ldb + n].  M, N, K are multiples of 32.  A 32 x 32 output
+// tile per block of four waves; each wave owns a 16 x 16 tile and issues one
+// 16x16x32 matrix-core operation per 32-deep slab staged through LDS (both
+// operand layouts are loaded coalesced and transposed in LDS as needed).
+enum : int { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_RELU_BF16 = 2, EPI_MASK = 3 };
+
+struct GemmArgs {
+  const __bf16* A;
+  int64_t lda;
+  const __bf16* B;
+  int64_t ldb;
+  int M, N, K;
+  const float* bias;     // [N]
+  const __bf16* mask;    // EPI_MASK: zero where mask <= 0
+  int64_t ldm;
+  float* C;              // FP32 out
+  int64_t ldc;
+  __bf16* Cb;            // BF16 out
+  int64_t ldcb;
+  int m_valid, n_valid;  // EPI_F32: rows / columns written
+};
+
+template <bool A_ROW, bool B_ROW, int EPI>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[32][40];   // [m][k], rows padded to 80 bytes
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[32][40];   // [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const int wm = (wv >> 1) * 16, wn = (wv & 1) * 16;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int t = tid & 127, r = t >> 2, c = (t & 3) * 8;
+  for (int k0 = 0; k0 < g.K; k0 += 32) {
+    if (tid < 128) {
+      if (A_ROW) {
+        *(bf16x8*)&As[r][c] = *(const bf16x8*)(g.A + (int64_t)(m0 + r) * g.lda + k0 + c);
+      } else {   // r indexes k, c indexes m
+        const bf16x8 v = *(const bf16x8*)(g.A + (int64_t)(k0 + r) * g.lda + m0 + c);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[c + e][r] = v[e];
+      }
+    } else {
+      if (B_ROW) {
+        *(bf16x8*)&Bs[r][c] = *(const bf16x8*)(g.B + (int64_t)(n0 + r) * g.ldb + k0 + c);
+      } else {
+        const bf16x8 v = *(const bf16x8*)(g.B + (int64_t)(k0 + r) * g.ldb + n0 + c);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[c + e][r] = v[e];
+      }
+    }
+    __syncthreads();
+    // operand lanes: A[i = lane % 16][k = 8 (lane / 16) + e], B likewise by column
+    const bf16x8 a = *(const bf16x8*)&As[wm + (lane & 15)][8 * (lane >> 4)];
+    const bf16x8 b = *(const bf16x8*)&Bs[wn + (lane & 15)][8 * (lane >> 4)];
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    __syncthreads();
+  }
+  // result lanes: element e of lane l is (row 4 (l / 16) + e, column l % 16)
+  const int n = n0 + wn + (lane & 15);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int m = m0 + wm + 4 * (lane >> 4) + e;
+    float v = acc[e];
+    if (EPI == EPI_F32) {
+      if (m < g.m_valid && n < g.n_valid) g.C[(int64_t)m * g.ldc + n] = v;
+    } else if (EPI == EPI_BIAS_F32) {
+      g.C[(int64_t)m * g.ldc + n] = v + g.bias[n];
+    } else if (EPI == EPI_BIAS_RELU_BF16) {
+      v = fmaxf(v + g.bias[n], 0.0f);
+      g.Cb[(int64_t)m * g.ldcb + n] = (__bf16)v;
+    } else {   // EPI_MASK
+      if (!((float)g.mask[(int64_t)m * g.ldm + n] > 0.0f)) v = 0.0f;
+      g.C[(int64_t)m * g.ldc + n] = v;
+      g.Cb[(int64_t)m * g.ldcb + n] = (__bf16)v;
+    }
+  }
+}
+
+template <bool AR, bool BR, int EPI>
+hipError_t gemm(const GemmArgs& g, hipStream_t s) {
+  if (g.M % 32 || g.N % 32 || g.K % 32 || g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gemm_kernel<AR, BR, EPI>), dim3(g.N / 32, g.M / 32), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ elementwise
+__global__ void standardize_kernel(const double* __restrict__ theta, int64_t n, int64_t Mp, Norm nm,
+                                   float* __restrict__ x, float* __restrict__ logdet) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Mp * kD) return;
+  const int64_t j = i / kD;
+  const int k = (int)(i - j * kD);
+  x[i] = j < n ? (float)((theta[i] - nm.mu[k]) / nm.sigma[k]) : 0.0f;
+  if (k == 0) logdet[j] = 0.0f;
+}
+
+__global__ void load_latent_kernel(const double* __restrict__ z, int64_t n, int64_t Mp, float* __restrict__ x,
+                                   float* __restrict__ logdet) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Mp * kD) return;
+  const int64_t j = i / kD;
+  x[i] = j < n ? (float)z[i] : 0.0f;
+  if (i - j * kD == 0) logdet[j] = 0.0f;
+}
+
+__global__ void gather_kernel(const float* __restrict__ x, __bf16* __restrict__ xc, int64_t Mp, LayerSpec ls) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Mp * kPad) return;
+  const int64_t j = i / kPad;
+  const int c = (int)(i - j * kPad);
+  float v = 0.0f;
+  if (c < ls.nc) v = x[j * kD + ls.cond[c]];
+  xc[i] = (__bf16)v;
+}
+
+// One coupling layer on the rows: forward y_T = x_T e^s + t or inverse
+// x_T = (y_T - t) e^-s; logdet += sum s (the normalizing map's).  xin (may be
+// null) receives the rows before the update.
+__global__ void couple_kernel(float* __restrict__ x, const float* __restrict__ O, float* __restrict__ logdet,
+                              float* __restrict__ xin, int64_t Mp, LayerSpec ls, int inverse) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Mp) return;
+  float* xr = x + j * kD;
+  if (xin)
+    for (int k = 0; k < kD; ++k) xin[j * kD + k] = xr[k];
+  const float* o = O + j * kPad;
+  float ld = 0.0f;
+  for (int q = 0; q < ls.nt; ++q) {
+    const float s = kSMax * tanhf(o[q] / kSMax);
+    const float t = o[ls.nt + q];
+    const int idx = ls.trans[q];
+    xr[idx] = inverse ? (xr[idx] - t) * expf(-s) : fmaf(xr[idx], expf(s), t);
+    ld += s;
+  }
+  logdet[j] += ld;
+}
+
+// log q(theta) = -|z|^2/2 - (11/2) log 2 pi + log det - sum log sigma.
+__global__ void logq_kernel(const float* __restrict__ z, const float* __restrict__ logdet, int64_t n,
+                            double lsig, double* __restrict__ logq, double* __restrict__ zout) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double q = 0.0;
+  for (int k = 0; k < kD; ++k) {
+    const double v = (double)z[j * kD + k];
+    q = fma(v, v, q);
+    if (zout) zout[j * kD + k] = v;
+  }
+  logq[j] = -0.5 * q - 0.5 * kD * 1.8378770664093454836 + (double)logdet[j] - lsig;
+}
+
+__global__ void unstandardize_kernel(const float* __restrict__ x, const float* __restrict__ logdet, int64_t n,
+                                     Norm nm, double* __restrict__ theta, double* __restrict__ ld_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * kD) return;
+  const int64_t j = i / kD;
+  const int k = (int)(i - j * kD);
+  theta[i] = fma(nm.sigma[k], (double)x[i], nm.mu[k]);
+  if (ld_out && k == 0) ld_out[j] = (double)logdet[j];
+}
+
+// ------------------------------------------------------------------ training
+// Seeds the backward pass of NLL = (1/n) sum_j (|z_j|^2/2 + 11/2 log 2 pi - logdet_j):
+// dNLL/dz = z / n, and the per-row NLL terms.
+__global__ void nll_seed_kernel(const float* __restrict__ z, const float* __restrict__ logdet, int64_t n,
+                                int64_t Mp, float* __restrict__ gy, double* __restrict__ rowv) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Mp) return;
+  const float w = j < n ? 1.0f / (float)n : 0.0f;
+  double q = 0.0;
+  for (int k = 0; k < kD; ++k) {
+    const float v = z[j * kD + k];
+    gy[j * kD + k] = w * v;
+    q = fma((double)v, (double)v, q);
+  }
+  rowv[j] = j < n ? (0.5 * q + 0.5 * kD * 1.8378770664093454836 - (double)logdet[j]) / (double)n : 0.0;
+}
+
+// Ordered sum of n doubles by one block (fixed order: bitwise repeatable).
+__global__ void __launch_bounds__(256) sum_rows_kernel(const double* __restrict__ v, int64_t n,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += v[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Backward of one coupling layer (normalizing direction).  gy: d/dy of the
+// layer output; gx receives d/dx of its input except the conditioner path
+// through the network (added later); gO: d/d(network output).
+__global__ void couple_bwd_kernel(const float* __restrict__ xin, const float* __restrict__ O,
+                                  const float* __restrict__ gy, float* __restrict__ gx, float* __restrict__ gOf,
+                                  __bf16* __restrict__ gOb, int64_t n, int64_t Mp, LayerSpec ls) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Mp) return;
+  const float gld = j < n ? -1.0f / (float)n : 0.0f;
+  for (int k = 0; k < kD; ++k) gx[j * kD + k] = gy[j * kD + k];
+  const float* o = O + j * kPad;
+  float* go = gOf + j * kPad;
+  for (int q = 0; q < kPad; ++q) go[q] = 0.0f;
+  for (int q = 0; q < ls.nt; ++q) {
+    const int idx = ls.trans[q];
+    const float th = tanhf(o[q] / kSMax);
+    const float es = expf(kSMax * th);
+    const float g = gy[j * kD + idx];
+    gx[j * kD + idx] = g * es;
+    const float gs = fmaf(g * xin[j * kD + idx], es, gld);
+    go[q] = gs * (1.0f - th * th);
+    go[ls.nt + q] = g;
+  }
+  for (int q = 0; q < kPad; ++q) gOb[j * kPad + q] = (__bf16)go[q];
+}
+
+// out[c] = sum_rows X[r][c] for c < ncols (one block per column, fixed order).
+__global__ void __launch_bounds__(256) colsum_kernel(const float* __restrict__ X, int64_t ldx, int64_t M,
+                                                     float* __restrict__ out) {
+  __shared__ float sh[256];
+  const int c = blockIdx.x;
+  float s = 0.0f;
+  for (int64_t r = threadIdx.x; r < M; r += 256) s += X[r * ldx + c];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = sh[0];
+}
+
+__global__ void scatter_cond_kernel(const float* __restrict__ dxc, float* __restrict__ gx, int64_t Mp,
+                                    LayerSpec ls) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Mp) return;
+  for (int c = 0; c < ls.nc; ++c) gx[j * kD + ls.cond[c]] += dxc[j * kPad + c];
+}
+
+// Adam (update != 0) and the refresh of the BF16 weight and padded bias copies.
+__global__ void adam_kernel(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ m1,
+                            float* __restrict__ m2, __bf16* __restrict__ wb, float* __restrict__ bp,
+                            TensorTable tt, int update, float lr, float b1, float b2, float c1, float c2,
+                            float eps) {
+  const TensorDesc d = tt.t[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)d.rows * d.cols) return;
+  const int64_t p = d.off + i;
+  float w = P[p];
+  if (update) {
+    const float g = G[p];
+    const float a = fmaf(b1, m1[p], (1.0f - b1) * g);
+    const float v = fmaf(b2, m2[p], (1.0f - b2) * g * g);
+    m1[p] = a;
+    m2[p] = v;
+    w -= lr * (a * c1) / (sqrtf(v * c2) + eps);
+    P[p] = w;
+  }
+  if (d.woff >= 0) {
+    const int64_t r = i / d.cols, c = i - r * d.cols;
+    wb[d.woff + r * d.ldw + c] = (__bf16)w;
+  } else {
+    bp[d.boff + i] = w;
+  }
+}
+
+// Minibatch of rows drawn with replacement (SplitMix64 of (seed, step, row),
+// Steele, Lea & Flood, OOPSLA 2014), or all rows in order when batch == n.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ void batch_kernel(const double* __restrict__ samples, int64_t n, int64_t batch, uint64_t seed,
+                             uint64_t step, double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= batch) return;
+  int64_t src = j;
+  if (batch != n) {
+    const uint64_t h = splitmix64(seed ^ splitmix64((step << 32) ^ (uint64_t)j));
+    src = (int64_t)(h % (uint64_t)n);
+  }
+  for (int k = 0; k < kD; ++k) out[j * kD + k] = samples[src * kD + k];
+}
+
+// Per-coordinate mean and standard deviation of n rows (one block per
+// coordinate, two passes, fixed order).
+__global__ void __launch_bounds__(256) moments_kernel(const double* __restrict__ x, int64_t n,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) s += x[r * kD + k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double mean = sh[0] / (double)n;
+  __syncthreads();
+  s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) {
+    const double d = x[r * kD + k] - mean;
+    s = fma(d, d, s);
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[k] = mean;
+    out[kD + k] = sqrt(sh[0] / (double)n);
+  }
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace fl
+}  // namespace pes
+
+using namespace pes::fl;
+
+struct pes_flow {
+  LayerSpec L[kLayers];
+  TensorTable tt;
+  int64_t np = 0;
+  float *P = nullptr, *G = nullptr, *m1 = nullptr, *m2 = nullptr;
+  __bf16* wb = nullptr;   // [layer][kLayerW]: W1 [32][256], W2 [256][256], W3 [256][32]
+  float* bp = nullptr;    // [layer][kLayerB]: b1 [256], b2 [256], b3 [32]
+  Norm nm;
+  double lsig = 0.0;
+  int64_t t_adam = 0;
+  // workspace (rows padded to a multiple of 64)
+  int64_t cap = 0;
+  float *x = nullptr, *logdet = nullptr, *xin = nullptr, *O = nullptr;
+  __bf16 *Xc = nullptr, *H1 = nullptr, *H2 = nullptr;
+  float *gy = nullptr, *gx = nullptr, *gOf = nullptr, *dpf = nullptr, *dXc = nullptr;
+  __bf16 *gOb = nullptr, *dpb = nullptr;
+  double *rowv = nullptr, *batchbuf = nullptr, *mom = nullptr;
+  char err[256] = {0};
+};
+
+namespace {
+
+#define FL_HIP(f, expr)                                                          \
+  do {                                                                           \
+    const hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess) {                                                      \
+      snprintf((f)->err, sizeof((f)->err), "%s: %s", #expr, hipGetErrorString(e_)); \
+      return PES_EHIP;                                                           \
+    }                                                                            \
+  } while (0)
+
+int64_t pad_rows(int64_t n) { return std::max<int64_t>(kRowAlign, (n + kRowAlign - 1) / kRowAlign * kRowAlign); }
+
+void free_ws(pes_flow* f) {
+  void* ps[] = {f->x, f->logdet, f->xin, f->O, f->Xc, f->H1, f->H2, f->gy, f->gx,
+                f->gOf, f->dpf, f->dXc, f->gOb, f->dpb, f->rowv, f->batchbuf};
+  for (void* p : ps) (void)hipFree(p);
+  f->x = f->logdet = f->xin = f->O = f->gy = f->gx = f->gOf = f->dpf = f->dXc = nullptr;
+  f->Xc = f->H1 = f->H2 = f->gOb = f->dpb = nullptr;
+  f->rowv = f->batchbuf = nullptr;
+  f->cap = 0;
+}
+
+int ensure_ws(pes_flow* f, int64_t n) {
+  const int64_t Mp = pad_rows(n);
+  if (Mp <= f->cap) return PES_OK;
+  free_ws(f);
+  const int64_t L = kLayers;
+  bool ok = hipMalloc(&f->x, sizeof(float) * Mp * kD) == hipSuccess &&
+            hipMalloc(&f->logdet, sizeof(float) * Mp) == hipSuccess &&
+            hipMalloc(&f->xin, sizeof(float) * L * Mp * kD) == hipSuccess &&
+            hipMalloc(&f->O, sizeof(float) * L * Mp * kPad) == hipSuccess &&
+            hipMalloc(&f->Xc, sizeof(__bf16) * L * Mp * kPad) == hipSuccess &&
+            hipMalloc(&f->H1, sizeof(__bf16) * L * Mp * kHid) == hipSuccess &&
+            hipMalloc(&f->H2, sizeof(__bf16) * L * Mp * kHid) == hipSuccess &&
+            hipMalloc(&f->gy, sizeof(float) * Mp * kD) == hipSuccess &&
+            hipMalloc(&f->gx, sizeof(float) * Mp * kD) == hipSuccess &&
+            hipMalloc(&f->gOf, sizeof(float) * Mp * kPad) == hipSuccess &&
+            hipMalloc(&f->gOb, sizeof(__bf16) * Mp * kPad) == hipSuccess &&
+            hipMalloc(&f->dpf, sizeof(float) * 2 * Mp * kHid) == hipSuccess &&
+            hipMalloc(&f->dpb, sizeof(__bf16) * 2 * Mp * kHid) == hipSuccess &&
+            hipMalloc(&f->dXc, sizeof(float) * Mp * kPad) == hipSuccess &&
+            hipMalloc(&f->rowv, sizeof(double) * Mp) == hipSuccess &&
+            hipMalloc(&f->batchbuf, sizeof(double) * Mp * kD) == hipSuccess;
+  if (!ok) {
+    free_ws(f);
+    snprintf(f->err, sizeof(f->err), "flow workspace for %lld rows failed", (long long)Mp);
+    return PES_ENOMEM;
+  }
+  f->cap = Mp;
+  return PES_OK;
+}
+
+const __bf16* W1b(const pes_flow* f, int l) { return f->wb + (int64_t)l * kLayerW; }
+const __bf16* W2b(const pes_flow* f, int l) { return f->wb + (int64_t)l * kLayerW + kPad * kHid; }
+const __bf16* W3b(const pes_flow* f, int l) { return f->wb + (int64_t)l * kLayerW + kPad * kHid + kHid * kHid; }
+const float* b1p(const pes_flow* f, int l) { return f->bp + (int64_t)l * kLayerB; }
+const float* b2p(const pes_flow* f, int l) { return f->bp + (int64_t)l * kLayerB + kHid; }
+const float* b3p(const pes_flow* f, int l) { return f->bp + (int64_t)l * kLayerB + 2 * kHid; }
+
+// Conditioner network of layer l on the rows of x: Xc -> H1 -> H2 -> O.
+int net_forward(pes_flow* f, int l, int64_t Mp, int slot, hipStream_t s) {
+  const int64_t so = (int64_t)slot * Mp;
+  __bf16* Xc = f->Xc + so * kPad;
+  __bf16* H1 = f->H1 + so * kHid;
+  __bf16* H2 = f->H2 + so * kHid;
+  float* O = f->O + so * kPad;
+  hipLaunchKernelGGL(gather_kernel, dim3(nblk(Mp * kPad, 256)), dim3(256), 0, s, f->x, Xc, Mp, f->L[l]);
+  GemmArgs g;
+  memset(&g, 0, sizeof(g));
+  g.M = (int)Mp;
+  // H1 = relu(Xc W1 + b1): B(n = out, k = in) = W1[in][out]
+  g.A = Xc; g.lda = kPad; g.B = W1b(f, l); g.ldb = kHid; g.N = kHid; g.K = kPad;
+  g.bias = b1p(f, l); g.Cb = H1; g.ldcb = kHid;
+  FL_HIP(f, (gemm<true, false, EPI_BIAS_RELU_BF16>(g, s)));
+  g.A = H1; g.lda = kHid; g.B = W2b(f, l); g.ldb = kHid; g.N = kHid; g.K = kHid;
+  g.bias = b2p(f, l); g.Cb = H2; g.ldcb = kHid;
+  FL_HIP(f, (gemm<true, false, EPI_BIAS_RELU_BF16>(g, s)));
+  g.A = H2; g.lda = kHid; g.B = W3b(f, l); g.ldb = kPad; g.N = kPad; g.K = kHid;
+  g.bias = b3p(f, l); g.C = O; g.ldc = kPad; g.Cb = nullptr;
+  FL_HIP(f, (gemm<true, false, EPI_BIAS_F32>(g, s)));
+  return PES_OK;
+}
+
+// Normalizing pass over f->x (standardized rows); store: keep every layer's
+// input and activations for the backward pass.
+int pass_forward(pes_flow* f, int64_t Mp, bool store, hipStream_t s) {
+  for (int l = 0; l < kLayers; ++l) {
+    const int slot = store ? l : 0;
+    int rc = net_forward(f, l, Mp, slot, s);
+    if (rc != PES_OK) return rc;
+    hipLaunchKernelGGL(couple_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, f->x, f->O + (int64_t)slot * Mp * kPad,
+                       f->logdet, store ? f->xin + (int64_t)l * Mp * kD : nullptr, Mp, f->L[l], 0);
+    FL_HIP(f, hipGetLastError());
+  }
+  return PES_OK;
+}
+
+int pass_inverse(pes_flow* f, int64_t Mp, hipStream_t s) {
+  for (int l = kLayers - 1; l >= 0; --l) {
+    int rc = net_forward(f, l, Mp, 0, s);
+    if (rc != PES_OK) return rc;
+    hipLaunchKernelGGL(couple_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, f->x, f->O, f->logdet,
+                       (float*)nullptr, Mp, f->L[l], 1);
+    FL_HIP(f, hipGetLastError());
+  }
+  return PES_OK;
+}
+
+// Backward of the mean NLL over the first n rows after pass_forward(store):
+// gradient into f->G, NLL into nll (device, may be null).
+int pass_backward(pes_flow* f, int64_t n, int64_t Mp, double* nll, hipStream_t s) {
+  hipLaunchKernelGGL(nll_seed_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, f->x, f->logdet, n, Mp, f->gy, f->rowv);
+  if (nll) hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(256), 0, s, f->rowv, Mp, nll);
+  FL_HIP(f, hipGetLastError());
+  float* dpf2 = f->dpf;
+  float* dpf1 = f->dpf + Mp * kHid;
+  __bf16* dpb2 = f->dpb;
+  __bf16* dpb1 = f->dpb + Mp * kHid;
+  for (int l = kLayers - 1; l >= 0; --l) {
+    const LayerSpec& ls = f->L[l];
+    const int64_t so = (int64_t)l * Mp;
+    const __bf16* Xc = f->Xc + so * kPad;
+    const __bf16* H1 = f->H1 + so * kHid;
+    const __bf16* H2 = f->H2 + so * kHid;
+    const TensorDesc* td = &f->tt.t[6 * l];   // W1, b1, W2, b2, W3, b3
+    hipLaunchKernelGGL(couple_bwd_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, f->xin + so * kD, f->O + so * kPad,
+                       f->gy, f->gx, f->gOf, f->gOb, n, Mp, ls);
+    FL_HIP(f, hipGetLastError());
+    GemmArgs g;
+    // dW3[i][o] = sum_m H2[m][i] gO[m][o]
+    memset(&g, 0, sizeof(g));
+    g.A = H2; g.lda = kHid; g.B = f->gOb; g.ldb = kPad; g.M = kHid; g.N = kPad; g.K = (int)Mp;
+    g.C = f->G + td[4].off; g.ldc = 2 * ls.nt; g.m_valid = kHid; g.n_valid = 2 * ls.nt;
+    FL_HIP(f, (gemm<false, false, EPI_F32>(g, s)));
+    hipLaunchKernelGGL(colsum_kernel, dim3(2 * ls.nt), dim3(256), 0, s, f->gOf, (int64_t)kPad, Mp, f->G + td[5].off);
+    // dpre2 = (gO W3^T) * [H2 > 0]: B(n = i, k = o) = W3[i][o]
+    memset(&g, 0, sizeof(g));
+    g.A = f->gOb; g.lda = kPad; g.B = W3b(f, l); g.ldb = kPad; g.M = (int)Mp; g.N = kHid; g.K = kPad;
+    g.mask = H2; g.ldm = kHid; g.C = dpf2; g.ldc = kHid; g.Cb = dpb2; g.ldcb = kHid;
+    FL_HIP(f, (gemm<true, true, EPI_MASK>(g, s)));
+    // dW2 = H1^T dpre2, db2
+    memset(&g, 0, sizeof(g));
+    g.A = H1; g.lda = kHid; g.B = dpb2; g.ldb = kHid; g.M = kHid; g.N = kHid; g.K = (int)Mp;
+    g.C = f->G + td[2].off; g.ldc = kHid; g.m_valid = kHid; g.n_valid = kHid;
+    FL_HIP(f, (gemm<false, false, EPI_F32>(g, s)));
+    hipLaunchKernelGGL(colsum_kernel, dim3(kHid), dim3(256), 0, s, dpf2, (int64_t)kHid, Mp, f->G + td[3].off);
+    // dpre1 = (dpre2 W2^T) * [H1 > 0]
+    memset(&g, 0, sizeof(g));
+    g.A = dpb2; g.lda = kHid; g.B = W2b(f, l); g.ldb = kHid; g.M = (int)Mp; g.N = kHid; g.K = kHid;
+    g.mask = H1; g.ldm = kHid; g.C = dpf1; g.ldc = kHid; g.Cb = dpb1; g.ldcb = kHid;
+    FL_HIP(f, (gemm<true, true, EPI_MASK>(g, s)));
+    // dW1 = Xc^T dpre1 (rows i < n_C), db1
+    memset(&g, 0, sizeof(g));
+    g.A = Xc; g.lda = kPad; g.B = dpb1; g.ldb = kHid; g.M = kPad; g.N = kHid; g.K = (int)Mp;
+    g.C = f->G + td[0].off; g.ldc = kHid; g.m_valid = ls.nc; g.n_valid = kHid;
+    FL_HIP(f, (gemm<false, false, EPI_F32>(g, s)));
+    hipLaunchKernelGGL(colsum_kernel, dim3(kHid), dim3(256), 0, s, dpf1, (int64_t)kHid, Mp, f->G + td[1].off);
+    FL_HIP(f, hipGetLastError());
+    if (l > 0) {
+      // dXc = dpre1 W1^T: B(n = i, k = o) = W1[i][o]
+      memset(&g, 0, sizeof(g));
+      g.A = dpb1; g.lda = kHid; g.B = W1b(f, l); g.ldb = kHid; g.M = (int)Mp; g.N = kPad; g.K = kHid;
+      g.C = f->dXc; g.ldc = kPad; g.m_valid = (int)Mp; g.n_valid = kPad;
+      FL_HIP(f, (gemm<true, true, EPI_F32>(g, s)));
+      hipLaunchKernelGGL(scatter_cond_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, f->dXc, f->gx, Mp, ls);
+      FL_HIP(f, hipGetLastError());
+      std::swap(f->gy, f->gx);
+    }
+  }
+  return PES_OK;
+}
+
+int refresh(pes_flow* f, bool update, float lr, hipStream_t s) {
+  float c1 = 1.0f, c2 = 1.0f;
+  const float b1 = 0.9f, b2 = 0.999f;
+  if (update) {
+    ++f->t_adam;
+    c1 = (float)(1.0 / (1.0 - pow((double)b1, (double)f->t_adam)));
+    c2 = (float)(1.0 / (1.0 - pow((double)b2, (double)f->t_adam)));
+  }
+  hipLaunchKernelGGL(adam_kernel, dim3(nblk(kHid * kHid, 256), kTensors), dim3(256), 0, s, f->P, f->G, f->m1, f->m2,
+                     f->wb, f->bp, f->tt, update ? 1 : 0, lr, b1, b2, c1, c2, 1e-8f);
+  FL_HIP(f, hipGetLastError());
+  return PES_OK;
+}
+
+void build_spec(pes_flow* f) {
+  int64_t off = 0;
+  for (int l = 0; l < kLayers; ++l) {
+    const int p = l / 2;
+    int in_c[kD], nc = 0, nt = 0;
+    for (int i = 0; i < kD; ++i) in_c[i] = ((i + 3 * p) % kD) < 6;
+    if (l % 2)
+      for (int i = 0; i < kD; ++i) in_c[i] = !in_c[i];
+    LayerSpec& ls = f->L[l];
+    for (int i = 0; i < kD; ++i) {
+      if (in_c[i]) ls.cond[nc++] = i;
+      else ls.trans[nt++] = i;
+    }
+    ls.nc = nc;
+    ls.nt = nt;
+    const int rows[6] = {nc, 1, kHid, 1, kHid, 1};
+    const int cols[6] = {kHid, kHid, kHid, kHid, 2 * nt, 2 * nt};
+    const int64_t wo[6] = {0, -1, kPad * kHid, -1, kPad * kHid + kHid * kHid, -1};
+    const int64_t bo[6] = {-1, 0, -1, kHid, -1, 2 * kHid};
+    const int ldw[6] = {kHid, 0, kHid, 0, kPad, 0};
+    for (int q = 0; q < 6; ++q) {
+      TensorDesc& d = f->tt.t[6 * l + q];
+      d.off = off;
+      d.rows = rows[q];
+      d.cols = cols[q];
+      d.woff = wo[q] >= 0 ? (int64_t)l * kLayerW + wo[q] : -1;
+      d.boff = bo[q] >= 0 ? (int64_t)l * kLayerB + bo[q] : -1;
+      d.ldw = ldw[q];
+      off += (int64_t)rows[q] * cols[q];
+    }
+  }
+  f->np = off;
+}
+
+void destroy(pes_flow* f) {
+  free_ws(f);
+  (void)hipFree(f->P);
+  (void)hipFree(f->G);
+  (void)hipFree(f->m1);
+  (void)hipFree(f->m2);
+  (void)hipFree(f->wb);
+  (void)hipFree(f->bp);
+  (void)hipFree(f->mom);
+  delete f;
+}
+
+int set_norm(pes_flow* f, const double* mu, const double* sigma) {
+  double ls = 0.0;
+  for (int k = 0; k < kD; ++k) {
+    if (!(sigma[k] > 0.0) || !std::isfinite(sigma[k]) || !std::isfinite(mu[k])) return PES_EINVAL;
+    ls += log(sigma[k]);
+  }
+  for (int k = 0; k < kD; ++k) {
+    f->nm.mu[k] = mu[k];
+    f->nm.sigma[k] = sigma[k];
+  }
+  f->lsig = ls;
+  return PES_OK;
+}
+
+}  // namespace
+
+namespace pes {
+
+int flow_reserve(pes_flow* f, int64_t n) { return ensure_ws(f, n); }
+
+int flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double* logq, hipStream_t s) {
+  if (n <= 0) return PES_OK;
+  const int64_t Mp = pad_rows(n);
+  if (Mp > f->cap) return PES_ESTATE;
+  hipLaunchKernelGGL(standardize_kernel, dim3(nblk(Mp * kD, 256)), dim3(256), 0, s, theta, n, Mp, f->nm, f->x,
+                     f->logdet);
+  FL_HIP(f, hipGetLastError());
+  int rc = pass_forward(f, Mp, false, s);
+  if (rc != PES_OK) return rc;
+  hipLaunchKernelGGL(logq_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, f->x, f->logdet, n, f->lsig, logq, z);
+  FL_HIP(f, hipGetLastError());
+  return PES_OK;
+}
+
+int flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, double* logdet, hipStream_t s) {
+  if (n <= 0) return PES_OK;
+  const int64_t Mp = pad_rows(n);
+  if (Mp > f->cap) return PES_ESTATE;
+  hipLaunchKernelGGL(load_latent_kernel, dim3(nblk(Mp * kD, 256)), dim3(256), 0, s, z, n, Mp, f->x, f->logdet);
+  FL_HIP(f, hipGetLastError());
+  int rc = pass_inverse(f, Mp, s);
+  if (rc != PES_OK) return rc;
+  hipLaunchKernelGGL(unstandardize_kernel, dim3(nblk(n * kD, 256)), dim3(256), 0, s, f->x, f->logdet, n, f->nm,
+                     theta, logdet);
+  FL_HIP(f, hipGetLastError());
+  return PES_OK;
+}
+
+}  // namespace pes
+
+extern "C" {
+
+int pes_flow_create(uint64_t seed, pes_flow** out) {
+  if (!out) return PES_EINVAL;
+  *out = nullptr;
+  pes_flow* f = new (std::nothrow) pes_flow();
+  if (!f) return PES_ENOMEM;
+  build_spec(f);
+  const int64_t np = f->np;
+  if (hipMalloc(&f->P, sizeof(float) * np) != hipSuccess || hipMalloc(&f->G, sizeof(float) * np) != hipSuccess ||
+      hipMalloc(&f->m1, sizeof(float) * np) != hipSuccess || hipMalloc(&f->m2, sizeof(float) * np) != hipSuccess ||
+      hipMalloc(&f->wb, sizeof(__bf16) * kLayers * kLayerW) != hipSuccess ||
+      hipMalloc(&f->bp, sizeof(float) * kLayers * kLayerB) != hipSuccess ||
+      hipMalloc(&f->mom, sizeof(double) * 2 * kD) != hipSuccess) {
+    destroy(f);
+    return PES_ENOMEM;
+  }
+  // padding of the BF16 and bias copies stays zero
+  if (hipMemset(f->wb, 0, sizeof(__bf16) * kLayers * kLayerW) != hipSuccess ||
+      hipMemset(f->bp, 0, sizeof(float) * kLayers * kLayerB) != hipSuccess ||
+      hipMemset(f->G, 0, sizeof(float) * np) != hipSuccess || hipMemset(f->m1, 0, sizeof(float) * np) != hipSuccess ||
+      hipMemset(f->m2, 0, sizeof(float) * np) != hipSuccess) {
+    destroy(f);
+    return PES_EHIP;
+  }
+  // Kaiming-uniform hidden layers, a small output layer (near-identity map), zero biases
+  float* h = new (std::nothrow) float[np]();
+  if (!h) {
+    destroy(f);
+    return PES_ENOMEM;
+  }
+  std::mt19937_64 rng(seed);
+  std::uniform_real_distribution<double> U(-1.0, 1.0);
+  for (int l = 0; l < kLayers; ++l) {
+    const TensorDesc* td = &f->tt.t[6 * l];
+    for (int q : {0, 2, 4}) {
+      const double bound = q == 4 ? 1e-2 / sqrt((double)kHid) : sqrt(6.0 / td[q].rows);
+      for (int64_t i = 0; i < (int64_t)td[q].rows * td[q].cols; ++i) h[td[q].off + i] = (float)(bound * U(rng));
+    }
+  }
+  const hipError_t e = hipMemcpy(f->P, h, sizeof(float) * np, hipMemcpyHostToDevice);
+  delete[] h;
+  if (e != hipSuccess) {
+    destroy(f);
+    return PES_EHIP;
+  }
+  double mu[kD], sg[kD];
+  for (int k = 0; k < kD; ++k) {
+    mu[k] = 0.0;
+    sg[k] = 1.0;
+  }
+  set_norm(f, mu, sg);
+  if (refresh(f, false, 0.0f, nullptr) != PES_OK || hipDeviceSynchronize() != hipSuccess) {
+    destroy(f);
+    return PES_EHIP;
+  }
+  *out = f;
+  return PES_OK;
+}
+
+int pes_flow_destroy(pes_flow* f) {
+  if (!f) return PES_EINVAL;
+  (void)hipDeviceSynchronize();
+  destroy(f);
+  return PES_OK;
+}
+
+int64_t pes_flow_num_params(void) {
+  pes_flow tmp;
+  build_spec(&tmp);
+  return tmp.np;
+}
+
+int pes_flow_set_params(pes_flow* f, const float* params, void* stream) {
+  if (!f || !params) return PES_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  FL_HIP(f, hipMemcpyAsync(f->P, params, sizeof(float) * f->np, hipMemcpyDeviceToDevice, s));
+  FL_HIP(f, hipMemsetAsync(f->m1, 0, sizeof(float) * f->np, s));
+  FL_HIP(f, hipMemsetAsync(f->m2, 0, sizeof(float) * f->np, s));
+  f->t_adam = 0;
+  return refresh(f, false, 0.0f, s);
+}
+
+int pes_flow_get_params(pes_flow* f, float* params, void* stream) {
+  if (!f || !params) return PES_EINVAL;
+  FL_HIP(f, hipMemcpyAsync(params, f->P, sizeof(float) * f->np, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return PES_OK;
+}
+
+int pes_flow_set_norm(pes_flow* f, const double* mu, const double* sigma) {
+  if (!f || !mu || !sigma) return PES_EINVAL;
+  return set_norm(f, mu, sigma);
+}
+
+int pes_flow_get_norm(pes_flow* f, double* mu, double* sigma) {
+  if (!f || !mu || !sigma) return PES_EINVAL;
+  for (int k = 0; k < kD; ++k) {
+    mu[k] = f->nm.mu[k];
+    sigma[k] = f->nm.sigma[k];
+  }
+  return PES_OK;
+}
+
+int pes_flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double* logq, void* stream) {
+  if (!f || n < 0 || (n > 0 && (!theta || !logq))) return PES_EINVAL;
+  int rc = ensure_ws(f, n);
+  if (rc != PES_OK) return rc;
+  return pes::flow_forward(f, theta, n, z, logq, (hipStream_t)stream);
+}
+
+int pes_flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, double* logdet, void* stream) {
+  if (!f || n < 0 || (n > 0 && (!z || !theta))) return PES_EINVAL;
+  int rc = ensure_ws(f, n);
+  if (rc != PES_OK) return rc;
+  return pes::flow_inverse(f, z, n, theta, logdet, (hipStream_t)stream);
+}
+
+int pes_flow_nll_grad(pes_flow* f, const double* theta, int64_t n, double* nll, float* grad, void* stream) {
+  if (!f || n <= 0 || !theta || !grad) return PES_EINVAL;
+  int rc = ensure_ws(f, n);
+  if (rc != PES_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t Mp = pad_rows(n);
+  hipLaunchKernelGGL(standardize_kernel, dim3(nblk(Mp * kD, 256)), dim3(256), 0, s, theta, n, Mp, f->nm, f->x,
+                     f->logdet);
+  FL_HIP(f, hipGetLastError());
+  rc = pass_forward(f, Mp, true, s);
+  if (rc != PES_OK) return rc;
+  rc = pass_backward(f, n, Mp, nll, s);
+  if (rc != PES_OK) return rc;
+  FL_HIP(f, hipMemcpyAsync(grad, f->G, sizeof(float) * f->np, hipMemcpyDeviceToDevice, s));
+  return PES_OK;
+}
+
+int pes_flow_adam_step(pes_flow* f, const float* grad, float lr, void* stream) {
+  if (!f || !(lr >= 0.0f)) return PES_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (grad) FL_HIP(f, hipMemcpyAsync(f->G, grad, sizeof(float) * f->np, hipMemcpyDeviceToDevice, s));
+  return refresh(f, true, lr, s);
+}
+
+int pes_flow_fit(pes_flow* f, const double* samples, int64_t n, int64_t steps, int64_t batch, float lr,
+                 uint64_t seed, int standardize, double* loss, void* stream) {
+  if (!f || !samples || n < 2 || steps < 0 || batch < 1 || batch > n || !(lr > 0.0f)) return PES_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_ws(f, batch);
+  if (rc != PES_OK) return rc;
+  if (standardize) {
+    hipLaunchKernelGGL(moments_kernel, dim3(kD), dim3(256), 0, s, samples, n, f->mom);
+    double h[2 * kD];
+    FL_HIP(f, hipMemcpyAsync(h, f->mom, sizeof(h), hipMemcpyDeviceToHost, s));
+    FL_HIP(f, hipStreamSynchronize(s));
+    rc = set_norm(f, h, h + kD);
+    if (rc != PES_OK) {
+      snprintf(f->err, sizeof(f->err), "training samples have a constant coordinate");
+      return rc;
+    }
+  }
+  const int64_t Mp = pad_rows(batch);
+  for (int64_t it = 0; it < steps; ++it) {
+    hipLaunchKernelGGL(batch_kernel, dim3(nblk(batch, 256)), dim3(256), 0, s, samples, n, batch, seed,
+                       (uint64_t)it, f->batchbuf);
+    hipLaunchKernelGGL(standardize_kernel, dim3(nblk(Mp * kD, 256)), dim3(256), 0, s, f->batchbuf, batch, Mp, f->nm,
+                       f->x, f->logdet);
+    FL_HIP(f, hipGetLastError());
+    rc = pass_forward(f, Mp, true, s);
+    if (rc != PES_OK) return rc;
+    rc = pass_backward(f, batch, Mp, loss ? loss + it : nullptr, s);
+    if (rc != PES_OK) return rc;
+    rc = refresh(f, true, lr, s);
+    if (rc != PES_OK) return rc;
+  }
+  return PES_OK;
+}
+
+const char* pes_flow_last_error(pes_flow* f) { return f ? f->err : "null flow"; }
+
+}  // extern "C"

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "pes_adjoint.hpp"
 #include "pes_eval.hpp"
 #include "pes_launch.hpp"
 
@@ -893,6 +894,94 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// Reverse-mode gradient: for each (walker, bin, detector) one forward
+// evaluation gives the channels and the weighted residual, adj_links turns it
+// into link adjoints, and adj_unit recomputes and back-propagates every active
+// mode, contracting table-entry adjoints with the setup's theta-derivatives.
+template <bool LS, bool GEO>
+__device__ __forceinline__ void adj_det(const double* __restrict__ bins, const double* __restrict__ tb,
+                                        const double* __restrict__ wt, const double* __restrict__ wtn,
+                                        const JacArgs& A, int det, int64_t k, bool in, double* g,
+                                        double& dh, double& hh) {
+  const int64_t N = A.N;
+  const int64_t kk = in ? k : N - 1;
+  BinRegs br;
+  br.f = bins[B_F * N + kk];
+  br.f13 = bins[B_F13 * N + kk];
+  br.fm13 = bins[B_FM13 * N + kk];
+  br.fm76 = bins[B_FM76 * N + kk];
+  br.lnf = bins[B_LNF * N + kk];
+  const double zr = tb[T_ZR * N + kk], zi = tb[T_ZI * N + kk], a = tb[T_A * N + kk];
+  const double wA = in ? tb[T_WA * N + kk] : 0.0;
+  const double wT = in ? tb[T_WT * N + kk] : 0.0;
+  double D[6];
+  D[0] = in ? tb[T_DAR * N + kk] : 0.0;
+  D[1] = in ? tb[T_DAI * N + kk] : 0.0;
+  D[2] = in ? tb[T_DER * N + kk] : 0.0;
+  D[3] = in ? tb[T_DEI * N + kk] : 0.0;
+  D[4] = in ? tb[T_DTR * N + kk] : 0.0;
+  D[5] = in ? tb[T_DTI * N + kk] : 0.0;
+  const DetParams& P = A.dt.p[det];
+  const Chan c = eval_channels<GEO, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br, a, zr, zi);
+  dh = fma(D[0], c.ar, dh);
+  dh = fma(D[1], c.ai, dh);
+  dh = fma(D[2], c.er, dh);
+  dh = fma(D[3], c.ei, dh);
+  dh = fma(D[4], c.tr, dh);
+  dh = fma(D[5], c.ti, dh);
+  const double a2 = fma(c.ar, c.ar, c.ai * c.ai) + (1.0 / 3.0) * fma(c.er, c.er, c.ei * c.ei);
+  const double t2 = fma(c.tr, c.tr, c.ti * c.ti);
+  hh = fma(wA, a2, fma(wT, t2, hh));
+  double yb[3][4];
+  adj_links(c, D, wA, wT, zr, zi, yb);
+  const double ftc = frac_prod(br.f, wt[W_TC]);
+#pragma unroll 1
+  for (int j = 0; j < A.n_modes; ++j)
+    adj_unit<GEO, LS>(wt, wtn, det, j, P.inv_year, P.inv_ptq, br, a, ftc, yb, g);
+}
+
+template <bool LS>
+__global__ void __launch_bounds__(64)
+    adj_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
+               const double* __restrict__ wtab, const double* __restrict__ wtan,
+               double* __restrict__ partial, JacArgs A) {
+  const int t = blockIdx.x;
+  const int b = blockIdx.y;
+  const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
+  const double* __restrict__ wtn = wtan + (int64_t)b * W_STRIDE * kNParams;
+  if (wt[W_VALID] == 0.0) return;
+  const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
+  const int64_t k0 = (int64_t)t * A.tile;
+  if (k0 >= nact) return;
+  const int lane = threadIdx.x;
+  const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
+  double g[kNParams];
+#pragma unroll
+  for (int i = 0; i < kNParams; ++i) g[i] = 0.0;
+  double dh = 0.0, hh = 0.0;
+  for (int64_t s0 = k0; s0 < kend; s0 += 64) {
+    const int64_t k = s0 + lane;
+    const bool in = k < kend;
+    for (int det = 0; det < A.n_det; ++det) {
+      const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * A.N;
+      if (A.dt.p[det].kind == 2)
+        adj_det<LS, true>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh);
+      else
+        adj_det<LS, false>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh);
+    }
+  }
+  double red[kNParams + 2];
+#pragma unroll
+  for (int i = 0; i < kNParams; ++i) red[i] = wave_sum_dpp(g[i]);
+  red[kNParams] = wave_sum_dpp(dh);
+  red[kNParams + 1] = wave_sum_dpp(hh);
+  if (lane == 0) {
+    double* p = partial + ((int64_t)t * A.B + b) * (kNParams + 2);
+#pragma unroll
+    for (int i = 0; i < kNParams + 2; ++i) p[i] = red[i];
+  }
+}
+
 // Per walker, tiles summed in order.  logl = <d|h> - <h|h>/2 - <d|d>/2.
 __global__ void grad_finalize_kernel(const double* __restrict__ partial, const double* __restrict__ wtab,
                                      const double* __restrict__ dd, JacArgs A, double* __restrict__ logl,
@@ -939,13 +1028,19 @@ __global__ void fisher_finalize_kernel(const double* __restrict__ partial, const
 }
 
 hipError_t launch_grad(const double* bins, const double* tabs, const double* wtab, const double* wtan,
-                       double* partial, const double* dd, const JacArgs& A, bool long_sinc, double* logl,
-                       double* grad, hipStream_t s) {
+                       double* partial, const double* dd, const JacArgs& A, bool long_sinc, bool adjoint,
+                       double* logl, double* grad, hipStream_t s) {
   const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
-  if (long_sinc)
+  if (adjoint) {
+    if (long_sinc)
+      hipLaunchKernelGGL((adj_kernel<true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+    else
+      hipLaunchKernelGGL((adj_kernel<false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+  } else if (long_sinc) {
     hipLaunchKernelGGL((jac_kernel<true, false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
-  else
+  } else {
     hipLaunchKernelGGL((jac_kernel<false, false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+  }
   hipLaunchKernelGGL(grad_finalize_kernel, dim3((A.B + 255) / 256), dim3(256), 0, s, partial, wtab, dd, A, logl,
                      grad);
   return hipGetLastError();

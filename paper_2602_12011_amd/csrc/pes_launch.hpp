@@ -55,8 +55,8 @@ struct JacArgs {
 };
 
 hipError_t launch_grad(const double* bins, const double* tabs, const double* wtab, const double* wtan,
-                       double* partial, const double* dd, const JacArgs& A, bool long_sinc, double* logl,
-                       double* grad, hipStream_t s);
+                       double* partial, const double* dd, const JacArgs& A, bool long_sinc, bool adjoint,
+                       double* logl, double* grad, hipStream_t s);
 hipError_t launch_fisher(const double* bins, const double* tabs, const double* wtab, const double* wtan,
                          double* partial, const JacArgs& A, bool long_sinc, double* F, hipStream_t s);
 

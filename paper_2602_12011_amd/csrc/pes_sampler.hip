@@ -184,6 +184,44 @@ __global__ void init_state_kernel(const double* __restrict__ theta, double* __re
   if (i < B) logp[i] = log_prior(theta + 11 * i, p);
 }
 
+// ---------------------------------------------------------------- flow proposal
+// Latent draws of the independence proposal: z_k ~ N(0, 1) by Box-Muller from
+// the Philox block of purpose 20 + k.
+__global__ void flow_latent_kernel(double* __restrict__ z, const uint64_t* __restrict__ step_ctr, DeArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_upd) return;
+  const int64_t i = a.upd0 + j;
+  const uint64_t step = step_ctr[0] * 2 + a.half;
+  for (int k = 0; k < kNParams; ++k) {
+    const uint4 r = draw(a.seed, (uint64_t)i, step, 20u + (uint32_t)k);
+    const double u1 = u01(r.x, r.y), u2 = u01(r.z, r.w);
+    z[11 * j + k] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+}
+
+// Mixture: with probability p_flow (purpose 19) the walker takes the flow's
+// proposal and the Hastings term log q(current) - log q(proposal); otherwise
+// it keeps the DE proposal already in prop (log q ratio 0).  A flow proposal
+// outside the range of a periodic parameter is rejected (log q ratio -inf).
+__global__ void flow_mix_kernel(const double* __restrict__ fprop, const double* __restrict__ lq_prop,
+                                const double* __restrict__ lq_cur, double* __restrict__ prop,
+                                double* __restrict__ qratio, const uint64_t* __restrict__ step_ctr, DeArgs a,
+                                double p_flow) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_upd) return;
+  const int64_t i = a.upd0 + j;
+  const uint64_t step = step_ctr[0] * 2 + a.half;
+  const uint4 r = draw(a.seed, (uint64_t)i, step, 19u);
+  if (!(u01(r.x, r.y) < p_flow)) return;
+  bool ok = isfinite(lq_prop[j]) && isfinite(lq_cur[j]);
+  for (int k = 0; k < kNParams; ++k) {
+    const double x = fprop[11 * j + k];
+    prop[11 * j + k] = x;
+    if (a.prior.kind[k] == PES_PRIOR_PERIODIC && !(x >= a.prior.lo[k] && x < a.prior.hi[k])) ok = false;
+  }
+  qratio[j] = ok ? lq_cur[j] - lq_prop[j] : -INFINITY;
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_philox(uint64_t key, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t* out,
                          hipStream_t s) {
@@ -212,6 +250,18 @@ hipError_t launch_end_step(const double* theta, uint64_t* step, double* chain, i
   hipLaunchKernelGGL(end_step_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, step, chain,
                      n_chain, B);
   hipLaunchKernelGGL(commit_step_kernel, dim3(1), dim3(1), 0, s, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_flow_latent(double* z, const uint64_t* step, const DeArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(flow_latent_kernel, dim3((unsigned)((a.n_upd + 127) / 128)), dim3(128), 0, s, z, step, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_flow_mix(const double* fprop, const double* lq_prop, const double* lq_cur, double* prop,
+                           double* qratio, const uint64_t* step, const DeArgs& a, double p_flow, hipStream_t s) {
+  hipLaunchKernelGGL(flow_mix_kernel, dim3((unsigned)((a.n_upd + 127) / 128)), dim3(128), 0, s, fprop, lq_prop,
+                     lq_cur, prop, qratio, step, a, p_flow);
   return hipGetLastError();
 }
 

@@ -31,5 +31,8 @@ hipError_t launch_accept(double* theta, double* logl, double* logp, const double
 hipError_t launch_end_step(const double* theta, uint64_t* step, double* chain, int64_t n_chain, int64_t B,
                            hipStream_t s);
 hipError_t launch_init_state(const double* theta, double* logp, int64_t B, const PriorArgs& p, hipStream_t s);
+hipError_t launch_flow_latent(double* z, const uint64_t* step, const DeArgs& a, hipStream_t s);
+hipError_t launch_flow_mix(const double* fprop, const double* lq_prop, const double* lq_cur, double* prop,
+                           double* qratio, const uint64_t* step, const DeArgs& a, double p_flow, hipStream_t s);
 
 }  // namespace pes

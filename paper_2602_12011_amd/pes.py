@@ -38,6 +38,8 @@ class Prior(C.Structure):
     _fields_ = [("kind", C.c_int * 11), ("lo", C.c_double * 11), ("hi", C.c_double * 11)]
 
 
+GRAD_ADJOINT, GRAD_FORWARD = 0, 1
+
 PRIOR_KIND = {"uniform": 0, "loguniform": 1, "cosine_sin": 2, "sin": 2, "arcsin": 3, "cos": 3,
               "periodic": 4, "fixed": 5}
 
@@ -63,6 +65,24 @@ def lib():
         L.pes_autotune.argtypes = [vp, vp, C.c_int64, vp, C.POINTER(C.c_double), vp]
         L.pes_grad.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
         L.pes_fisher.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.pes_set_grad_method.argtypes = [vp, C.c_int]
+        L.pes_flow_create.argtypes = [C.c_uint64, C.POINTER(vp)]
+        L.pes_flow_destroy.argtypes = [vp]
+        L.pes_flow_num_params.argtypes = []
+        L.pes_flow_num_params.restype = C.c_int64
+        L.pes_flow_set_params.argtypes = [vp, vp, vp]
+        L.pes_flow_get_params.argtypes = [vp, vp, vp]
+        L.pes_flow_set_norm.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.pes_flow_get_norm.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.pes_flow_forward.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
+        L.pes_flow_inverse.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
+        L.pes_flow_nll_grad.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
+        L.pes_flow_adam_step.argtypes = [vp, vp, C.c_float, vp]
+        L.pes_flow_fit.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_int64, C.c_float, C.c_uint64, C.c_int,
+                                   vp, vp]
+        L.pes_flow_last_error.argtypes = [vp]
+        L.pes_flow_last_error.restype = C.c_char_p
+        L.pes_sampler_set_flow.argtypes = [vp, vp, C.c_double]
         L.pes_sampler_create.argtypes = [vp, C.POINTER(Prior), C.c_int64, C.c_uint64, C.c_int64,
                                          C.POINTER(vp)]
         L.pes_sampler_destroy.argtypes = [vp]
@@ -83,7 +103,10 @@ def lib():
         L.pes_last_error.restype = C.c_char_p
         for name in ("pes_create", "pes_destroy", "pes_reserve", "pes_set_data",
                      "pes_response", "pes_loglike", "pes_timing", "pes_timing_read",
-                     "pes_set_tuning", "pes_get_tuning", "pes_autotune", "pes_grad",
+                     "pes_set_tuning", "pes_get_tuning", "pes_autotune", "pes_grad", "pes_set_grad_method",
+                     "pes_flow_create", "pes_flow_destroy", "pes_flow_set_params", "pes_flow_get_params",
+                     "pes_flow_set_norm", "pes_flow_get_norm", "pes_flow_forward", "pes_flow_inverse",
+                     "pes_flow_nll_grad", "pes_flow_adam_step", "pes_flow_fit", "pes_sampler_set_flow",
                      "pes_fisher", "pes_sampler_create", "pes_sampler_destroy",
                      "pes_sampler_set_state", "pes_sampler_step", "pes_sampler_capture",
                      "pes_sampler_launch", "pes_sampler_state", "pes_sampler_chain", "pes_propose",
@@ -231,6 +254,11 @@ class Context:
                                    _dev_f64(g, "grad"), _stream(stream)), "pes_grad")
         return logl, g
 
+    def set_grad_method(self, method):
+        """"adjoint" (reverse sweep, the default) or "forward" (tangents)."""
+        code = {"adjoint": GRAD_ADJOINT, "forward": GRAD_FORWARD}[method]
+        self._check(lib().pes_set_grad_method(self.h, code), "pes_set_grad_method")
+
     def fisher(self, theta, stream=None):
         """Fisher matrices [B, 11, 11]."""
         theta = theta.contiguous()
@@ -327,14 +355,115 @@ class Sampler:
         self.ctx._check(lib().pes_sampler_chain(self.h, C.byref(p)), "pes_sampler_chain")
         return p.value
 
-    def propose(self, half, stream=None):
+    def propose(self, half, kind="de", stream=None):
+        """Proposals of the given half: "de", or "flow" (the mixture set by set_flow)."""
         n = self.B // 2 if half == 0 else self.B - self.B // 2
         dev = torch.device("cuda")
         prop = torch.empty((n, 11), dtype=torch.float64, device=dev)
         q = torch.empty(n, dtype=torch.float64, device=dev)
-        self.ctx._check(lib().pes_propose(self.h, 0, int(half), _dev_f64(prop, "prop"), _dev_f64(q, "q"),
+        code = {"de": 0, "flow": 1}[kind]
+        self.ctx._check(lib().pes_propose(self.h, code, int(half), _dev_f64(prop, "prop"), _dev_f64(q, "q"),
                                           _stream(stream)), "pes_propose")
         return prop, q
+
+    def set_flow(self, flow, p_flow=0.9):
+        """Mix the flow's independence proposal (probability p_flow) with DE; None: DE only."""
+        self._flow = flow
+        self.ctx._check(lib().pes_sampler_set_flow(self.h, flow.h if flow is not None else None,
+                                                   C.c_double(p_flow)), "pes_sampler_set_flow")
+
+
+class Flow:
+    """Affine-coupling flow proposal (see pes_flow_create)."""
+
+    def __init__(self, seed=0):
+        h = C.c_void_p()
+        rc = lib().pes_flow_create(C.c_uint64(seed), C.byref(h))
+        if rc != 0:
+            raise PesError(f"pes_flow_create: {lib().pes_strerror(rc).decode()}")
+        self.h = h
+        self.n_params = int(lib().pes_flow_num_params())
+
+    def _check(self, rc, name):
+        if rc != 0:
+            raise PesError(f"{name}: {lib().pes_strerror(rc).decode()} "
+                           f"({lib().pes_flow_last_error(self.h).decode()})")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pes_flow_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, stream=None):
+        params = params.contiguous()
+        if params.dtype != torch.float32 or params.numel() != self.n_params or not params.is_cuda:
+            raise PesError("params must be a CUDA float32 tensor of num_params entries")
+        self._check(lib().pes_flow_set_params(self.h, C.c_void_p(params.data_ptr()), _stream(stream)),
+                    "pes_flow_set_params")
+
+    def get_params(self, stream=None):
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        self._check(lib().pes_flow_get_params(self.h, C.c_void_p(out.data_ptr()), _stream(stream)),
+                    "pes_flow_get_params")
+        return out
+
+    def set_norm(self, mu, sigma):
+        mu = (C.c_double * 11)(*[float(x) for x in mu])
+        sg = (C.c_double * 11)(*[float(x) for x in sigma])
+        self._check(lib().pes_flow_set_norm(self.h, mu, sg), "pes_flow_set_norm")
+
+    def get_norm(self):
+        mu, sg = (C.c_double * 11)(), (C.c_double * 11)()
+        self._check(lib().pes_flow_get_norm(self.h, mu, sg), "pes_flow_get_norm")
+        return list(mu), list(sg)
+
+    def forward(self, theta, stream=None):
+        """(z [n, 11], log q(theta) [n])."""
+        theta = theta.contiguous()
+        n = theta.shape[0]
+        z = torch.empty((n, 11), dtype=torch.float64, device=theta.device)
+        lq = torch.empty(n, dtype=torch.float64, device=theta.device)
+        self._check(lib().pes_flow_forward(self.h, _dev_f64(theta, "theta"), n, _dev_f64(z, "z"),
+                                           _dev_f64(lq, "logq"), _stream(stream)), "pes_flow_forward")
+        return z, lq
+
+    def inverse(self, z, stream=None):
+        """(theta [n, 11], log det [n])."""
+        z = z.contiguous()
+        n = z.shape[0]
+        th = torch.empty((n, 11), dtype=torch.float64, device=z.device)
+        ld = torch.empty(n, dtype=torch.float64, device=z.device)
+        self._check(lib().pes_flow_inverse(self.h, _dev_f64(z, "z"), n, _dev_f64(th, "theta"),
+                                           _dev_f64(ld, "logdet"), _stream(stream)), "pes_flow_inverse")
+        return th, ld
+
+    def nll_grad(self, theta, stream=None):
+        theta = theta.contiguous()
+        nll = torch.empty(1, dtype=torch.float64, device=theta.device)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=theta.device)
+        self._check(lib().pes_flow_nll_grad(self.h, _dev_f64(theta, "theta"), theta.shape[0],
+                                            _dev_f64(nll, "nll"), C.c_void_p(g.data_ptr()), _stream(stream)),
+                    "pes_flow_nll_grad")
+        return nll, g
+
+    def adam_step(self, grad=None, lr=1e-3, stream=None):
+        p = C.c_void_p(grad.contiguous().data_ptr()) if grad is not None else None
+        self._check(lib().pes_flow_adam_step(self.h, p, C.c_float(lr), _stream(stream)), "pes_flow_adam_step")
+
+    def fit(self, samples, steps, batch, lr=1e-3, seed=0, standardize=True, stream=None):
+        """Trains on samples [n, 11] (CUDA float64); returns the per-step NLL."""
+        samples = samples.contiguous()
+        loss = torch.empty(max(int(steps), 1), dtype=torch.float64, device=samples.device)
+        self._check(lib().pes_flow_fit(self.h, _dev_f64(samples, "samples"), samples.shape[0], int(steps),
+                                       int(batch), C.c_float(lr), C.c_uint64(seed), int(bool(standardize)),
+                                       _dev_f64(loss, "loss"), _stream(stream)), "pes_flow_fit")
+        return loss[:int(steps)]
 
 
 def philox(key, c0, c1, c2, c3, n, stream=None):
@@ -366,6 +495,10 @@ def pes_loglike(ctx, theta, out=None, stream=None):
 
 def pes_grad(ctx, theta, stream=None):
     return ctx.grad(theta, stream)
+
+
+def pes_set_grad_method(ctx, method):
+    ctx.set_grad_method(method)
 
 
 def pes_fisher(ctx, theta, stream=None):

@@ -54,15 +54,17 @@ def _check_fisher(F_gpu, F_or, what):
         assert np.all(err <= 1e-6), (what, b, err.max(), np.unravel_index(err.argmax(), err.shape))
 
 
+@pytest.mark.parametrize("method", ["adjoint", "forward"])
 @pytest.mark.parametrize("case", list(CASES))
-def test_grad_matches_oracle(orc, torch_dev, pes, case):
+def test_grad_matches_oracle(orc, torch_dev, pes, case, method):
     torch = torch_dev
     cfg = CASES[case][0]()
-    print(f"[grad] {case}: n_bins={cfg['n_bins']}", flush=True)
+    print(f"[grad] {case} {method}: n_bins={cfg['n_bins']}", flush=True)
     d = orc.response(cfg, W.THETA0)
     th = W.draw_walkers(6, stream=70, flat=CASES[case][1])
     th[0] = W.THETA0 + 1e-3 * W.prior_widths() * 0.01
     ctx = pes.Context(cfg)
+    ctx.set_grad_method(method)
     ctx.set_data(torch.from_numpy(d).to("cuda"))
     L, g = ctx.grad(torch.from_numpy(th).to("cuda"))
     L, g = L.cpu().numpy(), g.cpu().numpy()
@@ -88,13 +90,15 @@ def test_fisher_matches_oracle(orc, torch_dev, pes, case):
     _check_fisher(F, F_or, case)
 
 
-def test_gradient_zero_at_injection_and_invalid(orc, torch_dev, pes):
+@pytest.mark.parametrize("method", ["adjoint", "forward"])
+def test_gradient_zero_at_injection_and_invalid(orc, torch_dev, pes, method):
     torch = torch_dev
     cfg = _cfg("cfg1", n_bins=4000)
     d = orc.response(cfg, W.THETA0)
     th = np.vstack([W.THETA0, W.THETA0])
     th[1, 1] = 1.5   # unphysical
     ctx = pes.Context(cfg)
+    ctx.set_grad_method(method)
     ctx.set_data(torch.from_numpy(d).to("cuda"))
     L, g = ctx.grad(torch.from_numpy(th).to("cuda"))
     F = ctx.fisher(torch.from_numpy(th).to("cuda")).cpu().numpy()
@@ -137,11 +141,16 @@ def test_full_size_sampled(orc, torch_dev, pes, what):
     if what == "grad":
         d = orc.response(cfg, W.THETA0)
         ctx.set_data(torch.from_numpy(d).to("cuda"))
-        _, g = ctx.grad(torch.from_numpy(th).to("cuda"))
-        g = g.cpu().numpy()
+        L, g = ctx.grad(torch.from_numpy(th).to("cuda"))
+        ctx.set_grad_method("forward")
+        L_f, g_f = ctx.grad(torch.from_numpy(th).to("cuda"))
+        g, g_f = g.cpu().numpy(), g_f.cpu().numpy()
         ctx.close()
         _, g_or = orc.grad(cfg, d, th[idx])
         _check_grad(g[idx], g_or, "full grad")
+        # every walker: reverse and forward mode agree
+        _check_grad(g, g_f, "adjoint vs forward")
+        assert torch.allclose(L, L_f, rtol=1e-12, atol=1e-12 * float(L.abs().max()))
     else:
         F = ctx.fisher(torch.from_numpy(th).to("cuda")).cpu().numpy()
         ctx.close()

@@ -1,0 +1,260 @@
+"""The learned proposal on the GPU (pes_flow_*, pes_sampler_set_flow through the
+C-ABI) against the flow reference with the same BF16-rounded weights.
+
+Tolerances: the GPU accumulates in FP32 and may round a hidden activation to
+the other neighbouring BF16 value than the FP64 reference does; one such flip
+moves an output by ~1e-4 relative, so values are compared at 1e-3 relative
+(log q at 2e-3 max(1, |log q|)); gradients, whose back-propagated operands are
+BF16 as well, per tensor by norm at 2e-2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2602_12011_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pes():
+    from paper_2602_12011_amd import pes as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def F():
+    from oracle import flow
+    return flow
+
+
+def _flow_with(pes, torch, flat, mu, sigma):
+    f = pes.Flow(seed=1)
+    assert f.n_params == flat.size
+    f.set_params(torch.from_numpy(np.asarray(flat, dtype=np.float32)).to("cuda"))
+    f.set_norm(mu, sigma)
+    return f
+
+
+def _theta(n, seed):
+    th = W.draw_walkers(n, stream=seed)
+    return th, th.mean(axis=0), th.std(axis=0) * 0.7
+
+
+@pytest.mark.parametrize("n", [1, 333, 1000])
+def test_forward_matches_reference(torch_dev, pes, F, n):
+    torch = torch_dev
+    flat = F.init_params(21, scale_out=0.3)
+    th, mu, sigma = _theta(max(n, 8), 80)
+    th = th[:n]
+    f = _flow_with(pes, torch, flat, mu, sigma)
+    z, lq = f.forward(torch.from_numpy(th).to("cuda"))
+    z, lq = z.cpu().numpy(), lq.cpu().numpy()
+    f.close()
+    z_or, _ = F.forward(flat, F.standardize(th, mu, sigma))
+    lq_or = F.log_prob(flat, th, mu, sigma)
+    assert np.all(np.abs(z - z_or) <= 1e-3 * np.maximum(1.0, np.abs(z_or)))
+    assert np.all(np.abs(lq - lq_or) <= 2e-3 * np.maximum(1.0, np.abs(lq_or))), np.abs(lq - lq_or).max()
+
+
+def test_inverse_matches_reference_and_round_trips(torch_dev, pes, F):
+    torch = torch_dev
+    flat = F.init_params(22, scale_out=0.3)
+    _, mu, sigma = _theta(64, 81)
+    z = np.random.default_rng(5).normal(size=(777, 11))
+    f = _flow_with(pes, torch, flat, mu, sigma)
+    th, ld = f.inverse(torch.from_numpy(z).to("cuda"))
+    z2, _ = f.forward(th)
+    th, z2 = th.cpu().numpy(), z2.cpu().numpy()
+    f.close()
+    u_or, ld_or = F.inverse(flat, z.astype(np.float32).astype(np.float64))
+    u = (th - mu) / sigma
+    assert np.all(np.abs(u - u_or) <= 1e-3 * np.maximum(1.0, np.abs(u_or)))
+    assert np.all(np.abs(ld.cpu().numpy() - ld_or) <= 2e-3 * np.maximum(1.0, np.abs(ld_or)))
+    assert np.abs(z2 - z).max() < 1e-4
+
+
+def test_identity_flow_is_the_standardized_gaussian(torch_dev, pes, F):
+    torch = torch_dev
+    from scipy import stats
+    flat = F.init_params(23, scale_out=0.0)
+    th, mu, sigma = _theta(300, 82)
+    f = _flow_with(pes, torch, flat, mu, sigma)
+    _, lq = f.forward(torch.from_numpy(th).to("cuda"))
+    f.close()
+    ref = stats.norm.logpdf(th, loc=mu, scale=sigma).sum(axis=1)
+    assert np.allclose(lq.cpu().numpy(), ref, rtol=1e-6, atol=1e-6)
+
+
+def test_nll_gradient_matches_reference(torch_dev, pes, F):
+    torch = torch_dev
+    flat = F.init_params(24, scale_out=0.3)
+    th, mu, sigma = _theta(517, 83)
+    f = _flow_with(pes, torch, flat, mu, sigma)
+    nll, g = f.nll_grad(torch.from_numpy(th).to("cuda"))
+    nll, g = float(nll.cpu()), g.cpu().numpy().astype(np.float64)
+    f.close()
+    nll_or, g_or = F.nll_and_grad(flat, F.standardize(th, mu, sigma))
+    assert abs(nll - nll_or) <= 1e-3 * max(1.0, abs(nll_or))
+    o = 0
+    for l in range(F.N_LAYERS):
+        for name, sh in F.shapes(l):
+            k = int(np.prod(sh))
+            a, b = g[o:o + k], g_or[o:o + k]
+            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            assert rel <= 2e-2, (l, name, rel)
+            o += k
+
+
+def test_adam_step_matches_reference(torch_dev, pes, F):
+    torch = torch_dev
+    flat = F.init_params(25, scale_out=0.3)
+    rng = np.random.default_rng(26)
+    f = _flow_with(pes, torch, flat, np.zeros(11), np.ones(11))
+    p = flat.astype(np.float64)
+    m, v = np.zeros_like(p), np.zeros_like(p)
+    for t in (1, 2, 3):
+        g = rng.normal(size=flat.size).astype(np.float32)
+        f.adam_step(torch.from_numpy(g).to("cuda"), lr=1e-3)
+        F.adam_step(p, g.astype(np.float64), m, v, t, lr=1e-3)
+    got = f.get_params().cpu().numpy().astype(np.float64)
+    f.close()
+    assert np.all(np.abs(got - p) <= 1e-6 + 1e-5 * np.abs(p))
+
+
+def test_fit_learns_a_correlated_gaussian(torch_dev, pes):
+    torch = torch_dev
+    rng = np.random.default_rng(27)
+    A = rng.normal(size=(11, 11))
+    C = A @ A.T / 11 + 0.1 * np.eye(11)
+    m = rng.normal(size=11) * 5
+    x = rng.multivariate_normal(m, C, size=40000)
+    f = pes.Flow(seed=3)
+    loss = f.fit(torch.from_numpy(x).to("cuda"), steps=600, batch=2048, lr=2e-3, seed=9)
+    loss = loss.cpu().numpy()
+    sd = np.sqrt(np.diag(C))
+    R = C / np.outer(sd, sd)
+    optimum = 0.5 * (11 * math.log(2 * math.pi * math.e) + np.linalg.slogdet(R)[1])
+    print(f"loss first {loss[0]:.3f} last {loss[-20:].mean():.3f} optimum {optimum:.3f}")
+    assert loss[-20:].mean() < loss[0] - 1.0
+    assert loss[-20:].mean() < optimum + 0.3
+    th, _ = f.inverse(torch.from_numpy(rng.normal(size=(20000, 11))).to("cuda"))
+    th = th.cpu().numpy()
+    f.close()
+    assert np.all(np.abs(th.mean(axis=0) - m) / sd < 0.1)
+    Cs = np.cov(th.T)
+    assert np.abs(Cs / np.outer(sd, sd) - R).max() < 0.1
+
+
+def _prior_all_free():
+    spec = []
+    for name in W.PARAM_NAMES:
+        kind, lo, hi = W.PRIOR[name]
+        if name in ("phi_c", "lambda", "psi"):
+            kind = "periodic"
+        spec.append((kind, lo, hi))
+    return spec
+
+
+def test_mixture_proposals_match_reference(orc, torch_dev, pes, F):
+    """pes_propose(FLOW): the DE proposals of the walkers that keep DE are the
+    DE move's exactly; the flow's, and their Hastings terms, agree with the
+    reference sampler's mixture."""
+    torch = torch_dev
+    from oracle import sampler as S
+    cfg = W.config("cfg0")
+    d = orc.response(cfg, W.THETA0)
+    prior = _prior_all_free()
+    rng = np.random.default_rng(28)
+    B = 40
+    th0 = W.THETA0 + 1e-4 * W.prior_widths() * rng.normal(size=(B, 11))
+    mu, sigma = th0.mean(axis=0), th0.std(axis=0) * 1.5
+    flat = F.init_params(29, scale_out=0.1)
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(d).to("cuda"))
+    smp = pes.Sampler(ctx, prior, B, 0xF10)
+    smp.set_state(torch.from_numpy(th0).to("cuda"))
+    f = _flow_with(pes, torch, flat, mu, sigma)
+    smp.set_flow(f, 0.7)
+    ref = S.DESampler(lambda t: orc.loglike(cfg, d, t), prior, th0, 0xF10, flow=(flat, mu, sigma, 0.7))
+    for half in (0, 1):
+        prop, q = smp.propose(half, "flow")
+        prop_de, q_de = smp.propose(half, "de")
+        prop, q, prop_de = prop.cpu().numpy(), q.cpu().numpy(), prop_de.cpu().numpy()
+        _, rprop, rq = ref._propose(half)
+        flow_rows = q != 0.0
+        assert 0 < flow_rows.sum() < len(q)
+        assert np.array_equal(prop[~flow_rows], prop_de[~flow_rows])
+        assert np.allclose(prop[~flow_rows], rprop[~flow_rows], rtol=1e-13, atol=0)
+        uf = (prop[flow_rows] - mu) / sigma
+        ur = (rprop[flow_rows] - mu) / sigma
+        assert np.all(np.abs(uf - ur) <= 1e-3 * np.maximum(1.0, np.abs(ur)))
+        fin = np.isfinite(rq[flow_rows])
+        assert np.array_equal(fin, np.isfinite(q[flow_rows]))
+        assert np.all(np.abs(q[flow_rows][fin] - rq[flow_rows][fin]) <= 5e-3 * np.maximum(1.0, np.abs(rq[flow_rows][fin])))
+    smp.close()
+    f.close()
+    ctx.close()
+
+
+def test_flow_requires_free_parameters_and_a_flow(torch_dev, pes):
+    torch = torch_dev
+    cfg = W.config("cfg0")
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.zeros((1, 3, cfg["n_bins"], 2), dtype=torch.float64, device="cuda"))
+    prior = _prior_all_free()
+    prior[0] = ("fixed", prior[0][1], prior[0][2])
+    smp = pes.Sampler(ctx, prior, 8, 1)
+    f = pes.Flow(seed=2)
+    with pytest.raises(pes.PesError):
+        smp.set_flow(f, 0.9)
+    smp.set_state(torch.from_numpy(np.tile(W.THETA0, (8, 1))).to("cuda"))
+    with pytest.raises(pes.PesError):
+        smp.propose(0, "flow")
+    smp.close()
+    f.close()
+    ctx.close()
+
+
+def test_graph_replay_with_flow_is_bitwise_eager(orc, torch_dev, pes, F):
+    torch = torch_dev
+    cfg = W.config("cfg1", n_bins=3000)
+    d = orc.response(cfg, W.THETA0)
+    prior = _prior_all_free()
+    rng = np.random.default_rng(30)
+    th0 = W.THETA0 + 1e-5 * W.prior_widths() * rng.normal(size=(64, 11))
+    mu, sigma = th0.mean(axis=0), th0.std(axis=0) * 1.3
+    flat = F.init_params(31, scale_out=0.05)
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(d).to("cuda"))
+    f = _flow_with(pes, torch, flat, mu, sigma)
+    a = pes.Sampler(ctx, prior, 64, 78)
+    b = pes.Sampler(ctx, prior, 64, 78)
+    for s_ in (a, b):
+        s_.set_state(torch.from_numpy(th0).to("cuda"))
+        s_.set_flow(f, 0.9)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.capture(s)
+    a.step(4)
+    for _ in range(4):
+        b.launch(1, s)
+        s.synchronize()
+        torch.cuda.current_stream().synchronize()
+    ta, La, aa, na = a.state()
+    tb, Lb, ab, nb = b.state(s)
+    assert na == nb == 4
+    assert torch.equal(ta, tb) and torch.equal(La, Lb) and torch.equal(aa, ab)
+    assert int(aa.sum()) > 0
+    a.close()
+    b.close()
+    f.close()
+    ctx.close()
