@@ -31,10 +31,11 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6     # MI355X FP64 vector peak (AMD specification)
 # FP64 operations (FMA counted as 2) of the kernel's formulation, counted from
 # its source: per active (walker, bin, detector, mode) unit -- heliocentric or
 # geocentric orbit, short or long sinc fit -- and per active (walker, bin,
-# detector) for the TDI combination and the inner products.  The C^2 taper
-# (the last 10% below each cutoff) is not counted.
-FLOPS_PER_MODE_UNIT = {("helio", False): 459, ("geo", False): 485,
-                       ("helio", True): 487, ("geo", True): 513}
+# detector) for the TDI combination and the inner products.  Not counted: the
+# C^2 taper (the last 10% below each cutoff) and the quarter-turn rotation of
+# the sine/cosine reduction (products with 0 and +-1).
+FLOPS_PER_MODE_UNIT = {("helio", False): 454, ("geo", False): 481,
+                       ("helio", True): 486, ("geo", True): 513}
 FLOPS_PER_WBD_UNIT = 83
 MF_ISCO = 6.0 ** -1.5 / math.pi
 MSUN_S = 4.925490947641267e-6
@@ -113,6 +114,166 @@ def cpu_baseline(cfg, theta, n_sample, threads):
                        f"5 modes, {dt:.1f} s wall")
 
 
+def _time_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def derivative_leg(torch, pes, reps):
+    """Gradients (reverse and forward mode) at 1024 walkers and Fisher matrices
+    at 256 points on cfg1's signal and grid (2^20 bins, 5 modes)."""
+    cfg = W.config("cfg3")
+    dev = torch.device("cuda:0")
+    ctx = pes.Context(cfg)
+    th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
+    ctx.set_data(ctx.response(th0)[0].clone())
+    th = torch.from_numpy(W.draw_walkers(cfg["walkers"], stream=3)).to(dev)
+    thf = th[:cfg["fisher_points"]].contiguous()
+    out = {}
+    t_ll = _time_ms(torch, lambda: ctx.loglike(th), reps)
+    ctx.set_grad_method("adjoint")
+    t_adj = _time_ms(torch, lambda: ctx.grad(th), reps)
+    ctx.set_grad_method("forward")
+    t_fwd = _time_ms(torch, lambda: ctx.grad(th), max(1, reps // 2))
+    t_fis = _time_ms(torch, lambda: ctx.fisher(thf), max(1, reps // 2))
+    ctx.close()
+    B, Bf = cfg["walkers"], cfg["fisher_points"]
+    out = dict(workload="LISA-like, 5 modes, 2^20 bins; gradients at 1024 walkers, Fisher at 256",
+               loglike_ms=round(t_ll, 3), grad_adjoint_ms=round(t_adj, 3), grad_forward_ms=round(t_fwd, 3),
+               fisher_ms=round(t_fis, 3), grad_evals_per_s=round(B / (t_adj * 1e-3), 1),
+               grad_over_loglike=round(t_adj / t_ll, 3), adjoint_speedup_over_forward=round(t_fwd / t_adj, 2),
+               fisher_per_s=round(Bf / (t_fis * 1e-3), 1))
+    return out
+
+
+def graph_leg(torch, pes, steps):
+    """Sampler steps/s at the small workload (1000 walkers, 4096 bins, (2,2)),
+    where launches dominate: eager steps against one captured-graph replay per step."""
+    cfg = W.config("cfg0")
+    dev = torch.device("cuda:0")
+    ctx = pes.Context(cfg)
+    th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
+    ctx.set_data(ctx.response(th0)[0].clone())
+    prior = _prior_spec()
+    B = cfg["walkers"]
+    rng = np.random.default_rng(11)
+    start = torch.from_numpy(W.THETA0 + 1e-6 * W.prior_widths() * rng.normal(size=(B, 11))).to(dev)
+    a = pes.Sampler(ctx, prior, B, 5)
+    b = pes.Sampler(ctx, prior, B, 5)
+    a.set_state(start)
+    b.set_state(start)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.capture(s)
+        t_graph = _time_ms(torch, lambda: b.launch(1, s), steps)
+    t_eager = _time_ms(torch, lambda: a.step(1), steps)
+    a.close()
+    b.close()
+    ctx.close()
+    return dict(workload="1000 walkers, 4096 bins, (2,2) mode, LISA-like", eager_ms_per_step=round(t_eager, 4),
+                graph_ms_per_step=round(t_graph, 4), graph_speedup=round(t_eager / t_graph, 3))
+
+
+def _prior_spec():
+    spec = []
+    for name in W.PARAM_NAMES:
+        kind, lo, hi = W.PRIOR[name]
+        if name in ("phi_c", "lambda", "psi"):
+            kind = "periodic"
+        spec.append((kind, lo, hi))
+    return spec
+
+
+def _fisher_start(ctx, torch, B, seed):
+    """Walkers from the Fisher Gaussian at the injection (regularized by the
+    prior widths), clipped to the prior box."""
+    dev = torch.device("cuda:0")
+    th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
+    F = ctx.fisher(th0).cpu().numpy()[0]
+    w = W.prior_widths()
+    C = np.linalg.inv(F + np.diag(1.0 / w ** 2))
+    C = 0.5 * (C + C.T)
+    rng = np.random.default_rng(seed)
+    x = rng.multivariate_normal(W.THETA0, C, size=B)
+    lo = np.array([W.PRIOR[n][1] for n in W.PARAM_NAMES])
+    hi = np.array([W.PRIOR[n][2] for n in W.PARAM_NAMES])
+    eps = 1e-9 * (hi - lo)
+    return np.clip(x, lo + eps, hi - eps)
+
+
+def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps):
+    """ESS/s of the plain DE-MC sampler against the mixture with the learned
+    flow (p_flow 0.9), equal numbers of steps from the same starting ensemble,
+    on the three-detector network (cfg4's likelihood at B walkers)."""
+    from paper_2602_12011_amd import diagnostics as D
+    cfg = W.config("cfg4")
+    dev = torch.device("cuda:0")
+    ctx = pes.Context(cfg)
+    th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
+    ctx.set_data(ctx.response(th0)[0].clone())
+    prior = _prior_spec()
+    start = torch.from_numpy(_fisher_start(ctx, torch, B, 12)).to(dev)
+    # pilot DE run: burn-in and training samples
+    pilot = pes.Sampler(ctx, prior, B, 101, chain_len=n_pilot)
+    pilot.set_state(start)
+    t0 = time.perf_counter()
+    pilot.step(n_pilot)
+    torch.cuda.synchronize()
+    t_pilot = time.perf_counter() - t0
+    ch = pilot.read_chain().cpu().numpy()
+    state = pilot.state()[0].clone()
+    pilot.close()
+    half = ch[n_pilot // 2:]
+    rhat = float(D.gelman_rubin(half).max())
+    train = torch.from_numpy(half.reshape(-1, 11).copy()).to(dev)
+    flow = pes.Flow(seed=7)
+    t0 = time.perf_counter()
+    loss = flow.fit(train, steps=fit_steps, batch=min(4096, train.shape[0]), lr=1e-3, seed=3)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    results = {}
+    chains = {}
+    for name, seed, use_flow in (("plain", 202, False), ("plain_b", 303, False), ("learned", 202, True)):
+        smp = pes.Sampler(ctx, prior, B, seed, chain_len=n_run)
+        smp.set_state(state)
+        if use_flow:
+            smp.set_flow(flow, 0.9)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smp.step(n_run)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        acc = smp.state()[2].cpu().numpy().sum() / (B * n_run)
+        chains[name] = smp.read_chain().cpu().numpy()
+        smp.close()
+        e = D.ess(chains[name])
+        results[name] = dict(seconds=round(dt, 3), acceptance=round(float(acc), 4),
+                             ess_min=round(float(e.min()), 1), ess_per_s=round(float(e.min()) / dt, 2))
+    flow.close()
+    ctx.close()
+    flat = {k: v.reshape(-1, 11) for k, v in chains.items()}
+    ks_lp = max(D.ks_distance(flat["learned"][:, j], flat["plain"][:, j]) for j in range(11))
+    ks_pp = max(D.ks_distance(flat["plain_b"][:, j], flat["plain"][:, j]) for j in range(11))
+    gain = results["learned"]["ess_per_s"] / max(results["plain"]["ess_per_s"], 1e-30)
+    amort = results["learned"]["ess_min"] / (results["learned"]["seconds"] + t_fit)
+    return dict(workload=f"LISA+Taiji+TianQin, 5 modes, 2^20 bins, {B} walkers, noise-free injection; "
+                         f"{n_pilot}-step DE pilot (second half trains the flow), then {n_run} steps each",
+                pilot_seconds=round(t_pilot, 2), pilot_rhat_max=round(rhat, 4), fit_seconds=round(t_fit, 2),
+                fit_loss_first_last=[round(float(loss[0]), 3), round(float(loss[-1]), 3)],
+                plain=results["plain"], learned=results["learned"], gain=round(gain, 2),
+                learned_ess_per_s_with_training=round(amort, 2),
+                ks_learned_vs_plain=round(ks_lp, 4), ks_plain_vs_plain=round(ks_pp, 4),
+                accuracy_ok=bool(ks_lp <= 1.5 * ks_pp))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +284,14 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=None,
                     help="bins_per_lane,walkers_per_group,blocks_per_cu (skips the autotuner)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline measurement (no derivative, graph or ESS legs)")
+    ap.add_argument("--extras", default="derivatives,graph,ess",
+                    help="comma list of the extra legs to run after the headline")
+    ap.add_argument("--ess-walkers", type=int, default=1024)
+    ap.add_argument("--ess-pilot", type=int, default=300)
+    ap.add_argument("--ess-steps", type=int, default=300)
+    ap.add_argument("--ess-fit-steps", type=int, default=1500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -198,11 +367,21 @@ def main():
                            detectors=[d["kind"] for d in cfg["detectors"]],
                            mode_units=n_mode, wbd_units=n_wbd, tuning=tuning),
                roofline=roofline)
+    ctx.close()
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         rec["cpu_baseline"] = cpu_baseline(cfg, theta_np, args.cpu_sample, threads)
+    extras = [] if args.no_extras else [x for x in args.extras.split(",") if x]
+    if "derivatives" in extras:
+        print("[bench] derivatives", file=sys.stderr, flush=True)
+        rec["derivatives"] = derivative_leg(torch, pes, 3)
+    if "graph" in extras:
+        print("[bench] sampler graph", file=sys.stderr, flush=True)
+        rec["sampler_graph"] = graph_leg(torch, pes, 50)
+    if "ess" in extras:
+        print("[bench] ESS", file=sys.stderr, flush=True)
+        rec["ess"] = ess_leg(torch, pes, args.ess_walkers, args.ess_pilot, args.ess_steps, args.ess_fit_steps)
     print(json.dumps(rec), flush=True)
-    ctx.close()
     return 0
 
 

@@ -181,6 +181,10 @@ int pes_sampler_state(pes_sampler* s, double* theta, double* logl, int64_t* acce
 /* Device pointer of the chain ring (NULL without one). */
 int pes_sampler_chain(pes_sampler* s, const double** chain);
 
+/* The stored states in step order, oldest first: out (dev) [*n_states][n_walkers][11]
+ * with *n_states = min(steps done, chain_len) (host).  Synchronizes the stream. */
+int pes_sampler_read_chain(pes_sampler* s, double* out, int64_t* n_states, void* stream);
+
 /* One proposal for half `half` (0 or 1) of the ensemble from the current
  * state: theta_prop (dev) [half size][11], log_qratio (dev) [half size]
  * (log q(theta|theta') - log q(theta'|theta); 0 for the symmetric DE move).

@@ -66,18 +66,18 @@ __device__ __forceinline__ void adj_links(const Chan& c, const double (&D)[6], d
 }
 
 // Adjoint of one arm's contribution y_F += sinc(a(1-kn)) G, y_B += sinc(a(1+kn)) G
-// with G = (E e) P, P = (aP (np^2 - nq^2), aC 2 np nq).  Accumulates the
-// adjoints of E, aP, aC and returns those of the arm's e = (c, s), kn, np, nq.
+// with G = W e, W = pp (aP E) + i pc (2 aC E), pp = np^2 - nq^2, pc = np nq.
+// Accumulates the adjoints of aP E and 2 aC E and returns those of the arm's
+// e = (c, s), kn, np, nq.
 template <bool LS>
-__device__ __forceinline__ void adj_arm(const double (&yb)[4], double a, double Er, double Ei, double c,
-                                        double s, double np, double nq, double kn, double aP, double aC,
-                                        double& Ebr, double& Ebi, double& aPb, double& aCb, double& cb,
+__device__ __forceinline__ void adj_arm(const double (&yb)[4], double a, double pEr, double pEi, double cEr,
+                                        double cEi, double c, double s, double np, double nq, double kn,
+                                        double& pEbr, double& pEbi, double& cEbr, double& cEbi, double& cb,
                                         double& sb, double& knb, double& npb, double& nqb) {
-  const double Qr = fma(Er, c, -(Ei * s)), Qi = fma(Er, s, Ei * c);
-  const double pp = fma(np, np, -(nq * nq)), pc = 2.0 * np * nq;
-  const double Pr = aP * pp, Pi = aC * pc;
-  const double Gr = fma(Qr, Pr, -(Qi * Pi)), Gi = fma(Qr, Pi, Qi * Pr);
-  const double bf = a * (1.0 - kn), bb = a * (1.0 + kn);
+  const double pp = fma(np, np, -(nq * nq)), pc = np * nq;
+  const double Wr = fma(pp, pEr, -(pc * cEi)), Wi = fma(pp, pEi, pc * cEr);
+  const double Gr = fma(Wr, c, -(Wi * s)), Gi = fma(Wr, s, Wi * c);
+  const double bf = fma(-a, kn, a), bb = fma(a, kn, a);
   double sf, dsf, sbk, dsb;
   if (LS) {
     horner_d<1>(kSincLong, bf * bf, sf, dsf);
@@ -90,16 +90,18 @@ __device__ __forceinline__ void adj_arm(const double (&yb)[4], double a, double 
   const double Gbr = fma(sf, yb[0], sbk * yb[2]), Gbi = fma(sf, yb[1], sbk * yb[3]);
   // d sinc(b)/db = 2 b P'(b^2)
   knb = 2.0 * a * fma(sbb * bb, dsb, -(sfb * bf * dsf));
-  const double Qbr = fma(Gbr, Pr, Gbi * Pi), Qbi = fma(Gbi, Pr, -(Gbr * Pi));
-  const double Pbr = fma(Gbr, Qr, Gbi * Qi), Pbi = fma(Gbi, Qr, -(Gbr * Qi));
-  aPb = fma(Pbr, pp, aPb);
-  aCb = fma(Pbi, pc, aCb);
-  npb = 2.0 * fma(Pbr * aP, np, Pbi * aC * nq);
-  nqb = 2.0 * fma(Pbi * aC, np, -(Pbr * aP * nq));
-  Ebr = fma(Qbr, c, fma(Qbi, s, Ebr));
-  Ebi = fma(Qbi, c, fma(-Qbr, s, Ebi));
-  cb = fma(Qbr, Er, Qbi * Ei);
-  sb = fma(Qbi, Er, -(Qbr * Ei));
+  // G = W e
+  const double Wbr = fma(Gbr, c, Gbi * s), Wbi = fma(Gbi, c, -(Gbr * s));
+  cb = fma(Gbr, Wr, Gbi * Wi);
+  sb = fma(Gbi, Wr, -(Gbr * Wi));
+  // W = pp (pEr, pEi) + pc (-cEi, cEr)
+  const double ppb = fma(Wbr, pEr, Wbi * pEi), pcb = fma(Wbi, cEr, -(Wbr * cEi));
+  pEbr = fma(Wbr, pp, pEbr);
+  pEbi = fma(Wbi, pp, pEbi);
+  cEbr = fma(Wbi, pc, cEbr);
+  cEbi = fma(-Wbr, pc, cEbi);
+  npb = fma(2.0 * np, ppb, nq * pcb);
+  nqb = fma(-2.0 * nq, ppb, np * pcb);
 }
 
 // Adjoint of mode j's unit of (walker, bin, detector) given the link adjoints
@@ -149,7 +151,7 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
     dtap = -300.0 * (u * u) * (um * um);
   }
   const double amp = amp0 * tap;
-  const double aP = amp * wm(M_KP), aC = amp * wm(M_KC);
+  const double aP = amp * wm(M_KP), aC2 = amp * wm(M_KC);   // the table holds 2 K_x
   double sa, ca, ua, ub;
   sincos_cycles(tau * inv_year + wd(D_AO), sa, ca);
   if (GEO) {
@@ -168,7 +170,8 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   const double kR = fma(wd(D_KR), ca, wd(D_KR + 1) * sa);
   double sp, cp;
   sincos_cycles(fma(b.f, kR, phase), sp, cp);
-  const double Er = cp, Ei = -sp;
+  const double pEr = aP * cp, pEi = -(aP * sp);
+  const double cEr = aC2 * cp, cEi = -(aC2 * sp);
   double s0, c0, s1, c1;
   const double pi_f = kPi * b.f;
   if (LS) {
@@ -181,11 +184,16 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   const double c2 = fma(c0, c1, -(s0 * s1)), s2 = -fma(s0, c1, c0 * s1);
 
   // ---- reverse: arms
-  double Ebr = 0.0, Ebi = 0.0, aPb = 0.0, aCb = 0.0;
+  double pEbr = 0.0, pEbi = 0.0, cEbr = 0.0, cEbi = 0.0;
   double cb0, sb0, knb0, npb0, nqb0, cb1, sb1, knb1, npb1, nqb1, cb2, sb2, knb2, npb2, nqb2;
-  adj_arm<LS>(yb[0], a, Er, Ei, c0, s0, np0, nq0, kn0, aP, aC, Ebr, Ebi, aPb, aCb, cb0, sb0, knb0, npb0, nqb0);
-  adj_arm<LS>(yb[1], a, Er, Ei, c1, s1, np1, nq1, kn1, aP, aC, Ebr, Ebi, aPb, aCb, cb1, sb1, knb1, npb1, nqb1);
-  adj_arm<LS>(yb[2], a, Er, Ei, c2, s2, np2, nq2, kn2, aP, aC, Ebr, Ebi, aPb, aCb, cb2, sb2, knb2, npb2, nqb2);
+  adj_arm<LS>(yb[0], a, pEr, pEi, cEr, cEi, c0, s0, np0, nq0, kn0, pEbr, pEbi, cEbr, cEbi, cb0, sb0, knb0, npb0, nqb0);
+  adj_arm<LS>(yb[1], a, pEr, pEi, cEr, cEi, c1, s1, np1, nq1, kn1, pEbr, pEbi, cEbr, cEbi, cb1, sb1, knb1, npb1, nqb1);
+  adj_arm<LS>(yb[2], a, pEr, pEi, cEr, cEi, c2, s2, np2, nq2, kn2, pEbr, pEbi, cEbr, cEbi, cb2, sb2, knb2, npb2, nqb2);
+  // aP E, 2 aC E with E = (cp, -sp)
+  const double aPb = fma(pEbr, cp, -(pEbi * sp));
+  const double aCb = fma(cEbr, cp, -(cEbi * sp));
+  const double cpb = fma(pEbr, aP, cEbr * aC2);
+  const double spb = -fma(pEbi, aP, cEbi * aC2);
   // the third arm follows from the other two
   knb0 -= knb2;
   knb1 -= knb2;
@@ -200,8 +208,8 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   // arm phases pi f kd_t (radians)
   const double kdb0 = pi_f * fma(sb0, c0, -(cb0 * s0));
   const double kdb1 = pi_f * fma(sb1, c1, -(cb1 * s1));
-  // common phase (cycles): E = (cos, -sin)(2 pi Phi), Phi = f kR + phase
-  const double Phib = -kTwoPi * fma(Ebi, cp, Ebr * sp);
+  // common phase (cycles): (sp, cp) = (sin, cos)(2 pi Phi), Phi = f kR + phase
+  const double Phib = kTwoPi * fma(spb, cp, -(cpb * sp));
   const double kRb = b.f * Phib;
   // ---- projections: P = c0 ua + c1 ub + c2 ca + c3 sa + c4
   double uab = 0.0, ubb = 0.0, cab = kRb * wd(D_KR), sab = kRb * wd(D_KR + 1);
@@ -244,7 +252,7 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   // ---- amplitude, polarization, taper
   DepIota::add(g, aPb * amp, tm(M_KP));
   DepIota::add(g, aCb * amp, tm(M_KC));
-  const double ampb = fma(aPb, wm(M_KP), aCb * wm(M_KC));
+  const double ampb = fma(aPb, wm(M_KP), aCb * wm(M_KC));   // aCb: adjoint of 2 aC
   const double xb = ampb * amp0 * dtap;
   const double qa = ampb * tap * b.fm76;
   DepMQD::add(g, qa, tm(M_AM0));

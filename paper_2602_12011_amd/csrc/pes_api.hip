@@ -753,6 +753,29 @@ int pes_sampler_chain(pes_sampler* s, const double** chain) {
   return PES_OK;
 }
 
+int pes_sampler_read_chain(pes_sampler* s, double* out, int64_t* n_states, void* stream) {
+  if (!s || !out || !n_states) return PES_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  PES_HIP(s->ctx, hipStreamSynchronize(st));
+  uint64_t step = 0;
+  PES_HIP(s->ctx, hipMemcpy(&step, s->step, sizeof(uint64_t), hipMemcpyDeviceToHost));
+  const int64_t L = s->chain_len;
+  const int64_t n = std::min<int64_t>((int64_t)step, L);
+  *n_states = n;
+  if (n == 0) return PES_OK;
+  const size_t row = sizeof(double) * s->B * 11;
+  if ((int64_t)step <= L) {
+    PES_HIP(s->ctx, hipMemcpyAsync(out, s->chain, row * n, hipMemcpyDeviceToDevice, st));
+  } else {   // ring: the oldest state sits at step % L
+    const int64_t o = (int64_t)(step % (uint64_t)L);
+    PES_HIP(s->ctx, hipMemcpyAsync(out, s->chain + o * s->B * 11, row * (L - o), hipMemcpyDeviceToDevice, st));
+    if (o > 0)
+      PES_HIP(s->ctx, hipMemcpyAsync(out + (L - o) * s->B * 11, s->chain, row * o, hipMemcpyDeviceToDevice, st));
+  }
+  PES_HIP(s->ctx, hipStreamSynchronize(st));
+  return PES_OK;
+}
+
 int pes_propose(pes_sampler* s, int kind, int half, double* theta_prop, double* log_qratio, void* stream) {
   if (!s || !theta_prop || !log_qratio || (half != 0 && half != 1) ||
       (kind != PES_PROPOSE_DE && kind != PES_PROPOSE_FLOW))

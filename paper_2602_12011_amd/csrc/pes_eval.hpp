@@ -134,7 +134,7 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
       amp *= fma(-(u * u * u), fma(u, fma(6.0, u, -15.0), 10.0), 1.0);
     }
     const S aP = amp * wm(M_KP);
-    const S aC = amp * wm(M_KC);
+    const S aC2 = amp * wm(M_KC);   // the table holds 2 K_x
     // spacecraft geometry at t_f
     S sa, ca;
     sincos_cycles(tau * inv_year + wd(D_AO), sa, ca);
@@ -156,7 +156,9 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
     // mode phase plus the Roemer delay of the centre: E = e^{-2 pi i (phase + f k.R)}
     S sp, cp;
     sincos_cycles(fma(b.f, kR, phase), sp, cp);
-    const S Er = cp, Ei = -sp;
+    // polarization amplitudes times E = (cp, -sp): aP E and 2 aC E
+    const S pEr = aP * cp, pEi = -(aP * sp);
+    const S cEr = aC2 * cp, cEi = -(aC2 * sp);
     // per-arm phase e^{+i pi f k.Delta_t} of the spacecraft opposite arm t
     S s0, c0, s1, c1;
     if (LONG_SINC) {
@@ -168,12 +170,14 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
     }
     const S c2 = fma(c0, c1, -(s0 * s1)), s2 = -fma(s0, c1, c0 * s1);
 
+// One arm: W = E (aP (n.p)^2 - (n.q)^2) + i 2 aC (n.p)(n.q)), G = W e_arm,
+// y_F += sinc(a (1 - k.n)) G, y_B += sinc(a (1 + k.n)) G.
 #define PES_ARM(er, ei, np, nq, kn, FR, FI, BR, BI)                    \
   {                                                                   \
-    const S Qr = fma(Er, er, -(Ei * ei)), Qi = fma(Er, ei, Ei * er); \
-    const S Pr = aP * fma(np, np, -(nq * nq)), Pi = aC * 2.0 * np * nq; \
-    const S Gr = fma(Qr, Pr, -(Qi * Pi)), Gi = fma(Qr, Pi, Qi * Pr); \
-    const S sf = sinc<LONG_SINC>(a * (1.0 - kn)), sb = sinc<LONG_SINC>(a * (1.0 + kn)); \
+    const S pp = fma(np, np, -(nq * nq)), pc = np * nq;               \
+    const S Wr = fma(pp, pEr, -(pc * cEi)), Wi = fma(pp, pEi, pc * cEr); \
+    const S Gr = fma(Wr, er, -(Wi * ei)), Gi = fma(Wr, ei, Wi * er); \
+    const S sf = sinc<LONG_SINC>(fma(-a, kn, a)), sb = sinc<LONG_SINC>(fma(a, kn, a)); \
     FR = fma(sf, Gr, FR);                                             \
     FI = fma(sf, Gi, FI);                                             \
     BR = fma(sb, Gr, BR);                                             \

@@ -279,7 +279,7 @@ __device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put)
     ylm_pair(l, m, iota, yp, ym);
     const double sgn = (l & 1) ? -1.0 : 1.0;
     put(M0 + M_KP, 0.5 * (ym + sgn * yp));
-    put(M0 + M_KC, 0.5 * (ym - sgn * yp));
+    put(M0 + M_KC, ym - sgn * yp);   // 2 K_x
     const T fcut = (0.5 * mm * kMfIsco) / M;
     put(M0 + M_FCI, 1.0 / fcut);
     fmx = fmx > val(fcut) ? fmx : val(fcut);

@@ -29,7 +29,7 @@ enum : int {
 // t_f - t_c [s]:
 //   T0 w^8 + T2 w^6 + T3 w^5 + T4 w^4 + T5 w^3 + (T6 + T6L ln v) w^2 + T7 w
 // Amplitude: f^{-7/6} (AM0 + AM1 v + AM2 v^2) x taper(f * FCI); polarization
-// h_+ = KP amp e^{-i phase}, h_x = i KC amp e^{-i phase}.
+// h_+ = KP amp e^{-i phase}, h_x = i (KC / 2) amp e^{-i phase} (KC holds 2 K_x).
 enum : int {
   M_CM = 0, M_CMI, M_LNCM, M_C0, M_A0, M_A2, M_A3, M_A4, M_B5, M_A6, M_B6, M_A7,
   M_T0, M_T2, M_T3, M_T4, M_T5, M_T6, M_T6L, M_T7, M_AM0, M_AM1, M_AM2, M_KP, M_KC, M_FCI

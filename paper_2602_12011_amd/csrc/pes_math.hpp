@@ -21,8 +21,11 @@ __device__ __forceinline__ double horner(const double (&c)[N], double t) {
 }
 
 // sin(2 pi x), cos(2 pi x) for any finite x given in cycles.
-// r = x - rint(x) in [-1/2, 1/2], quadrant q = rint(4 r), y = r - q/4 in
-// [-1/8, 1/8] (both exact), then the fitted polynomials and a quadrant swap.
+// r = x - rint(x) in [-1/2, 1/2], quadrant q = rint(4 r) in {-2, ..., 2},
+// y = r - q/4 in [-1/8, 1/8] (all exact), then the fitted polynomials and the
+// rotation by q quarter turns, (cos, sin)(q pi/2) = (1 - |q|, q (2 - |q|)):
+// products with 0 and +-1, so exact, and FP64 arithmetic instead of integer
+// selects.
 __device__ __forceinline__ void sincos_cycles(double x, double& s, double& c) {
   const double r = x - rint(x);
   const double q = rint(4.0 * r);
@@ -30,11 +33,11 @@ __device__ __forceinline__ void sincos_cycles(double x, double& s, double& c) {
   const double t = y * y;
   const double sy = y * horner(kSin2pi, t);
   const double cy = horner(kCos2pi, t);
-  const int qi = static_cast<int>(q) & 3;
-  const double ss = (qi & 1) ? cy : sy;
-  const double cc = (qi & 1) ? sy : cy;
-  s = (qi & 2) ? -ss : ss;
-  c = ((qi + 1) & 2) ? -cc : cc;
+  const double aq = fabs(q);
+  const double cq = 1.0 - aq;
+  const double sq = q * (2.0 - aq);
+  s = fma(sy, cq, cy * sq);
+  c = fma(cy, cq, -(sy * sq));
 }
 
 // sin(b)/b as a polynomial in b^2.  LONG selects the fit valid to b = 4

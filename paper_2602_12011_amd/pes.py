@@ -83,6 +83,7 @@ def lib():
         L.pes_flow_last_error.argtypes = [vp]
         L.pes_flow_last_error.restype = C.c_char_p
         L.pes_sampler_set_flow.argtypes = [vp, vp, C.c_double]
+        L.pes_sampler_read_chain.argtypes = [vp, vp, C.POINTER(C.c_int64), vp]
         L.pes_sampler_create.argtypes = [vp, C.POINTER(Prior), C.c_int64, C.c_uint64, C.c_int64,
                                          C.POINTER(vp)]
         L.pes_sampler_destroy.argtypes = [vp]
@@ -107,6 +108,7 @@ def lib():
                      "pes_flow_create", "pes_flow_destroy", "pes_flow_set_params", "pes_flow_get_params",
                      "pes_flow_set_norm", "pes_flow_get_norm", "pes_flow_forward", "pes_flow_inverse",
                      "pes_flow_nll_grad", "pes_flow_adam_step", "pes_flow_fit", "pes_sampler_set_flow",
+                     "pes_sampler_read_chain",
                      "pes_fisher", "pes_sampler_create", "pes_sampler_destroy",
                      "pes_sampler_set_state", "pes_sampler_step", "pes_sampler_capture",
                      "pes_sampler_launch", "pes_sampler_state", "pes_sampler_chain", "pes_propose",
@@ -354,6 +356,14 @@ class Sampler:
         p = C.c_void_p()
         self.ctx._check(lib().pes_sampler_chain(self.h, C.byref(p)), "pes_sampler_chain")
         return p.value
+
+    def read_chain(self, stream=None):
+        """Stored states, oldest first: [n_states, n_walkers, 11] tensor."""
+        out = torch.empty((max(self.chain_len, 1), self.B, 11), dtype=torch.float64, device="cuda")
+        n = C.c_int64()
+        self.ctx._check(lib().pes_sampler_read_chain(self.h, _dev_f64(out, "out"), C.byref(n), _stream(stream)),
+                        "pes_sampler_read_chain")
+        return out[:n.value]
 
     def propose(self, half, kind="de", stream=None):
         """Proposals of the given half: "de", or "flow" (the mixture set by set_flow)."""

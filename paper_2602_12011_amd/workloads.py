@@ -57,7 +57,9 @@ def config(name, n_bins=None):
            1000 walkers (the small case the oracle runs in full);
     cfg1   one LISA-like detector, five modes, 2^20 bins at df = 1/yr, 4096 walkers;
     cfg2   LISA + Taiji + TianQin, five modes, 2^20 bins, 16384 walkers;
-    cfg3   cfg1's signal, 1024 walkers for gradients, 256 for Fisher matrices.
+    cfg3   cfg1's signal, 1024 walkers for gradients, 256 for Fisher matrices;
+    cfg4   cfg2's network and grid, 16384 walkers, with the learned proposal
+           (11-D flow, 8 coupling layers of width 256).
     ``n_bins`` shortens the grid (same start and spacing) for quick tests.
     """
     if name == "cfg0":
@@ -71,6 +73,9 @@ def config(name, n_bins=None):
     elif name == "cfg3":
         c = dict(detectors=[LISA], modes=MODES_HM, walkers=1024, fisher_points=256,
                  **grid_rfft(1 << 20))
+    elif name == "cfg4":
+        c = dict(detectors=[LISA, TAIJI, TIANQIN], modes=MODES_HM, walkers=16384,
+                 flow=dict(layers=8, width=256), **grid_rfft(1 << 20))
     else:
         raise KeyError(name)
     c["name"] = name
