@@ -34,8 +34,8 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6     # MI355X FP64 vector peak (AMD specification)
 # detector) for the TDI combination and the inner products.  Not counted: the
 # C^2 taper (the last 10% below each cutoff) and the quarter-turn rotation of
 # the sine/cosine reduction (products with 0 and +-1).
-FLOPS_PER_MODE_UNIT = {("helio", False): 454, ("geo", False): 481,
-                       ("helio", True): 486, ("geo", True): 513}
+FLOPS_PER_MODE_UNIT = {("helio", False): 442, ("geo", False): 469,
+                       ("helio", True): 474, ("geo", True): 501}
 FLOPS_PER_WBD_UNIT = 83
 MF_ISCO = 6.0 ** -1.5 / math.pi
 MSUN_S = 4.925490947641267e-6

@@ -1006,8 +1006,8 @@ __global__ void grad_finalize_kernel(const double* __restrict__ partial, const d
   if (logl) logl[b] = (s[kNParams] - 0.5 * s[kNParams + 1]) - 0.5 * dd[0];
 }
 
-// Fisher matrix: the 16 x 16 matrix-core accumulator of each tile is held as
-// lane l, element r <-> (row 4 (l / 16) + r, column l % 16); tiles summed in
+// Fisher matrix: the 16 x 16 FP64 matrix-core accumulator of each tile is held
+// as lane l, element r <-> (row 4 r + l / 16, column l % 16); tiles summed in
 // order, the leading 11 x 11 block written out.
 __global__ void fisher_finalize_kernel(const double* __restrict__ partial, const double* __restrict__ wtab,
                                        JacArgs A, double* __restrict__ F) {
@@ -1015,7 +1015,7 @@ __global__ void fisher_finalize_kernel(const double* __restrict__ partial, const
   const int e = threadIdx.x;   // 0..255: lane = e / 4, r = e % 4
   const double* wt = wtab + (int64_t)b * W_STRIDE;
   const int lane = e >> 2, r = e & 3;
-  const int row = 4 * (lane >> 4) + r, col = lane & 15;
+  const int row = 4 * r + (lane >> 4), col = lane & 15;
   double s = 0.0;
   if (wt[W_VALID] != 0.0) {
     const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
