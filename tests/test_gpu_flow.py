@@ -1,11 +1,17 @@
 """The learned proposal on the GPU (pes_flow_*, pes_sampler_set_flow through the
 C-ABI) against the flow reference with the same BF16-rounded weights.
 
-Tolerances: the GPU accumulates in FP32 and may round a hidden activation to
-the other neighbouring BF16 value than the FP64 reference does; one such flip
-moves an output by ~1e-4 relative, so values are compared at 1e-3 relative
-(log q at 2e-3 max(1, |log q|)); gradients, whose back-propagated operands are
-BF16 as well, per tensor by norm at 2e-2.
+Tolerances: the GPU accumulates in FP32 and may round a network input or a
+hidden activation to the other neighbouring BF16 value than the FP64 reference
+does.  A flipped hidden activation moves an output by ~1e-4 relative; a flipped
+conditioner input (one BF16 step, 2^-8 relative) by up to ~1e-2, and this
+happens to a few rows in a thousand (an FP32 emulation of the same arithmetic
+against the reference: median row error 2.5e-7, 99th percentile 4.5e-5, 0.26%
+of rows above 1e-3, largest 2e-2).  Rows are therefore compared by their
+distribution: median <= 1e-5, at most 1% above 1e-3 (log q: 2e-3), none above
+0.1, which no rounding flip reaches but any wrong weight, layer or mask does.
+Gradients, whose back-propagated operands are BF16 as well, are compared per
+tensor by norm at 2e-2.
 """
 import math
 
@@ -36,6 +42,17 @@ def F():
     return flow
 
 
+def _check_rows(err, tol, what):
+    """err [rows]: per-row relative error (see the module docstring); fewer
+    than 50 rows are held to tol row by row."""
+    med, frac, mx = float(np.median(err)), float(np.mean(err > tol)), float(err.max())
+    print(f"{what}: median {med:.2e}, above {tol:g}: {frac:.4f}, max {mx:.2e}")
+    if err.size < 50:
+        assert mx <= tol, (what, mx)
+    else:
+        assert med <= 1e-5 and frac <= 0.01 and mx <= 0.1, (what, med, frac, mx)
+
+
 def _flow_with(pes, torch, flat, mu, sigma):
     f = pes.Flow(seed=1)
     assert f.n_params == flat.size
@@ -61,8 +78,8 @@ def test_forward_matches_reference(torch_dev, pes, F, n):
     f.close()
     z_or, _ = F.forward(flat, F.standardize(th, mu, sigma))
     lq_or = F.log_prob(flat, th, mu, sigma)
-    assert np.all(np.abs(z - z_or) <= 1e-3 * np.maximum(1.0, np.abs(z_or)))
-    assert np.all(np.abs(lq - lq_or) <= 2e-3 * np.maximum(1.0, np.abs(lq_or))), np.abs(lq - lq_or).max()
+    _check_rows((np.abs(z - z_or) / np.maximum(1.0, np.abs(z_or))).max(axis=1), 1e-3, f"z, n={n}")
+    _check_rows(np.abs(lq - lq_or) / np.maximum(1.0, np.abs(lq_or)), 2e-3, f"log q, n={n}")
 
 
 def test_inverse_matches_reference_and_round_trips(torch_dev, pes, F):
@@ -77,9 +94,10 @@ def test_inverse_matches_reference_and_round_trips(torch_dev, pes, F):
     f.close()
     u_or, ld_or = F.inverse(flat, z.astype(np.float32).astype(np.float64))
     u = (th - mu) / sigma
-    assert np.all(np.abs(u - u_or) <= 1e-3 * np.maximum(1.0, np.abs(u_or)))
-    assert np.all(np.abs(ld.cpu().numpy() - ld_or) <= 2e-3 * np.maximum(1.0, np.abs(ld_or)))
-    assert np.abs(z2 - z).max() < 1e-4
+    _check_rows((np.abs(u - u_or) / np.maximum(1.0, np.abs(u_or))).max(axis=1), 1e-3, "u")
+    _check_rows(np.abs(ld.cpu().numpy() - ld_or) / np.maximum(1.0, np.abs(ld_or)), 2e-3, "log det")
+    # round trip through the GPU's own maps: FP32 rounding only, plus the rare BF16 flip
+    _check_rows((np.abs(z2 - z) / np.maximum(1.0, np.abs(z))).max(axis=1), 1e-4, "round trip")
 
 
 def test_identity_flow_is_the_standardized_gaussian(torch_dev, pes, F):
@@ -196,10 +214,12 @@ def test_mixture_proposals_match_reference(orc, torch_dev, pes, F):
         assert np.allclose(prop[~flow_rows], rprop[~flow_rows], rtol=1e-13, atol=0)
         uf = (prop[flow_rows] - mu) / sigma
         ur = (rprop[flow_rows] - mu) / sigma
-        assert np.all(np.abs(uf - ur) <= 1e-3 * np.maximum(1.0, np.abs(ur)))
+        err = (np.abs(uf - ur) / np.maximum(1.0, np.abs(ur))).max(axis=1)
+        assert np.median(err) <= 1e-5 and np.sum(err > 1e-3) <= 1 and err.max() <= 0.1, err
         fin = np.isfinite(rq[flow_rows])
         assert np.array_equal(fin, np.isfinite(q[flow_rows]))
-        assert np.all(np.abs(q[flow_rows][fin] - rq[flow_rows][fin]) <= 5e-3 * np.maximum(1.0, np.abs(rq[flow_rows][fin])))
+        eq = np.abs(q[flow_rows][fin] - rq[flow_rows][fin]) / np.maximum(1.0, np.abs(rq[flow_rows][fin]))
+        assert np.median(eq) <= 1e-5 and np.sum(eq > 5e-3) <= 1 and eq.max() <= 0.1, eq
     smp.close()
     f.close()
     ctx.close()
@@ -245,6 +265,7 @@ def test_graph_replay_with_flow_is_bitwise_eager(orc, torch_dev, pes, F):
     with torch.cuda.stream(s):
         b.capture(s)
     a.step(4)
+    torch.cuda.synchronize()   # a and b share the context and the flow: one at a time
     for _ in range(4):
         b.launch(1, s)
         s.synchronize()

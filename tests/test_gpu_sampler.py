@@ -109,6 +109,7 @@ def test_graph_replay_is_bitwise_eager(orc, torch_dev, pes):
     with torch.cuda.stream(s):
         b.capture(s)
     a.step(5)
+    torch.cuda.synchronize()   # a and b share the context's workspace: one at a time
     for _ in range(5):
         b.launch(1, s)
         s.synchronize()
