@@ -209,10 +209,13 @@ def _fisher_start(ctx, torch, B, seed):
     return np.clip(x, lo + eps, hi - eps)
 
 
-def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps):
+def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps, tau=1.1, fit_batch=1024):
     """ESS/s of the plain DE-MC sampler against the mixture with the learned
-    flow (p_flow 0.9), equal numbers of steps from the same starting ensemble,
-    on the three-detector network (cfg4's likelihood at B walkers)."""
+    flow (p_flow 0.9, temperature tau), equal numbers of steps from the same
+    burned-in ensemble, on the three-detector network (cfg4's likelihood at B
+    walkers).  Accuracy: the largest per-parameter KS distance between the
+    mixture's and the plain run's draws against the one between the plain run
+    and an independent plain run (own start, own burn-in of the same length)."""
     from paper_2602_12011_amd import diagnostics as D
     cfg = W.config("cfg4")
     dev = torch.device("cuda:0")
@@ -220,10 +223,9 @@ def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps):
     th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
     ctx.set_data(ctx.response(th0)[0].clone())
     prior = _prior_spec()
-    start = torch.from_numpy(_fisher_start(ctx, torch, B, 12)).to(dev)
     # pilot DE run: burn-in and training samples
     pilot = pes.Sampler(ctx, prior, B, 101, chain_len=n_pilot)
-    pilot.set_state(start)
+    pilot.set_state(torch.from_numpy(_fisher_start(ctx, torch, B, 12)).to(dev))
     t0 = time.perf_counter()
     pilot.step(n_pilot)
     torch.cuda.synchronize()
@@ -233,17 +235,32 @@ def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps):
     pilot.close()
     half = ch[n_pilot // 2:]
     rhat = float(D.gelman_rubin(half).max())
-    train = torch.from_numpy(half.reshape(-1, 11).copy()).to(dev)
+    # distinct states only (rejected moves repeat a state), 10% held out
+    uniq = np.unique(half.reshape(-1, 11), axis=0)
+    rng = np.random.default_rng(5)
+    rng.shuffle(uniq)
+    n_val = max(len(uniq) // 10, 1)
+    val, train = uniq[:n_val], uniq[n_val:]
     flow = pes.Flow(seed=7)
     t0 = time.perf_counter()
-    loss = flow.fit(train, steps=fit_steps, batch=min(4096, train.shape[0]), lr=1e-3, seed=3)
+    loss = flow.fit(torch.from_numpy(train).to(dev), steps=fit_steps, batch=min(fit_batch, len(train)), lr=1e-3,
+                    seed=3)
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t0
-    results = {}
-    chains = {}
-    for name, seed, use_flow in (("plain", 202, False), ("plain_b", 303, False), ("learned", 202, True)):
+    nll_val = float(flow.nll_grad(torch.from_numpy(val).to(dev))[0].cpu())
+    flow.set_temperature(tau)
+    results, chains = {}, {}
+    runs = (("plain", 202, False, state), ("learned", 202, True, state),
+            ("plain_independent", 303, False, None))
+    for name, seed, use_flow, start in runs:
+        if start is None:   # independent run: own Fisher start and burn-in
+            burn = pes.Sampler(ctx, prior, B, seed + 1)
+            burn.set_state(torch.from_numpy(_fisher_start(ctx, torch, B, 13)).to(dev))
+            burn.step(n_pilot)
+            start = burn.state()[0].clone()
+            burn.close()
         smp = pes.Sampler(ctx, prior, B, seed, chain_len=n_run)
-        smp.set_state(state)
+        smp.set_state(start)
         if use_flow:
             smp.set_flow(flow, 0.9)
         torch.cuda.synchronize()
@@ -259,18 +276,22 @@ def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps):
                              ess_min=round(float(e.min()), 1), ess_per_s=round(float(e.min()) / dt, 2))
     flow.close()
     ctx.close()
-    flat = {k: v.reshape(-1, 11) for k, v in chains.items()}
+    flat = {k: v[n_run // 2:].reshape(-1, 11) for k, v in chains.items()}
     ks_lp = max(D.ks_distance(flat["learned"][:, j], flat["plain"][:, j]) for j in range(11))
-    ks_pp = max(D.ks_distance(flat["plain_b"][:, j], flat["plain"][:, j]) for j in range(11))
+    ks_pp = max(D.ks_distance(flat["plain_independent"][:, j], flat["plain"][:, j]) for j in range(11))
     gain = results["learned"]["ess_per_s"] / max(results["plain"]["ess_per_s"], 1e-30)
     amort = results["learned"]["ess_min"] / (results["learned"]["seconds"] + t_fit)
     return dict(workload=f"LISA+Taiji+TianQin, 5 modes, 2^20 bins, {B} walkers, noise-free injection; "
-                         f"{n_pilot}-step DE pilot (second half trains the flow), then {n_run} steps each",
-                pilot_seconds=round(t_pilot, 2), pilot_rhat_max=round(rhat, 4), fit_seconds=round(t_fit, 2),
+                         f"{n_pilot}-step DE pilot (distinct states of its second half train the flow), "
+                         f"then {n_run} steps each",
+                pilot_seconds=round(t_pilot, 2), pilot_rhat_max=round(rhat, 4),
+                train_rows=int(len(train)), fit_seconds=round(t_fit, 2),
                 fit_loss_first_last=[round(float(loss[0]), 3), round(float(loss[-1]), 3)],
-                plain=results["plain"], learned=results["learned"], gain=round(gain, 2),
+                heldout_nll=round(nll_val, 3), temperature=tau,
+                plain=results["plain"], learned=results["learned"],
+                plain_independent=results["plain_independent"], gain=round(gain, 2),
                 learned_ess_per_s_with_training=round(amort, 2),
-                ks_learned_vs_plain=round(ks_lp, 4), ks_plain_vs_plain=round(ks_pp, 4),
+                ks_learned_vs_plain=round(ks_lp, 4), ks_independent_plain_vs_plain=round(ks_pp, 4),
                 accuracy_ok=bool(ks_lp <= 1.5 * ks_pp))
 
 
@@ -289,9 +310,9 @@ def main():
     ap.add_argument("--extras", default="derivatives,graph,ess",
                     help="comma list of the extra legs to run after the headline")
     ap.add_argument("--ess-walkers", type=int, default=1024)
-    ap.add_argument("--ess-pilot", type=int, default=300)
+    ap.add_argument("--ess-pilot", type=int, default=1000)
     ap.add_argument("--ess-steps", type=int, default=300)
-    ap.add_argument("--ess-fit-steps", type=int, default=1500)
+    ap.add_argument("--ess-fit-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()

@@ -196,30 +196,38 @@ int pes_propose(pes_sampler* s, int kind, int half, double* theta_prop, double* 
 /* ---- Learned proposal.  An affine-coupling normalizing flow q(theta) on the
  * 11 parameters, trained on posterior samples and used as an independence
  * Metropolis-Hastings proposal mixed with the DE move (the proposal is the
- * sampler's choice, Sec. 2.2).  Definition: u = float((theta - mu) / sigma);
+ * sampler's choice, Sec. 2.2).  Definition: u = float(L^-1 (theta - mu)) with
+ * L lower triangular (whitening; forward substitution in FP64);
  * 8 layers, layer 2p conditions on C_p = {i : (i + 3p) mod 11 < 6} and
  * transforms the rest, layer 2p + 1 conditions on the rest and transforms
  * C_p; conditioner networks n_C -> 256 (ReLU) -> 256 (ReLU) -> 2 n_T with
  * outputs (s_hat, t), s = 3 tanh(s_hat / 3); normalizing map y_T = x_T e^s + t;
- * base N(0, I); log q(theta) = log N(z) + sum s - sum log sigma.  Network
+ * base N(0, I); log q(theta) = log N(z) + sum s - sum log L_kk.  Network
  * products take BF16 operands (weights, inputs, hidden activations rounded to
  * nearest even) with FP32 accumulation on the matrix cores; FP32 master
  * weights; Adam (beta 0.9, 0.999, eps 1e-8).  Parameters: per layer W1
  * [n_C][256], b1 [256], W2 [256][256], b2 [256], W3 [256][2 n_T], b3 [2 n_T]
  * (y = x W + b), flat FP32 in that order, pes_flow_num_params() in total. */
 typedef struct pes_flow pes_flow;
-int pes_flow_create(uint64_t seed, pes_flow** out);   /* random init, near identity; mu 0, sigma 1 */
+int pes_flow_create(uint64_t seed, pes_flow** out);   /* random init, near identity; mu 0, L = I */
 int pes_flow_destroy(pes_flow* f);
 int64_t pes_flow_num_params(void);
 /* params (dev) FP32 [pes_flow_num_params()]; set also resets the Adam state. */
 int pes_flow_set_params(pes_flow* f, const float* params, void* stream);
 int pes_flow_get_params(pes_flow* f, float* params, void* stream);
-/* Standardization (host arrays [11]; sigma > 0, else PES_EINVAL). */
+/* Whitening map (host arrays): mu [11] and L [11][11] row-major, lower
+ * triangular (entries above the diagonal ignored), L_kk > 0, else PES_EINVAL.
+ * set_norm is the diagonal case L = diag(sigma). */
+int pes_flow_set_affine(pes_flow* f, const double* mu, const double* L);
+int pes_flow_get_affine(pes_flow* f, double* mu, double* L);
 int pes_flow_set_norm(pes_flow* f, const double* mu, const double* sigma);
-int pes_flow_get_norm(pes_flow* f, double* mu, double* sigma);
+/* Temperature tau > 0 of the base density N(0, tau^2 I) used by forward,
+ * inverse (latent tau z) and the sampler's proposals; training is unaffected
+ * (default 1; tau > 1 widens the proposal's tails). */
+int pes_flow_set_temperature(pes_flow* f, double tau);
 /* log q(theta) for theta (dev) [n][11] -> logq (dev) [n]; z (dev) [n][11] or NULL. */
 int pes_flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double* logq, void* stream);
-/* theta = inverse map of z (dev) [n][11]; logdet (dev) [n] or NULL: sum s at theta. */
+/* theta = inverse map of tau z, z (dev) [n][11]; logdet (dev) [n] or NULL: sum s at theta. */
 int pes_flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, double* logdet, void* stream);
 /* Mean negative log-likelihood of the rows of theta (dev) [n][11] in the
  * standardized space, -(1/n) sum log q_u(u_j), into nll (dev) [1] (may be
@@ -229,8 +237,10 @@ int pes_flow_nll_grad(pes_flow* f, const double* theta, int64_t n, double* nll, 
 int pes_flow_adam_step(pes_flow* f, const float* grad, float lr, void* stream);
 /* steps Adam updates on minibatches of `batch` rows of samples (dev) [n][11]
  * (drawn with replacement; all rows in order when batch == n); standardize
- * != 0 first sets mu, sigma to the samples' mean and standard deviation
- * (synchronizes).  loss (dev) [steps] or NULL receives each step's NLL. */
+ * != 0 first sets mu to the samples' mean and L to the Cholesky factor of
+ * their covariance (synchronizes; PES_EINVAL if it is not positive definite).
+ * The learning rate decays as lr (1 + cos(pi t / steps)) / 2.  loss (dev)
+ * [steps] or NULL receives each step's NLL. */
 int pes_flow_fit(pes_flow* f, const double* samples, int64_t n, int64_t steps, int64_t batch, float lr,
                  uint64_t seed, int standardize, double* loss, void* stream);
 const char* pes_flow_last_error(pes_flow* f);

@@ -11,7 +11,9 @@ points, so both sides evaluate the same function up to FP32 accumulation.
 Shares no code with the GPU library.
 
 Conventions (the paper gives none; these are the proposal's definition):
-  u = float32((theta - mu) / sigma); base density N(0, I_11).
+  u = float32(L^-1 (theta - mu)) with L lower triangular (a whitening map:
+  L L^T is a covariance; a vector sigma stands for L = diag(sigma)), the
+  triangular solve by forward substitution in FP64; base density N(0, I_11).
   8 layers.  Layer 2p conditions on C_p = {i : (i + 3p) mod 11 < 6} (6
   entries) and transforms the other 5; layer 2p + 1 conditions on those 5
   and transforms C_p.  Conditioner: x_C -> 256 (ReLU) -> 256 (ReLU) -> 2 n_T
@@ -20,7 +22,10 @@ Conventions (the paper gives none; these are the proposal's definition):
   Normalizing direction (u -> z), layers 0..7: y_T = x_T exp(s) + t,
   y_C = x_C, log det += sum s.
   log q_u(u) = -|z|^2 / 2 - (11/2) log(2 pi) + log det;
-  log q(theta) = log q_u(u) - sum log sigma.
+  log q(theta) = log q_u(u) - sum log L_ii.
+  A temperature tau widens the base density to N(0, tau^2 I): draws use
+  z = tau * (standard normal), rounded to FP32 after the product, and
+  log q_u(u) = -|z|^2 / (2 tau^2) - 11 log tau - (11/2) log(2 pi) + log det.
   Parameters per layer, y = x W + b: W1 [n_C, 256], b1 [256], W2 [256, 256],
   b2 [256], W3 [256, 2 n_T], b3 [2 n_T]; stored flat in that order, layer
   after layer (562264 numbers).
@@ -144,18 +149,39 @@ def inverse(flat, z, rnd=True):
     return x, logdet
 
 
-def log_prob_u(flat, u, rnd=True):
+def log_prob_u(flat, u, rnd=True, tau=1.0):
     z, ld = forward(flat, u, rnd)
-    return -0.5 * (z * z).sum(axis=1) - 0.5 * D * math.log(2.0 * math.pi) + ld
+    return (-0.5 * (z * z).sum(axis=1) / (tau * tau) - D * math.log(tau)
+            - 0.5 * D * math.log(2.0 * math.pi) + ld)
+
+
+def whitening(sigma):
+    """L from a vector of scales (diagonal) or a lower-triangular matrix."""
+    s = np.asarray(sigma, dtype=np.float64)
+    return np.diag(s) if s.ndim == 1 else np.tril(s)
 
 
 def standardize(theta, mu, sigma):
-    return ((np.asarray(theta, dtype=np.float64) - mu) / sigma).astype(np.float32).astype(np.float64)
+    """u = float32(L^-1 (theta - mu)), forward substitution row by row."""
+    L = whitening(sigma)
+    r = np.atleast_2d(np.asarray(theta, dtype=np.float64)) - mu
+    u = np.zeros_like(r)
+    for k in range(D):
+        acc = r[:, k].copy()
+        for j in range(k):
+            acc -= L[k, j] * u[:, j]
+        u[:, k] = acc / L[k, k]
+    return u.astype(np.float32).astype(np.float64)
 
 
-def log_prob(flat, theta, mu, sigma, rnd=True):
+def unstandardize(u, mu, sigma):
+    return mu + np.asarray(u, dtype=np.float64) @ whitening(sigma).T
+
+
+def log_prob(flat, theta, mu, sigma, rnd=True, tau=1.0):
     """log q(theta) of the proposal."""
-    return log_prob_u(flat, standardize(theta, mu, sigma), rnd) - np.log(sigma).sum()
+    return (log_prob_u(flat, standardize(theta, mu, sigma), rnd, tau)
+            - np.log(np.diag(whitening(sigma))).sum())
 
 
 def nll_and_grad(flat, u, weight=None, rnd=True):

@@ -77,10 +77,11 @@ class DESampler:
     flow's independence proposal instead (Metropolis-Hastings term
     log q(current) - log q(proposal))."""
 
-    def __init__(self, loglike, prior, theta0, seed, tie_tol=1e-7, flow=None):
+    def __init__(self, loglike, prior, theta0, seed, tie_tol=1e-7, flow=None, tau=1.0):
         """tie_tol: |log u - Delta| below which an acceptance counts as a near tie
         (a decision another implementation could take the other way)."""
         self.flow = flow
+        self.tau = tau
         self.loglike = loglike
         self.tie_tol = tie_tol
         self.prior = prior
@@ -149,11 +150,12 @@ class DESampler:
         if not take:
             return props, qratio
         take = np.array(take)
-        z32 = np.array(zs, dtype=np.float32).astype(np.float64)   # the latent point enters in FP32
+        # the latent point tau z enters in FP32
+        z32 = (self.tau * np.array(zs)).astype(np.float32).astype(np.float64)
         u, _ = F.inverse(flat, z32)
-        fprop = mu + sigma * u
-        lq_prop = F.log_prob(flat, fprop, mu, sigma)
-        lq_cur = F.log_prob(flat, self.theta[[upd[j] for j in take]], mu, sigma)
+        fprop = F.unstandardize(u, mu, sigma)
+        lq_prop = F.log_prob(flat, fprop, mu, sigma, tau=self.tau)
+        lq_cur = F.log_prob(flat, self.theta[[upd[j] for j in take]], mu, sigma, tau=self.tau)
         props = props.copy()
         props[take] = fprop
         qratio = qratio.copy()

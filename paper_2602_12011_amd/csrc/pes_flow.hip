@@ -6,7 +6,9 @@
 // feed an independence Metropolis-Hastings proposal whose acceptance uses the
 // exact FP64 likelihood; Sec. 2.2 leaves the proposal to the sampler.
 //
-// Conventions (the flow's definition): u = float((theta - mu) / sigma);
+// Conventions (the flow's definition): u = float(L^-1 (theta - mu)) with L
+// lower triangular (a whitening map, L L^T a covariance; forward substitution
+// in FP64);
 // layer 2p conditions on C_p = {i : (i + 3p) mod 11 < 6} and transforms the
 // other 5 coordinates, layer 2p + 1 conditions on those 5 and transforms C_p;
 // s = 3 tanh(s_hat / 3); normalizing direction y_T = x_T e^s + t, log det +=
@@ -59,7 +61,8 @@ struct TensorTable {
 };
 
 struct Norm {
-  double mu[kD], sigma[kD];
+  double mu[kD];
+  double L[kD][kD];   // lower triangular
 };
 
 // ------------------------------------------------------------------ GEMM
@@ -150,22 +153,30 @@ hipError_t gemm(const GemmArgs& g, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ elementwise
+// u = L^-1 (theta - mu) by forward substitution in FP64, rounded to FP32.
 __global__ void standardize_kernel(const double* __restrict__ theta, int64_t n, int64_t Mp, Norm nm,
+                                   float* __restrict__ x, float* __restrict__ logdet) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Mp) return;
+  logdet[j] = 0.0f;
+  double u[kD];
+#pragma unroll
+  for (int k = 0; k < kD; ++k) {
+    double acc = j < n ? theta[j * kD + k] - nm.mu[k] : 0.0;
+#pragma unroll
+    for (int m = 0; m < k; ++m) acc -= nm.L[k][m] * u[m];
+    u[k] = acc / nm.L[k][k];
+    x[j * kD + k] = (float)u[k];
+  }
+}
+
+// Latent rows tau z, rounded to FP32 after the product.
+__global__ void load_latent_kernel(const double* __restrict__ z, int64_t n, int64_t Mp, double tau,
                                    float* __restrict__ x, float* __restrict__ logdet) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Mp * kD) return;
   const int64_t j = i / kD;
-  const int k = (int)(i - j * kD);
-  x[i] = j < n ? (float)((theta[i] - nm.mu[k]) / nm.sigma[k]) : 0.0f;
-  if (k == 0) logdet[j] = 0.0f;
-}
-
-__global__ void load_latent_kernel(const double* __restrict__ z, int64_t n, int64_t Mp, float* __restrict__ x,
-                                   float* __restrict__ logdet) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Mp * kD) return;
-  const int64_t j = i / kD;
-  x[i] = j < n ? (float)z[i] : 0.0f;
+  x[i] = j < n ? (float)(tau * z[i]) : 0.0f;
   if (i - j * kD == 0) logdet[j] = 0.0f;
 }
 
@@ -201,9 +212,9 @@ __global__ void couple_kernel(float* __restrict__ x, const float* __restrict__ O
   logdet[j] += ld;
 }
 
-// log q(theta) = -|z|^2/2 - (11/2) log 2 pi + log det - sum log sigma.
+// log q(theta) = -|z|^2/(2 tau^2) - 11 log tau - (11/2) log 2 pi + log det - sum log L_kk.
 __global__ void logq_kernel(const float* __restrict__ z, const float* __restrict__ logdet, int64_t n,
-                            double lsig, double* __restrict__ logq, double* __restrict__ zout) {
+                            double lsig, double tau, double* __restrict__ logq, double* __restrict__ zout) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   double q = 0.0;
@@ -212,17 +223,25 @@ __global__ void logq_kernel(const float* __restrict__ z, const float* __restrict
     q = fma(v, v, q);
     if (zout) zout[j * kD + k] = v;
   }
-  logq[j] = -0.5 * q - 0.5 * kD * 1.8378770664093454836 + (double)logdet[j] - lsig;
+  logq[j] = -0.5 * q / (tau * tau) - kD * log(tau) - 0.5 * kD * 1.8378770664093454836 + (double)logdet[j] - lsig;
 }
 
+// theta = mu + L u.
 __global__ void unstandardize_kernel(const float* __restrict__ x, const float* __restrict__ logdet, int64_t n,
                                      Norm nm, double* __restrict__ theta, double* __restrict__ ld_out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * kD) return;
-  const int64_t j = i / kD;
-  const int k = (int)(i - j * kD);
-  theta[i] = fma(nm.sigma[k], (double)x[i], nm.mu[k]);
-  if (ld_out && k == 0) ld_out[j] = (double)logdet[j];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double u[kD];
+#pragma unroll
+  for (int k = 0; k < kD; ++k) u[k] = (double)x[j * kD + k];
+#pragma unroll
+  for (int k = 0; k < kD; ++k) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m <= k; ++m) acc = fma(nm.L[k][m], u[m], acc);
+    theta[j * kD + k] = nm.mu[k] + acc;
+  }
+  if (ld_out) ld_out[j] = (double)logdet[j];
 }
 
 // ------------------------------------------------------------------ training
@@ -354,37 +373,39 @@ __global__ void batch_kernel(const double* __restrict__ samples, int64_t n, int6
   for (int k = 0; k < kD; ++k) out[j * kD + k] = samples[src * kD + k];
 }
 
-// Per-coordinate mean and standard deviation of n rows (one block per
-// coordinate, two passes, fixed order).
-__global__ void __launch_bounds__(256) moments_kernel(const double* __restrict__ x, int64_t n,
-                                                      double* __restrict__ out) {
+// Mean (blocks 0..10) of n rows, then the covariance entry (a, b), a >= b,
+// of block a * 11 + b (second launch); fixed order per block.
+__device__ double block_sum(double s) {
   __shared__ double sh[256];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(256) mean_kernel(const double* __restrict__ x, int64_t n,
+                                                   double* __restrict__ out) {
   const int k = blockIdx.x;
   double s = 0.0;
   for (int64_t r = threadIdx.x; r < n; r += 256) s += x[r * kD + k];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double mean = sh[0] / (double)n;
-  __syncthreads();
-  s = 0.0;
-  for (int64_t r = threadIdx.x; r < n; r += 256) {
-    const double d = x[r * kD + k] - mean;
-    s = fma(d, d, s);
-  }
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[k] = mean;
-    out[kD + k] = sqrt(sh[0] / (double)n);
-  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[k] = s / (double)n;
+}
+
+__global__ void __launch_bounds__(256) cov_kernel(const double* __restrict__ x, int64_t n,
+                                                  double* __restrict__ mom) {
+  const int a = blockIdx.x / kD, b = blockIdx.x % kD;
+  if (b > a) return;
+  const double ma = mom[a], mb = mom[b];
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) s = fma(x[r * kD + a] - ma, x[r * kD + b] - mb, s);
+  s = block_sum(s);
+  if (threadIdx.x == 0) mom[kD + a * kD + b] = s / (double)n;
 }
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -403,6 +424,7 @@ struct pes_flow {
   float* bp = nullptr;    // [layer][kLayerB]: b1 [256], b2 [256], b3 [32]
   Norm nm;
   double lsig = 0.0;
+  double tau = 1.0;     // temperature of the base density
   int64_t t_adam = 0;
   // workspace (rows padded to a multiple of 64)
   int64_t cap = 0;
@@ -647,18 +669,48 @@ void destroy(pes_flow* f) {
   delete f;
 }
 
-int set_norm(pes_flow* f, const double* mu, const double* sigma) {
+// mu [11], L [11][11] row-major (entries above the diagonal ignored).
+int set_affine(pes_flow* f, const double* mu, const double* L) {
   double ls = 0.0;
   for (int k = 0; k < kD; ++k) {
-    if (!(sigma[k] > 0.0) || !std::isfinite(sigma[k]) || !std::isfinite(mu[k])) return PES_EINVAL;
-    ls += log(sigma[k]);
+    if (!std::isfinite(mu[k]) || !(L[k * kD + k] > 0.0)) return PES_EINVAL;
+    for (int m = 0; m <= k; ++m)
+      if (!std::isfinite(L[k * kD + m])) return PES_EINVAL;
+    ls += log(L[k * kD + k]);
   }
   for (int k = 0; k < kD; ++k) {
     f->nm.mu[k] = mu[k];
-    f->nm.sigma[k] = sigma[k];
+    for (int m = 0; m < kD; ++m) f->nm.L[k][m] = m <= k ? L[k * kD + m] : 0.0;
   }
   f->lsig = ls;
   return PES_OK;
+}
+
+int set_norm(pes_flow* f, const double* mu, const double* sigma) {
+  double L[kD * kD] = {0.0};
+  for (int k = 0; k < kD; ++k) {
+    if (!(sigma[k] > 0.0)) return PES_EINVAL;
+    L[k * kD + k] = sigma[k];
+  }
+  return set_affine(f, mu, L);
+}
+
+// Lower Cholesky factor of the symmetric matrix C (lower triangle used); false
+// if C is not positive definite.
+bool cholesky(const double* C, double* L) {
+  for (int i = 0; i < kD * kD; ++i) L[i] = 0.0;
+  for (int k = 0; k < kD; ++k) {
+    double d = C[k * kD + k];
+    for (int m = 0; m < k; ++m) d -= L[k * kD + m] * L[k * kD + m];
+    if (!(d > 0.0)) return false;
+    L[k * kD + k] = sqrt(d);
+    for (int i = k + 1; i < kD; ++i) {
+      double v = C[i * kD + k];
+      for (int m = 0; m < k; ++m) v -= L[i * kD + m] * L[k * kD + m];
+      L[i * kD + k] = v / L[k * kD + k];
+    }
+  }
+  return true;
 }
 
 }  // namespace
@@ -671,12 +723,13 @@ int flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double*
   if (n <= 0) return PES_OK;
   const int64_t Mp = pad_rows(n);
   if (Mp > f->cap) return PES_ESTATE;
-  hipLaunchKernelGGL(standardize_kernel, dim3(nblk(Mp * kD, 256)), dim3(256), 0, s, theta, n, Mp, f->nm, f->x,
+  hipLaunchKernelGGL(standardize_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, theta, n, Mp, f->nm, f->x,
                      f->logdet);
   FL_HIP(f, hipGetLastError());
   int rc = pass_forward(f, Mp, false, s);
   if (rc != PES_OK) return rc;
-  hipLaunchKernelGGL(logq_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, f->x, f->logdet, n, f->lsig, logq, z);
+  hipLaunchKernelGGL(logq_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, f->x, f->logdet, n, f->lsig, f->tau, logq,
+                     z);
   FL_HIP(f, hipGetLastError());
   return PES_OK;
 }
@@ -685,11 +738,12 @@ int flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, double*
   if (n <= 0) return PES_OK;
   const int64_t Mp = pad_rows(n);
   if (Mp > f->cap) return PES_ESTATE;
-  hipLaunchKernelGGL(load_latent_kernel, dim3(nblk(Mp * kD, 256)), dim3(256), 0, s, z, n, Mp, f->x, f->logdet);
+  hipLaunchKernelGGL(load_latent_kernel, dim3(nblk(Mp * kD, 256)), dim3(256), 0, s, z, n, Mp, f->tau, f->x,
+                     f->logdet);
   FL_HIP(f, hipGetLastError());
   int rc = pass_inverse(f, Mp, s);
   if (rc != PES_OK) return rc;
-  hipLaunchKernelGGL(unstandardize_kernel, dim3(nblk(n * kD, 256)), dim3(256), 0, s, f->x, f->logdet, n, f->nm,
+  hipLaunchKernelGGL(unstandardize_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, f->x, f->logdet, n, f->nm,
                      theta, logdet);
   FL_HIP(f, hipGetLastError());
   return PES_OK;
@@ -710,7 +764,7 @@ int pes_flow_create(uint64_t seed, pes_flow** out) {
       hipMalloc(&f->m1, sizeof(float) * np) != hipSuccess || hipMalloc(&f->m2, sizeof(float) * np) != hipSuccess ||
       hipMalloc(&f->wb, sizeof(__bf16) * kLayers * kLayerW) != hipSuccess ||
       hipMalloc(&f->bp, sizeof(float) * kLayers * kLayerB) != hipSuccess ||
-      hipMalloc(&f->mom, sizeof(double) * 2 * kD) != hipSuccess) {
+      hipMalloc(&f->mom, sizeof(double) * (kD + kD * kD)) != hipSuccess) {
     destroy(f);
     return PES_ENOMEM;
   }
@@ -791,11 +845,22 @@ int pes_flow_set_norm(pes_flow* f, const double* mu, const double* sigma) {
   return set_norm(f, mu, sigma);
 }
 
-int pes_flow_get_norm(pes_flow* f, double* mu, double* sigma) {
-  if (!f || !mu || !sigma) return PES_EINVAL;
+int pes_flow_set_temperature(pes_flow* f, double tau) {
+  if (!f || !(tau > 0.0) || !std::isfinite(tau)) return PES_EINVAL;
+  f->tau = tau;
+  return PES_OK;
+}
+
+int pes_flow_set_affine(pes_flow* f, const double* mu, const double* L) {
+  if (!f || !mu || !L) return PES_EINVAL;
+  return set_affine(f, mu, L);
+}
+
+int pes_flow_get_affine(pes_flow* f, double* mu, double* L) {
+  if (!f || !mu || !L) return PES_EINVAL;
   for (int k = 0; k < kD; ++k) {
     mu[k] = f->nm.mu[k];
-    sigma[k] = f->nm.sigma[k];
+    for (int m = 0; m < kD; ++m) L[k * kD + m] = f->nm.L[k][m];
   }
   return PES_OK;
 }
@@ -820,7 +885,7 @@ int pes_flow_nll_grad(pes_flow* f, const double* theta, int64_t n, double* nll, 
   if (rc != PES_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
   const int64_t Mp = pad_rows(n);
-  hipLaunchKernelGGL(standardize_kernel, dim3(nblk(Mp * kD, 256)), dim3(256), 0, s, theta, n, Mp, f->nm, f->x,
+  hipLaunchKernelGGL(standardize_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, theta, n, Mp, f->nm, f->x,
                      f->logdet);
   FL_HIP(f, hipGetLastError());
   rc = pass_forward(f, Mp, true, s);
@@ -844,29 +909,31 @@ int pes_flow_fit(pes_flow* f, const double* samples, int64_t n, int64_t steps, i
   hipStream_t s = (hipStream_t)stream;
   int rc = ensure_ws(f, batch);
   if (rc != PES_OK) return rc;
-  if (standardize) {
-    hipLaunchKernelGGL(moments_kernel, dim3(kD), dim3(256), 0, s, samples, n, f->mom);
-    double h[2 * kD];
+  if (standardize) {   // whitening by the samples' mean and covariance (Cholesky factor)
+    hipLaunchKernelGGL(mean_kernel, dim3(kD), dim3(256), 0, s, samples, n, f->mom);
+    hipLaunchKernelGGL(cov_kernel, dim3(kD * kD), dim3(256), 0, s, samples, n, f->mom);
+    FL_HIP(f, hipGetLastError());
+    double h[kD + kD * kD], L[kD * kD];
     FL_HIP(f, hipMemcpyAsync(h, f->mom, sizeof(h), hipMemcpyDeviceToHost, s));
     FL_HIP(f, hipStreamSynchronize(s));
-    rc = set_norm(f, h, h + kD);
-    if (rc != PES_OK) {
-      snprintf(f->err, sizeof(f->err), "training samples have a constant coordinate");
-      return rc;
+    if (!cholesky(h + kD, L) || set_affine(f, h, L) != PES_OK) {
+      snprintf(f->err, sizeof(f->err), "the training samples' covariance is not positive definite");
+      return PES_EINVAL;
     }
   }
   const int64_t Mp = pad_rows(batch);
   for (int64_t it = 0; it < steps; ++it) {
     hipLaunchKernelGGL(batch_kernel, dim3(nblk(batch, 256)), dim3(256), 0, s, samples, n, batch, seed,
                        (uint64_t)it, f->batchbuf);
-    hipLaunchKernelGGL(standardize_kernel, dim3(nblk(Mp * kD, 256)), dim3(256), 0, s, f->batchbuf, batch, Mp, f->nm,
+    hipLaunchKernelGGL(standardize_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, f->batchbuf, batch, Mp, f->nm,
                        f->x, f->logdet);
     FL_HIP(f, hipGetLastError());
     rc = pass_forward(f, Mp, true, s);
     if (rc != PES_OK) return rc;
     rc = pass_backward(f, batch, Mp, loss ? loss + it : nullptr, s);
     if (rc != PES_OK) return rc;
-    rc = refresh(f, true, lr, s);
+    const float lr_t = (float)(0.5 * lr * (1.0 + cos(M_PI * (double)it / (double)steps)));   // cosine decay
+    rc = refresh(f, true, lr_t, s);
     if (rc != PES_OK) return rc;
   }
   return PES_OK;

@@ -9,6 +9,7 @@ this module without it raises, there is no fallback.
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -73,7 +74,9 @@ def lib():
         L.pes_flow_set_params.argtypes = [vp, vp, vp]
         L.pes_flow_get_params.argtypes = [vp, vp, vp]
         L.pes_flow_set_norm.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
-        L.pes_flow_get_norm.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.pes_flow_set_affine.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.pes_flow_set_temperature.argtypes = [vp, C.c_double]
+        L.pes_flow_get_affine.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.pes_flow_forward.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
         L.pes_flow_inverse.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
         L.pes_flow_nll_grad.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
@@ -106,7 +109,7 @@ def lib():
                      "pes_response", "pes_loglike", "pes_timing", "pes_timing_read",
                      "pes_set_tuning", "pes_get_tuning", "pes_autotune", "pes_grad", "pes_set_grad_method",
                      "pes_flow_create", "pes_flow_destroy", "pes_flow_set_params", "pes_flow_get_params",
-                     "pes_flow_set_norm", "pes_flow_get_norm", "pes_flow_forward", "pes_flow_inverse",
+                     "pes_flow_set_norm", "pes_flow_set_affine", "pes_flow_get_affine", "pes_flow_set_temperature", "pes_flow_forward", "pes_flow_inverse",
                      "pes_flow_nll_grad", "pes_flow_adam_step", "pes_flow_fit", "pes_sampler_set_flow",
                      "pes_sampler_read_chain",
                      "pes_fisher", "pes_sampler_create", "pes_sampler_destroy",
@@ -428,10 +431,19 @@ class Flow:
         sg = (C.c_double * 11)(*[float(x) for x in sigma])
         self._check(lib().pes_flow_set_norm(self.h, mu, sg), "pes_flow_set_norm")
 
-    def get_norm(self):
-        mu, sg = (C.c_double * 11)(), (C.c_double * 11)()
-        self._check(lib().pes_flow_get_norm(self.h, mu, sg), "pes_flow_get_norm")
-        return list(mu), list(sg)
+    def set_temperature(self, tau):
+        self._check(lib().pes_flow_set_temperature(self.h, C.c_double(tau)), "pes_flow_set_temperature")
+
+    def set_affine(self, mu, L):
+        """Whitening u = L^-1 (theta - mu), L lower triangular [11, 11]."""
+        mu = (C.c_double * 11)(*[float(x) for x in mu])
+        Lf = (C.c_double * 121)(*[float(x) for x in np.asarray(L, dtype=np.float64).ravel()])
+        self._check(lib().pes_flow_set_affine(self.h, mu, Lf), "pes_flow_set_affine")
+
+    def get_affine(self):
+        mu, L = (C.c_double * 11)(), (C.c_double * 121)()
+        self._check(lib().pes_flow_get_affine(self.h, mu, L), "pes_flow_get_affine")
+        return np.array(mu[:]), np.array(L[:]).reshape(11, 11)
 
     def forward(self, theta, stream=None):
         """(z [n, 11], log q(theta) [n])."""

@@ -143,3 +143,36 @@ def test_adam_first_step_and_convergence():
     for t in range(1, 3001):
         F.adam_step(p, 2.0 * (p - target), m, v, t, lr=1e-2)
     assert np.abs(p - target).max() < 1e-3
+
+
+def test_whitened_identity_flow_is_the_multivariate_normal():
+    """With the identity flow, q(theta) is the Gaussian N(mu, L L^T) of the
+    whitening map (scipy's density)."""
+    rng = np.random.default_rng(15)
+    A = rng.normal(size=(11, 11))
+    C = A @ A.T / 11 + 0.05 * np.eye(11)
+    L = np.linalg.cholesky(C)
+    mu = rng.normal(size=11) * 3
+    flat = F.init_params(16, scale_out=0.0)
+    th = rng.multivariate_normal(mu, C, size=300)
+    lq = F.log_prob(flat, th, mu, L)
+    ref = stats.multivariate_normal(mu, C).logpdf(th)
+    assert np.allclose(lq, ref, rtol=1e-6, atol=1e-5)
+    # standardize and unstandardize are inverse maps (up to the FP32 rounding of u)
+    u = F.standardize(th, mu, L)
+    assert np.allclose(F.unstandardize(u, mu, L), th, rtol=0, atol=1e-5 * np.abs(th).max())
+    assert np.allclose(np.cov(u.T), np.linalg.inv(L) @ np.cov(th.T) @ np.linalg.inv(L).T, atol=1e-6)
+
+
+def test_temperature_widens_the_gaussian():
+    """Identity flow at temperature tau: q is N(mu, tau^2 L L^T)."""
+    rng = np.random.default_rng(17)
+    A = rng.normal(size=(11, 11))
+    C = A @ A.T / 11 + 0.05 * np.eye(11)
+    L = np.linalg.cholesky(C)
+    mu = rng.normal(size=11)
+    flat = F.init_params(18, scale_out=0.0)
+    th = rng.multivariate_normal(mu, 2.0 * C, size=200)
+    lq = F.log_prob(flat, th, mu, L, tau=1.4)
+    ref = stats.multivariate_normal(mu, 1.96 * C).logpdf(th)
+    assert np.allclose(lq, ref, rtol=1e-6, atol=1e-5)
