@@ -940,20 +940,30 @@ __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const d
     adj_unit<GEO, LS>(wt, wtn, det, j, P.inv_year, P.inv_ptq, br, a, ftc, yb, g);
 }
 
+// The walker's tangent table is staged in LDS: the contraction reads ~150 of
+// its entries per mode unit as wave-uniform LDS broadcasts, which keeps them
+// out of the scalar registers and their spills (the walker table itself stays
+// on scalar loads: staging it too moves the pressure into vector registers).
 template <bool LS>
 __global__ void __launch_bounds__(64)
     adj_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                const double* __restrict__ wtab, const double* __restrict__ wtan,
                double* __restrict__ partial, JacArgs A) {
+  __shared__ double tan_s[W_STRIDE * kNParams];
   const int t = blockIdx.x;
   const int b = blockIdx.y;
   const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
-  const double* __restrict__ wtn = wtan + (int64_t)b * W_STRIDE * kNParams;
   if (wt[W_VALID] == 0.0) return;
   const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
   const int64_t k0 = (int64_t)t * A.tile;
   if (k0 >= nact) return;
   const int lane = threadIdx.x;
+  {
+    const double* __restrict__ src = wtan + (int64_t)b * W_STRIDE * kNParams;
+    for (int i = lane; i < W_STRIDE * kNParams; i += 64) tan_s[i] = src[i];
+    __syncthreads();
+  }
+  const double* wtn = tan_s;
   const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
   double g[kNParams];
 #pragma unroll
