@@ -277,8 +277,10 @@ def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps, tau=1.1, fit_batch=1024):
     flow.close()
     ctx.close()
     flat = {k: v[n_run // 2:].reshape(-1, 11) for k, v in chains.items()}
-    ks_lp = max(D.ks_distance(flat["learned"][:, j], flat["plain"][:, j]) for j in range(11))
-    ks_pp = max(D.ks_distance(flat["plain_independent"][:, j], flat["plain"][:, j]) for j in range(11))
+    ks_lp_j = [D.ks_distance(flat["learned"][:, j], flat["plain"][:, j]) for j in range(11)]
+    ks_pp_j = [D.ks_distance(flat["plain_independent"][:, j], flat["plain"][:, j]) for j in range(11)]
+    ks_lp, ks_pp = max(ks_lp_j), max(ks_pp_j)
+    sd_ratio = flat["learned"].std(axis=0) / flat["plain"].std(axis=0)
     gain = results["learned"]["ess_per_s"] / max(results["plain"]["ess_per_s"], 1e-30)
     amort = results["learned"]["ess_min"] / (results["learned"]["seconds"] + t_fit)
     return dict(workload=f"LISA+Taiji+TianQin, 5 modes, 2^20 bins, {B} walkers, noise-free injection; "
@@ -292,7 +294,10 @@ def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps, tau=1.1, fit_batch=1024):
                 plain_independent=results["plain_independent"], gain=round(gain, 2),
                 learned_ess_per_s_with_training=round(amort, 2),
                 ks_learned_vs_plain=round(ks_lp, 4), ks_independent_plain_vs_plain=round(ks_pp, 4),
-                accuracy_ok=bool(ks_lp <= 1.5 * ks_pp))
+                accuracy_ok=bool(ks_lp <= 1.5 * ks_pp),
+                ks_per_parameter_learned_vs_plain=[round(x, 4) for x in ks_lp_j],
+                ks_per_parameter_independent_plain_vs_plain=[round(x, 4) for x in ks_pp_j],
+                sd_ratio_learned_over_plain=[round(float(x), 3) for x in sd_ratio])
 
 
 def main():

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libpes.so")
-SOURCES = ["pes_kernels.hip", "pes_sampler.hip", "pes_flow.hip", "pes_api.hip"]
+SOURCES = ["pes_kernels.hip", "pes_deriv.hip", "pes_sampler.hip", "pes_flow.hip", "pes_api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result"]

@@ -5,7 +5,6 @@
 #include <math.h>
 #include <stdint.h>
 
-#include "pes_adjoint.hpp"
 #include "pes_eval.hpp"
 #include "pes_launch.hpp"
 
@@ -757,314 +756,6 @@ int loglike_blocks_per_cu(int bpl, bool long_sinc) {
     e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, true>, 256, 0)
                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, false>, 256, 0);
   return e == hipSuccess ? nb : 1;
-}
-
-// ---------------------------------------------------------------- derivatives
-// Forward-mode tangents of the channels, one direction per pass: for each
-// 64-bin sub-tile and detector the 11 passes give dC/dtheta_k for the lane's
-// bin.  GRAD accumulates sum (D - W C) . dC/dtheta_k (the gradient of
-// <d|h> - <h|h>/2) together with <d|h> and <h|h>; FISHER stores
-// sqrt(W) dC/dtheta in LDS and accumulates J^T J with FP64 matrix-core
-// operations (16 x 16 x 4 blocks, parameters padded to 16).
-__device__ __forceinline__ int64_t active_bins(double fmx, double f0, double df, int64_t N) {
-  double nb = ceil((fmx - f0) / df) + 1.0;
-  nb = fmin(fmax(nb, 0.0), (double)N);
-  return (int64_t)nb;
-}
-
-template <bool LS, bool GEO, bool FISHER>
-__device__ __forceinline__ void jac_det(const double* __restrict__ bins, const double* __restrict__ tb,
-                                        const double* __restrict__ wt, const double* __restrict__ wtn,
-                                        const JacArgs& A, int det, int64_t k, bool in, double* g,
-                                        double& dh, double& hh, double* J) {
-  const int64_t N = A.N;
-  const int64_t kk = in ? k : N - 1;
-  BinRegs br;
-  br.f = bins[B_F * N + kk];
-  br.f13 = bins[B_F13 * N + kk];
-  br.fm13 = bins[B_FM13 * N + kk];
-  br.fm76 = bins[B_FM76 * N + kk];
-  br.lnf = bins[B_LNF * N + kk];
-  const double zr = tb[T_ZR * N + kk], zi = tb[T_ZI * N + kk], a = tb[T_A * N + kk];
-  const double wA = in ? tb[T_WA * N + kk] : 0.0;
-  const double wT = in ? tb[T_WT * N + kk] : 0.0;
-  const double W[6] = {wA, wA, wA * (1.0 / 3.0), wA * (1.0 / 3.0), wT, wT};
-  double D[6];
-  D[0] = in ? tb[T_DAR * N + kk] : 0.0;
-  D[1] = in ? tb[T_DAI * N + kk] : 0.0;
-  D[2] = in ? tb[T_DER * N + kk] : 0.0;
-  D[3] = in ? tb[T_DEI * N + kk] : 0.0;
-  D[4] = in ? tb[T_DTR * N + kk] : 0.0;
-  D[5] = in ? tb[T_DTI * N + kk] : 0.0;
-  const DetParams& P = A.dt.p[det];
-  double R[6];
-  const int lane = threadIdx.x;
-#pragma unroll 1
-  for (int kp = 0; kp < kNParams; ++kp) {
-    const ChanT<Dual<1>> c = eval_channels_t<GEO, LS, Dual<1>>(TanTab{wt, wtn, kp}, det, A.n_modes,
-                                                              P.inv_year, P.inv_ptq, br, a, zr, zi);
-    const double cv[6] = {c.ar.v, c.ai.v, c.er.v, c.ei.v, c.tr.v, c.ti.v};
-    const double cd[6] = {c.ar.d[0], c.ai.d[0], c.er.d[0], c.ei.d[0], c.tr.d[0], c.ti.d[0]};
-    if (kp == 0) {
-#pragma unroll
-      for (int r = 0; r < 6; ++r) {
-        dh = fma(D[r], cv[r], dh);
-        hh = fma(W[r] * cv[r], cv[r], hh);
-        R[r] = fma(-W[r], cv[r], D[r]);
-      }
-    }
-    if (FISHER) {
-#pragma unroll
-      for (int r = 0; r < 6; ++r) J[(6 * lane + r) * 16 + kp] = sqrt(W[r]) * cd[r];
-    } else {
-      double acc = 0.0;
-#pragma unroll
-      for (int r = 0; r < 6; ++r) acc = fma(R[r], cd[r], acc);
-#pragma unroll
-      for (int i = 0; i < kNParams; ++i) g[i] += (i == kp) ? acc : 0.0;   // keeps g in registers
-    }
-  }
-}
-
-template <bool LS, bool FISHER>
-__global__ void __launch_bounds__(64)
-    jac_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
-               const double* __restrict__ wtab, const double* __restrict__ wtan,
-               double* __restrict__ partial, JacArgs A) {
-  __shared__ double J[FISHER ? 64 * 6 * 16 : 1];
-  const int t = blockIdx.x;
-  const int b = blockIdx.y;
-  const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
-  const double* __restrict__ wtn = wtan + (int64_t)b * W_STRIDE * kNParams;
-  if (wt[W_VALID] == 0.0) return;
-  const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
-  const int64_t k0 = (int64_t)t * A.tile;
-  if (k0 >= nact) return;
-  const int lane = threadIdx.x;
-  const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
-  double g[kNParams];
-#pragma unroll
-  for (int i = 0; i < kNParams; ++i) g[i] = 0.0;
-  double dh = 0.0, hh = 0.0;
-  typedef double v4d __attribute__((ext_vector_type(4)));
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
-  if (FISHER) {
-    for (int i = lane; i < 64 * 6 * 16; i += 64) J[i] = 0.0;   // padding columns stay 0
-    __syncthreads();
-  }
-  for (int64_t s0 = k0; s0 < kend; s0 += 64) {
-    const int64_t k = s0 + lane;
-    const bool in = k < kend;
-    for (int det = 0; det < A.n_det; ++det) {
-      const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * A.N;
-      if (A.dt.p[det].kind == 2)
-        jac_det<LS, true, FISHER>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, J);
-      else
-        jac_det<LS, false, FISHER>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, J);
-      if (FISHER) {
-        __syncthreads();
-        // acc += Jt^T Jt over the 384 rows of this sub-tile, 4 rows per operation:
-        // operand element (row 4q + lane/16, column lane%16) serves as both A and B.
-        for (int q = 0; q < 96; ++q) {
-          const double v = J[(4 * q + (lane >> 4)) * 16 + (lane & 15)];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
-        }
-        __syncthreads();
-      }
-    }
-  }
-  const int64_t slot = (int64_t)t * A.B + b;
-  if (FISHER) {
-    double* p = partial + slot * 256 + lane * 4;
-    p[0] = acc[0];
-    p[1] = acc[1];
-    p[2] = acc[2];
-    p[3] = acc[3];
-  } else {
-    double red[kNParams + 2];
-#pragma unroll
-    for (int i = 0; i < kNParams; ++i) red[i] = wave_sum_dpp(g[i]);
-    red[kNParams] = wave_sum_dpp(dh);
-    red[kNParams + 1] = wave_sum_dpp(hh);
-    if (lane == 0) {
-      double* p = partial + slot * (kNParams + 2);
-#pragma unroll
-      for (int i = 0; i < kNParams + 2; ++i) p[i] = red[i];
-    }
-  }
-}
-
-// Reverse-mode gradient: for each (walker, bin, detector) one forward
-// evaluation gives the channels and the weighted residual, adj_links turns it
-// into link adjoints, and adj_unit recomputes and back-propagates every active
-// mode, contracting table-entry adjoints with the setup's theta-derivatives.
-template <bool LS, bool GEO>
-__device__ __forceinline__ void adj_det(const double* __restrict__ bins, const double* __restrict__ tb,
-                                        const double* __restrict__ wt, const double* __restrict__ wtn,
-                                        const JacArgs& A, int det, int64_t k, bool in, double* g,
-                                        double& dh, double& hh) {
-  const int64_t N = A.N;
-  const int64_t kk = in ? k : N - 1;
-  BinRegs br;
-  br.f = bins[B_F * N + kk];
-  br.f13 = bins[B_F13 * N + kk];
-  br.fm13 = bins[B_FM13 * N + kk];
-  br.fm76 = bins[B_FM76 * N + kk];
-  br.lnf = bins[B_LNF * N + kk];
-  const double zr = tb[T_ZR * N + kk], zi = tb[T_ZI * N + kk], a = tb[T_A * N + kk];
-  const double wA = in ? tb[T_WA * N + kk] : 0.0;
-  const double wT = in ? tb[T_WT * N + kk] : 0.0;
-  double D[6];
-  D[0] = in ? tb[T_DAR * N + kk] : 0.0;
-  D[1] = in ? tb[T_DAI * N + kk] : 0.0;
-  D[2] = in ? tb[T_DER * N + kk] : 0.0;
-  D[3] = in ? tb[T_DEI * N + kk] : 0.0;
-  D[4] = in ? tb[T_DTR * N + kk] : 0.0;
-  D[5] = in ? tb[T_DTI * N + kk] : 0.0;
-  const DetParams& P = A.dt.p[det];
-  const Chan c = eval_channels<GEO, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br, a, zr, zi);
-  dh = fma(D[0], c.ar, dh);
-  dh = fma(D[1], c.ai, dh);
-  dh = fma(D[2], c.er, dh);
-  dh = fma(D[3], c.ei, dh);
-  dh = fma(D[4], c.tr, dh);
-  dh = fma(D[5], c.ti, dh);
-  const double a2 = fma(c.ar, c.ar, c.ai * c.ai) + (1.0 / 3.0) * fma(c.er, c.er, c.ei * c.ei);
-  const double t2 = fma(c.tr, c.tr, c.ti * c.ti);
-  hh = fma(wA, a2, fma(wT, t2, hh));
-  double yb[3][4];
-  adj_links(c, D, wA, wT, zr, zi, yb);
-  const double ftc = frac_prod(br.f, wt[W_TC]);
-#pragma unroll 1
-  for (int j = 0; j < A.n_modes; ++j)
-    adj_unit<GEO, LS>(wt, wtn, det, j, P.inv_year, P.inv_ptq, br, a, ftc, yb, g);
-}
-
-// The walker's tangent table is staged in LDS: the contraction reads ~150 of
-// its entries per mode unit as wave-uniform LDS broadcasts, which keeps them
-// out of the scalar registers and their spills (the walker table itself stays
-// on scalar loads: staging it too moves the pressure into vector registers).
-template <bool LS>
-__global__ void __launch_bounds__(64)
-    adj_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
-               const double* __restrict__ wtab, const double* __restrict__ wtan,
-               double* __restrict__ partial, JacArgs A) {
-  __shared__ double tan_s[W_STRIDE * kNParams];
-  const int t = blockIdx.x;
-  const int b = blockIdx.y;
-  const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
-  if (wt[W_VALID] == 0.0) return;
-  const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
-  const int64_t k0 = (int64_t)t * A.tile;
-  if (k0 >= nact) return;
-  const int lane = threadIdx.x;
-  {
-    const double* __restrict__ src = wtan + (int64_t)b * W_STRIDE * kNParams;
-    for (int i = lane; i < W_STRIDE * kNParams; i += 64) tan_s[i] = src[i];
-    __syncthreads();
-  }
-  const double* wtn = tan_s;
-  const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
-  double g[kNParams];
-#pragma unroll
-  for (int i = 0; i < kNParams; ++i) g[i] = 0.0;
-  double dh = 0.0, hh = 0.0;
-  for (int64_t s0 = k0; s0 < kend; s0 += 64) {
-    const int64_t k = s0 + lane;
-    const bool in = k < kend;
-    for (int det = 0; det < A.n_det; ++det) {
-      const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * A.N;
-      if (A.dt.p[det].kind == 2)
-        adj_det<LS, true>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh);
-      else
-        adj_det<LS, false>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh);
-    }
-  }
-  double red[kNParams + 2];
-#pragma unroll
-  for (int i = 0; i < kNParams; ++i) red[i] = wave_sum_dpp(g[i]);
-  red[kNParams] = wave_sum_dpp(dh);
-  red[kNParams + 1] = wave_sum_dpp(hh);
-  if (lane == 0) {
-    double* p = partial + ((int64_t)t * A.B + b) * (kNParams + 2);
-#pragma unroll
-    for (int i = 0; i < kNParams + 2; ++i) p[i] = red[i];
-  }
-}
-
-// Per walker, tiles summed in order.  logl = <d|h> - <h|h>/2 - <d|d>/2.
-__global__ void grad_finalize_kernel(const double* __restrict__ partial, const double* __restrict__ wtab,
-                                     const double* __restrict__ dd, JacArgs A, double* __restrict__ logl,
-                                     double* __restrict__ grad) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= A.B) return;
-  const double* wt = wtab + (int64_t)b * W_STRIDE;
-  if (wt[W_VALID] == 0.0) {
-    if (logl) logl[b] = -INFINITY;
-    for (int i = 0; i < kNParams; ++i) grad[(int64_t)b * kNParams + i] = 0.0;
-    return;
-  }
-  const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
-  const int nt = (int)((nact + A.tile - 1) / A.tile);
-  double s[kNParams + 2];
-  for (int i = 0; i < kNParams + 2; ++i) s[i] = 0.0;
-  for (int t = 0; t < nt; ++t) {
-    const double* p = partial + ((int64_t)t * A.B + b) * (kNParams + 2);
-    for (int i = 0; i < kNParams + 2; ++i) s[i] += p[i];
-  }
-  for (int i = 0; i < kNParams; ++i) grad[(int64_t)b * kNParams + i] = s[i];
-  if (logl) logl[b] = (s[kNParams] - 0.5 * s[kNParams + 1]) - 0.5 * dd[0];
-}
-
-// Fisher matrix: the 16 x 16 FP64 matrix-core accumulator of each tile is held
-// as lane l, element r <-> (row 4 r + l / 16, column l % 16); tiles summed in
-// order, the leading 11 x 11 block written out.
-__global__ void fisher_finalize_kernel(const double* __restrict__ partial, const double* __restrict__ wtab,
-                                       JacArgs A, double* __restrict__ F) {
-  const int b = blockIdx.x;
-  const int e = threadIdx.x;   // 0..255: lane = e / 4, r = e % 4
-  const double* wt = wtab + (int64_t)b * W_STRIDE;
-  const int lane = e >> 2, r = e & 3;
-  const int row = 4 * r + (lane >> 4), col = lane & 15;
-  double s = 0.0;
-  if (wt[W_VALID] != 0.0) {
-    const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
-    const int nt = (int)((nact + A.tile - 1) / A.tile);
-    for (int t = 0; t < nt; ++t) s += partial[((int64_t)t * A.B + b) * 256 + e];
-  } else {
-    s = NAN;
-  }
-  if (row < kNParams && col < kNParams) F[((int64_t)b * kNParams + row) * kNParams + col] = s;
-}
-
-hipError_t launch_grad(const double* bins, const double* tabs, const double* wtab, const double* wtan,
-                       double* partial, const double* dd, const JacArgs& A, bool long_sinc, bool adjoint,
-                       double* logl, double* grad, hipStream_t s) {
-  const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
-  if (adjoint) {
-    if (long_sinc)
-      hipLaunchKernelGGL((adj_kernel<true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
-    else
-      hipLaunchKernelGGL((adj_kernel<false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
-  } else if (long_sinc) {
-    hipLaunchKernelGGL((jac_kernel<true, false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
-  } else {
-    hipLaunchKernelGGL((jac_kernel<false, false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
-  }
-  hipLaunchKernelGGL(grad_finalize_kernel, dim3((A.B + 255) / 256), dim3(256), 0, s, partial, wtab, dd, A, logl,
-                     grad);
-  return hipGetLastError();
-}
-
-hipError_t launch_fisher(const double* bins, const double* tabs, const double* wtab, const double* wtan,
-                         double* partial, const JacArgs& A, bool long_sinc, double* F, hipStream_t s) {
-  const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
-  if (long_sinc)
-    hipLaunchKernelGGL((jac_kernel<true, true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
-  else
-    hipLaunchKernelGGL((jac_kernel<false, true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
-  hipLaunchKernelGGL(fisher_finalize_kernel, dim3(A.B), dim3(256), 0, s, partial, wtab, A, F);
-  return hipGetLastError();
 }
 
 }  // namespace pes
