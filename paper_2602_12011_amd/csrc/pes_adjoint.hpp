@@ -17,12 +17,21 @@
 
 namespace pes {
 
+// A value the compiler must treat as unknown (an empty asm that claims to
+// modify it): recomputations from it are not merged with earlier ones.
+__device__ __forceinline__ double opaque(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // g[J...] += cbar * d(entry)/d(theta_J) for the parameters J the entry depends
-// on (the setup makes every other derivative exactly zero).
+// on (the setup makes every other derivative exactly zero).  tan_row holds
+// those derivatives in the order of J (the compact tangent layout below).
 template <int... J>
 struct Deps {
-  __device__ __forceinline__ static void add(double* g, double cbar, const double* __restrict__ tan_row) {
-    ((g[J] = fma(cbar, tan_row[J], g[J])), ...);
+  __device__ __forceinline__ static void add(double* g, double cbar, const double* tan_row) {
+    int i = 0;
+    ((g[J] = fma(cbar, tan_row[i++], g[J])), ...);
   }
 };
 // theta = (M, q, chi1, chi2, D_L, iota, phi_c, lambda, beta, psi, t_c)
@@ -37,6 +46,78 @@ using DepIota = Deps<5>;
 using DepSky = Deps<7, 8>;
 using DepSkyPsi = Deps<7, 8, 9>;
 using DepTc = Deps<10>;
+
+// Compact tangent layout: per table entry only the derivatives with respect
+// to the parameters in its mask (bit k: theta_k), in increasing k; entries
+// ordered t_c, then modes 0..4 (26 fields each), then detectors 0..2 (44
+// fields each).  The masks are the parameter lists the reverse sweep uses.
+constexpr unsigned kBitM = 1u << 0, kBitQ = 1u << 1, kBitChi = (1u << 2) | (1u << 3), kBitD = 1u << 4,
+                   kBitIota = 1u << 5, kBitPhi = 1u << 6, kBitSky = (1u << 7) | (1u << 8), kBitPsi = 1u << 9,
+                   kBitTc = 1u << 10;
+__host__ __device__ constexpr unsigned mode_mask(int f) {
+  switch (f) {
+    case M_CM: case M_CMI: case M_LNCM: case M_FCI: return kBitM;
+    case M_C0: return kBitQ | kBitPhi;
+    case M_A3: case M_A4: return kBitQ | kBitChi;
+    case M_A0: case M_A2: case M_B5: case M_A6: case M_B6: case M_A7: return kBitQ;
+    case M_T3: case M_T4: return kBitM | kBitQ | kBitChi;
+    case M_T0: case M_T2: case M_T5: case M_T6: case M_T6L: case M_T7: return kBitM | kBitQ;
+    case M_AM0: case M_AM1: case M_AM2: return kBitM | kBitQ | kBitD;
+    default: return kBitIota;   // M_KP, M_KC
+  }
+}
+__host__ __device__ constexpr unsigned det_mask(int f) {
+  return f < D_KN ? kBitTc : (f >= D_NP && f < D_KD) ? (kBitSky | kBitPsi) : kBitSky;
+}
+// Slot offsets of the fields within a mode / detector block, evaluated at
+// compile time (tm/td below index them with constants).
+struct TanLayout {
+  int mode[W_MODE_STRIDE + 1];
+  int det[W_DET_STRIDE + 1];
+  constexpr TanLayout() : mode(), det() {
+    for (int f = 0; f < W_MODE_STRIDE; ++f) mode[f + 1] = mode[f] + __builtin_popcount(mode_mask(f));
+    for (int f = 0; f < W_DET_STRIDE; ++f) det[f + 1] = det[f] + __builtin_popcount(det_mask(f));
+  }
+};
+constexpr TanLayout kTanLayout{};
+constexpr int kModeSlots = kTanLayout.mode[W_MODE_STRIDE];   // 49
+constexpr int kDetSlots = kTanLayout.det[W_DET_STRIDE];      // 106
+constexpr int kTanMode0 = 1;
+constexpr int kTanDet0 = kTanMode0 + kMaxModes * kModeSlots;
+constexpr int kTanSlots = kTanDet0 + kMaxDet * kDetSlots;
+static_assert(kModeSlots == 49 && kDetSlots == 106, "compact tangent layout");
+template <int F> struct ModeOff { static constexpr int value = kTanLayout.mode[F]; };
+template <int F> struct DetOff { static constexpr int value = kTanLayout.det[F]; };
+
+// Copies the full tangent table [W_STRIDE][11] of one walker into the compact
+// layout, entries split over the n threads of a block.
+__device__ inline void compact_tangents(const double* __restrict__ full, double* __restrict__ out, int tid,
+                                        int n) {
+  for (int e = tid; e < 1 + kMaxModes * W_MODE_STRIDE + kMaxDet * W_DET_STRIDE; e += n) {
+    int entry, slot;
+    unsigned mask;
+    if (e == 0) {
+      entry = W_TC;
+      slot = 0;
+      mask = kBitTc;
+    } else if (e < 1 + kMaxModes * W_MODE_STRIDE) {
+      const int j = (e - 1) / W_MODE_STRIDE, f = (e - 1) % W_MODE_STRIDE;
+      entry = W_MODE0 + j * W_MODE_STRIDE + f;
+      mask = mode_mask(f);
+      slot = kTanMode0 + j * kModeSlots;
+      for (int q = 0; q < f; ++q) slot += __builtin_popcount(mode_mask(q));
+    } else {
+      const int r = e - 1 - kMaxModes * W_MODE_STRIDE;
+      const int d = r / W_DET_STRIDE, f = r % W_DET_STRIDE;
+      entry = W_DET0 + d * W_DET_STRIDE + f;
+      mask = det_mask(f);
+      slot = kTanDet0 + d * kDetSlots;
+      for (int q = 0; q < f; ++q) slot += __builtin_popcount(det_mask(q));
+    }
+    for (int k = 0; k < kNParams; ++k)
+      if (mask & (1u << k)) out[slot++] = full[entry * kNParams + k];
+  }
+}
 
 // Link adjoints yb[arm][Fr, Fi, Br, Bi] from the channel values c and the
 // per-bin data D and weights (wA, wT).  Arm 0 carries y32 (F) / y23 (B),
@@ -70,7 +151,7 @@ __device__ __forceinline__ void adj_links(const Chan& c, const double (&D)[6], d
 // Accumulates the adjoints of aP E and 2 aC E and returns those of the arm's
 // e = (c, s), kn, np, nq.
 template <bool LS>
-__device__ __forceinline__ void adj_arm(const double (&yb)[4], double a, double pEr, double pEi, double cEr,
+__device__ __forceinline__ void adj_arm(const double* yb, double a, double pEr, double pEi, double cEr,
                                         double cEi, double c, double s, double np, double nq, double kn,
                                         double& pEbr, double& pEbi, double& cEbr, double& cEbi, double& cb,
                                         double& sb, double& knb, double& npb, double& nqb) {
@@ -105,44 +186,50 @@ __device__ __forceinline__ void adj_arm(const double (&yb)[4], double a, double 
 }
 
 // Adjoint of mode j's unit of (walker, bin, detector) given the link adjoints
-// yb; accumulates d l / d theta into g.  wt: the walker's table; tn: its
-// tangent table [W_STRIDE][11]; ftc = f t_c mod 1.
+// yb (12 values: arm-major Fr, Fi, Br, Bi); accumulates d l / d theta into g.  wt: the walker's table; tn: its
+// tangents in the compact layout; ftc = f t_c mod 1.
 template <bool GEO, bool LS>
 __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const double* __restrict__ tn, int det,
                                          int j, double inv_year, double inv_ptq, const BinRegs& b, double a,
-                                         double ftc, const double (&yb)[3][4], double* g) {
+                                         double ftc, const double* yb, double* g) {
   const int M0 = W_MODE0 + j * W_MODE_STRIDE;
   const int D0 = W_DET0 + det * W_DET_STRIDE;
 #define wm(i) wt[M0 + (i)]
 #define wd(i) wt[D0 + (i)]
-#define tm(i) (tn + (M0 + (i)) * kNParams)
-#define td(i) (tn + (D0 + (i)) * kNParams)
+#define tm(i) (tn + kTanMode0 + j * kModeSlots + ModeOff<(i)>::value)
+#define td(i) (tn + kTanDet0 + det * kDetSlots + DetOff<(i)>::value)
   const double x = b.f * wm(M_FCI);
   if (!(x < 1.0)) return;
-  // ---- forward values (the same arithmetic as eval_channels_t)
-  const double v = wm(M_CM) * b.f13;
-  const double w = wm(M_CMI) * b.fm13;
-  const double lnv = b.lnf * (1.0 / 3.0) + wm(M_LNCM);
-  const double w2 = w * w, w3 = w2 * w, w4 = w2 * w2, w5 = w4 * w, w6 = w4 * w2, w8 = w4 * w4;
-  const double v2 = v * v, lv = lnv * v, lw2 = lnv * w2;
-  double ph = wm(M_A4) * w;
-  ph = fma(wm(M_A3), w2, ph);
-  ph = fma(wm(M_A2), w3, ph);
-  ph = fma(wm(M_A0), w5, ph);
-  ph = fma(wm(M_B5), lnv, ph);
-  ph = fma(wm(M_A6), v, ph);
-  ph = fma(wm(M_B6), lv, ph);
-  ph = fma(wm(M_A7), v2, ph);
-  const double phase = ftc + (ph + wm(M_C0));
-  double tau = wm(M_T7) * w;
-  tau = fma(wm(M_T6), w2, tau);
-  tau = fma(wm(M_T6L), lw2, tau);
-  tau = fma(wm(M_T5), w3, tau);
-  tau = fma(wm(M_T4), w4, tau);
-  tau = fma(wm(M_T3), w5, tau);
-  tau = fma(wm(M_T2), w6, tau);
-  tau = fma(wm(M_T0), w8, tau);
-  const double amp0 = (fma(wm(M_AM2), v2, wm(M_AM1) * v) + wm(M_AM0)) * b.fm76;
+  // ---- forward values (the same arithmetic as eval_channels_t).  The
+  // waveform's intermediate powers are not kept through the geometry part:
+  // they are recomputed for the waveform reverse below, which keeps the live
+  // register set of this function small.
+  double phase, tau, amp0;
+  {
+    const double v = wm(M_CM) * b.f13;
+    const double w = wm(M_CMI) * b.fm13;
+    const double lnv = b.lnf * (1.0 / 3.0) + wm(M_LNCM);
+    const double w2 = w * w, w3 = w2 * w, w4 = w2 * w2, w5 = w4 * w, w6 = w4 * w2, w8 = w4 * w4;
+    const double v2 = v * v, lv = lnv * v, lw2 = lnv * w2;
+    double ph = wm(M_A4) * w;
+    ph = fma(wm(M_A3), w2, ph);
+    ph = fma(wm(M_A2), w3, ph);
+    ph = fma(wm(M_A0), w5, ph);
+    ph = fma(wm(M_B5), lnv, ph);
+    ph = fma(wm(M_A6), v, ph);
+    ph = fma(wm(M_B6), lv, ph);
+    ph = fma(wm(M_A7), v2, ph);
+    phase = ftc + (ph + wm(M_C0));
+    tau = wm(M_T7) * w;
+    tau = fma(wm(M_T6), w2, tau);
+    tau = fma(wm(M_T6L), lw2, tau);
+    tau = fma(wm(M_T5), w3, tau);
+    tau = fma(wm(M_T4), w4, tau);
+    tau = fma(wm(M_T3), w5, tau);
+    tau = fma(wm(M_T2), w6, tau);
+    tau = fma(wm(M_T0), w8, tau);
+    amp0 = (fma(wm(M_AM2), v2, wm(M_AM1) * v) + wm(M_AM0)) * b.fm76;
+  }
   double tap = 1.0, dtap = 0.0;   // taper and its derivative in x
   if (x > 0.9) {
     const double u = (x - 0.9) * 10.0;
@@ -186,9 +273,9 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   // ---- reverse: arms
   double pEbr = 0.0, pEbi = 0.0, cEbr = 0.0, cEbi = 0.0;
   double cb0, sb0, knb0, npb0, nqb0, cb1, sb1, knb1, npb1, nqb1, cb2, sb2, knb2, npb2, nqb2;
-  adj_arm<LS>(yb[0], a, pEr, pEi, cEr, cEi, c0, s0, np0, nq0, kn0, pEbr, pEbi, cEbr, cEbi, cb0, sb0, knb0, npb0, nqb0);
-  adj_arm<LS>(yb[1], a, pEr, pEi, cEr, cEi, c1, s1, np1, nq1, kn1, pEbr, pEbi, cEbr, cEbi, cb1, sb1, knb1, npb1, nqb1);
-  adj_arm<LS>(yb[2], a, pEr, pEi, cEr, cEi, c2, s2, np2, nq2, kn2, pEbr, pEbi, cEbr, cEbi, cb2, sb2, knb2, npb2, nqb2);
+  adj_arm<LS>(yb, a, pEr, pEi, cEr, cEi, c0, s0, np0, nq0, kn0, pEbr, pEbi, cEbr, cEbi, cb0, sb0, knb0, npb0, nqb0);
+  adj_arm<LS>(yb + 4, a, pEr, pEi, cEr, cEi, c1, s1, np1, nq1, kn1, pEbr, pEbi, cEbr, cEbi, cb1, sb1, knb1, npb1, nqb1);
+  adj_arm<LS>(yb + 8, a, pEr, pEi, cEr, cEi, c2, s2, np2, nq2, kn2, pEbr, pEbi, cEbr, cEbi, cb2, sb2, knb2, npb2, nqb2);
   // aP E, 2 aC E with E = (cp, -sp)
   const double aPb = fma(pEbr, cp, -(pEbi * sp));
   const double aCb = fma(cEbr, cp, -(cEbi * sp));
@@ -256,10 +343,17 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   const double xb = ampb * amp0 * dtap;
   const double qa = ampb * tap * b.fm76;
   DepMQD::add(g, qa, tm(M_AM0));
+  DepM::add(g, xb * b.f, tm(M_FCI));
+  // recompute the waveform powers (from opaque copies of the bin values, so
+  // the forward ones are not kept alive)
+  const double v = wm(M_CM) * opaque(b.f13);
+  const double w = wm(M_CMI) * opaque(b.fm13);
+  const double lnv = opaque(b.lnf) * (1.0 / 3.0) + wm(M_LNCM);
+  const double w2 = w * w, w3 = w2 * w, w4 = w2 * w2, w5 = w4 * w, w6 = w4 * w2, w8 = w4 * w4;
+  const double v2 = v * v, lv = lnv * v, lw2 = lnv * w2;
   DepMQD::add(g, qa * v, tm(M_AM1));
   DepMQD::add(g, qa * v2, tm(M_AM2));
   double vb = qa * fma(2.0 * wm(M_AM2), v, wm(M_AM1));
-  DepM::add(g, xb * b.f, tm(M_FCI));
   // ---- t_f - t_c
   DepMQ::add(g, taub * w, tm(M_T7));
   DepMQ::add(g, taub * w2, tm(M_T6));
@@ -281,7 +375,7 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   double lnvb = taub * wm(M_T6L) * w2;
   // ---- phase
   const double phb = Phib;
-  DepTc::add(g, phb * b.f, tn + W_TC * kNParams);
+  DepTc::add(g, phb * b.f, tn);
   DepQPhi::add(g, phb, tm(M_C0));
   DepQ::add(g, phb * w5, tm(M_A0));
   DepQ::add(g, phb * w3, tm(M_A2));

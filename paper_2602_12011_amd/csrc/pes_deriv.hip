@@ -155,7 +155,7 @@ template <bool LS, bool GEO>
 __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const double* __restrict__ tb,
                                         const double* __restrict__ wt, const double* __restrict__ wtn,
                                         const JacArgs& A, int det, int64_t k, bool in, double* g,
-                                        double& dh, double& hh) {
+                                        double& dh, double& hh, double* __restrict__ ybs) {
   const int64_t N = A.N;
   const int64_t kk = in ? k : N - 1;
   BinRegs br;
@@ -185,24 +185,32 @@ __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const d
   const double a2 = fma(c.ar, c.ar, c.ai * c.ai) + (1.0 / 3.0) * fma(c.er, c.er, c.ei * c.ei);
   const double t2 = fma(c.tr, c.tr, c.ti * c.ti);
   hh = fma(wA, a2, fma(wT, t2, hh));
-  double yb[3][4];
-  adj_links(c, D, wA, wT, zr, zi, yb);
+  {   // the link adjoints wait in LDS (this lane's 12 slots) while the modes run
+    double yb[3][4];
+    adj_links(c, D, wA, wT, zr, zi, yb);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) ybs[q] = yb[q / 4][q % 4];
+  }
   const double ftc = frac_prod(br.f, wt[W_TC]);
 #pragma unroll 1
   for (int j = 0; j < A.n_modes; ++j)
-    adj_unit<GEO, LS>(wt, wtn, det, j, P.inv_year, P.inv_ptq, br, a, ftc, yb, g);
+    adj_unit<GEO, LS>(wt, wtn, det, j, P.inv_year, P.inv_ptq, br, a, ftc, ybs, g);
 }
 
-// The walker's tangent table is staged in LDS: the contraction reads ~150 of
-// its entries per mode unit as wave-uniform LDS broadcasts, which keeps them
-// out of the scalar registers and their spills (the walker table itself stays
-// on scalar loads: staging it too moves the pressure into vector registers).
+// The walker's tangents are staged in LDS in the compact layout (4.5 KiB):
+// the contraction reads ~150 of them per mode unit as wave-uniform LDS
+// broadcasts, which keeps them out of the scalar registers and their spills
+// (the walker table itself stays on scalar loads: staging it too moves the
+// pressure into vector registers).
+// Two waves per SIMD: the reverse sweep fits 254 registers (a couple of
+// spilled values); one wave per SIMD leaves its long dependency chains exposed.
 template <bool LS>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     adj_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                const double* __restrict__ wtab, const double* __restrict__ wtan,
                double* __restrict__ partial, JacArgs A) {
-  __shared__ double tan_s[W_STRIDE * kNParams];
+  __shared__ double tan_s[kTanSlots];
+  __shared__ double yb_s[64 * 12];
   const int t = blockIdx.x;
   const int b = blockIdx.y;
   const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
@@ -212,8 +220,7 @@ __global__ void __launch_bounds__(64)
   if (k0 >= nact) return;
   const int lane = threadIdx.x;
   {
-    const double* __restrict__ src = wtan + (int64_t)b * W_STRIDE * kNParams;
-    for (int i = lane; i < W_STRIDE * kNParams; i += 64) tan_s[i] = src[i];
+    compact_tangents(wtan + (int64_t)b * W_STRIDE * kNParams, tan_s, lane, 64);
     __syncthreads();
   }
   const double* wtn = tan_s;
@@ -228,9 +235,9 @@ __global__ void __launch_bounds__(64)
     for (int det = 0; det < A.n_det; ++det) {
       const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * A.N;
       if (A.dt.p[det].kind == 2)
-        adj_det<LS, true>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh);
+        adj_det<LS, true>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, yb_s + 12 * lane);
       else
-        adj_det<LS, false>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh);
+        adj_det<LS, false>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, yb_s + 12 * lane);
     }
   }
   double red[kNParams + 2];
