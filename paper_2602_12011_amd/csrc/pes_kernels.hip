@@ -616,25 +616,41 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// log L = <d|h> - <h|h>/2 - <d|d>/2, tiles summed in order (partial is
-// tile-major, [tile][walker][2], so neighbouring threads read neighbouring data).
-__global__ void finalize_kernel(const double* __restrict__ partial, const int* __restrict__ ntiles,
-                                const double* __restrict__ wtab, const double* __restrict__ dd,
-                                int64_t B, double* __restrict__ logl) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  if (wtab[b * W_STRIDE + W_VALID] == 0.0) {
-    logl[b] = -INFINITY;
-    return;
-  }
-  const int nt = ntiles[b];
+// log L = <d|h> - <h|h>/2 - <d|d>/2.  partial is tile-major, [tile][walker][2].
+// A block takes kFinW walkers; its kFinP thread rows each sum the tiles
+// t = row, row + kFinP, ... of every walker (neighbouring threads read
+// neighbouring walkers), then the row sums are combined in a fixed order, so
+// the result does not depend on the launch or on the batch order.
+constexpr int kFinW = 32, kFinP = 32;
+__global__ void __launch_bounds__(kFinW * kFinP)
+    finalize_kernel(const double* __restrict__ partial, const int* __restrict__ ntiles,
+                    const double* __restrict__ wtab, const double* __restrict__ dd, int64_t B,
+                    double* __restrict__ logl) {
+  __shared__ double sh[kFinP][kFinW][2];
+  const int wl = threadIdx.x % kFinW, row = threadIdx.x / kFinW;
+  const int64_t b = (int64_t)blockIdx.x * kFinW + wl;
   double dh = 0.0, hh = 0.0;
-  for (int t = 0; t < nt; ++t) {
-    const double* p = partial + ((int64_t)t * B + b) * 2;
-    dh += p[0];
-    hh += p[1];
+  if (b < B) {
+    const int nt = ntiles[b];
+    for (int t = row; t < nt; t += kFinP) {
+      const double* p = partial + ((int64_t)t * B + b) * 2;
+      dh += p[0];
+      hh += p[1];
+    }
   }
-  logl[b] = (dh - 0.5 * hh) - 0.5 * dd[0];
+  sh[row][wl][0] = dh;
+  sh[row][wl][1] = hh;
+  __syncthreads();
+  for (int h = kFinP / 2; h > 0; h >>= 1) {   // pairwise tree over the rows
+    if (row < h) {
+      sh[row][wl][0] += sh[row + h][wl][0];
+      sh[row][wl][1] += sh[row + h][wl][1];
+    }
+    __syncthreads();
+  }
+  if (row == 0 && b < B)
+    logl[b] = wtab[b * W_STRIDE + W_VALID] == 0.0 ? -INFINITY
+                                                  : (sh[0][wl][0] - 0.5 * sh[0][wl][1]) - 0.5 * dd[0];
 }
 
 // ---------------------------------------------------------------- response
@@ -730,9 +746,8 @@ hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, int gri
 
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
                            int64_t B, double* logl, hipStream_t s) {
-  const int bs = 256;
-  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((B + bs - 1) / bs)), dim3(bs), 0, s, partial, ntiles,
-                     wtab, dd, B, logl);
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((B + kFinW - 1) / kFinW)), dim3(kFinW * kFinP), 0, s, partial,
+                     ntiles, wtab, dd, B, logl);
   return hipGetLastError();
 }
 
