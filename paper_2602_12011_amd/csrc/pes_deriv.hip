@@ -68,7 +68,7 @@ __device__ __forceinline__ void jac_det(const double* __restrict__ bins, const d
     }
     if (FISHER) {
 #pragma unroll
-      for (int r = 0; r < 6; ++r) J[(6 * lane + r) * 16 + kp] = sqrt(W[r]) * cd[r];
+      for (int r = 0; r < 6; ++r) J[(6 * lane + r) * kNParams + kp] = sqrt(W[r]) * cd[r];
     } else {
       double acc = 0.0;
 #pragma unroll
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(64)
     jac_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                const double* __restrict__ wtab, const double* __restrict__ wtan,
                double* __restrict__ partial, JacArgs A) {
-  __shared__ double J[FISHER ? 64 * 6 * 16 : 1];
+  __shared__ double J[FISHER ? 64 * 6 * kNParams : 1];   // [bin row][parameter], 33 KiB
   const int t = blockIdx.x;
   const int b = blockIdx.y;
   const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
@@ -101,10 +101,6 @@ __global__ void __launch_bounds__(64)
   double dh = 0.0, hh = 0.0;
   typedef double v4d __attribute__((ext_vector_type(4)));
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  if (FISHER) {
-    for (int i = lane; i < 64 * 6 * 16; i += 64) J[i] = 0.0;   // padding columns stay 0
-    __syncthreads();
-  }
   for (int64_t s0 = k0; s0 < kend; s0 += 64) {
     const int64_t k = s0 + lane;
     const bool in = k < kend;
@@ -119,7 +115,8 @@ __global__ void __launch_bounds__(64)
         // acc += Jt^T Jt over the 384 rows of this sub-tile, 4 rows per operation:
         // operand element (row 4q + lane/16, column lane%16) serves as both A and B.
         for (int q = 0; q < 96; ++q) {
-          const double v = J[(4 * q + (lane >> 4)) * 16 + (lane & 15)];
+          const int col = lane & 15;   // parameters padded to 16 with zeros
+          const double v = col < kNParams ? J[(4 * q + (lane >> 4)) * kNParams + col] : 0.0;
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
         }
         __syncthreads();
