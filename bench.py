@@ -30,40 +30,67 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6     # MI355X FP64 vector peak (AMD specification)
 
 # FP64 operations (FMA counted as 2) of the kernel's formulation, counted from
 # its source: per active (walker, bin, detector, mode) unit -- heliocentric or
-# geocentric orbit, short or long sinc fit -- and per active (walker, bin,
-# detector) for the TDI combination and the inner products.  Not counted: the
-# C^2 taper (the last 10% below each cutoff) and the quarter-turn rotation of
-# the sine/cosine reduction (products with 0 and +-1).
-FLOPS_PER_MODE_UNIT = {("helio", False): 442, ("geo", False): 469,
-                       ("helio", True): 474, ("geo", True): 501}
+# geocentric orbit, short or long sinc fit, fit class of the bin's wavefront --
+# and per active (walker, bin, detector) for the TDI combination and the inner
+# products.  Not counted: the C^2 taper (the last 10% below each cutoff) and
+# the quarter-turn rotation of the sine/cosine reduction (products with 0 and
+# +-1).  A wavefront of 64 consecutive bins whose largest link sinc argument
+# 2 pi f L stays at or below 0.5 (class 0) evaluates the sinc and the arm
+# phases with shorter fits of that range; class 1 is the full range.
+FLOPS_PER_MODE_UNIT = {("helio", False, 1): 442, ("geo", False, 1): 469,
+                       ("helio", True, 1): 474, ("geo", True, 1): 501,
+                       ("helio", False, 0): 390, ("geo", False, 0): 417,
+                       ("helio", True, 0): 390, ("geo", True, 0): 417}
 FLOPS_PER_WBD_UNIT = 83
+CLASS_BMAX0 = 0.5
 MF_ISCO = 6.0 ** -1.5 / math.pi
 MSUN_S = 4.925490947641267e-6
 
 
-def active_units(cfg, theta):
-    """(mode units, walker-bin units) per detector that one pes_loglike evaluates."""
+def mode_bin_counts(cfg, theta):
+    """Active bins per (walker, mode) -- bins k < n below the mode's cutoff --
+    and, per walker, the largest of them."""
     N, f0, df = cfg["n_bins"], cfg["f0"], cfg["df"]
     M = theta[:, 0] * MSUN_S
-    n_mode = np.zeros(len(theta))
-    n_any = np.zeros(len(theta))
+    ns = []
     for (l, m) in cfg["modes"]:
         fcut = 0.5 * m * MF_ISCO / M
-        n = np.clip(np.ceil((fcut - f0) / df), 0, N)
-        n_mode += n
-        n_any = np.maximum(n_any, n)
-    return float(n_mode.sum()), float(n_any.sum())
+        ns.append(np.clip(np.ceil((fcut - f0) / df), 0, N).astype(np.int64))
+    ns = np.stack(ns, axis=1)
+    return ns, ns.max(axis=1)
+
+
+def active_units(cfg, theta):
+    """(mode units, walker-bin units) per detector that one pes_loglike evaluates."""
+    ns, nmax = mode_bin_counts(cfg, theta)
+    return float(ns.sum()), float(nmax.sum())
+
+
+def bin_classes(cfg, det):
+    """Fit class of every bin: that of its aligned 64-bin wavefront."""
+    N = cfg["n_bins"]
+    L = det["arm_m"] / 299792458.0
+    k = np.arange(((N + 63) // 64) * 64)
+    f = cfg["f0"] + np.minimum(k, N - 1) * cfg["df"]
+    bmax = (2 * math.pi * L * f).reshape(-1, 64).max(axis=1)
+    cls = np.where(bmax <= CLASS_BMAX0, 0, 1)
+    return np.repeat(cls, 64)[:N]
 
 
 def algorithmic_flops(cfg, theta):
-    n_mode, n_wb = active_units(cfg, theta)
+    ns, nmax = mode_bin_counts(cfg, theta)
+    n_mode, n_wb = float(ns.sum()), float(nmax.sum())
     f_max = cfg["f0"] + (cfg["n_bins"] - 1) * cfg["df"]
     total = 0.0
     for d in cfg["detectors"]:
         L = d["arm_m"] / 299792458.0
         long_sinc = (2 * math.pi * f_max * L) ** 2 > 4.9
         orbit = "geo" if d["kind"] == "tianqin" else "helio"
-        total += FLOPS_PER_MODE_UNIT[(orbit, long_sinc)] * n_mode + FLOPS_PER_WBD_UNIT * n_wb
+        cls = bin_classes(cfg, d)
+        for c in range(2):
+            cum = np.concatenate([[0], np.cumsum(cls == c)])
+            total += FLOPS_PER_MODE_UNIT[(orbit, long_sinc, c)] * float(cum[ns].sum())
+        total += FLOPS_PER_WBD_UNIT * n_wb
     nd = len(cfg["detectors"])
     return total, n_mode * nd, n_wb * nd
 

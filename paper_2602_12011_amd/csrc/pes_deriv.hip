@@ -54,7 +54,7 @@ __device__ __forceinline__ void jac_det(const double* __restrict__ bins, const d
   const int lane = threadIdx.x;
 #pragma unroll 1
   for (int kp = 0; kp < kNParams; ++kp) {
-    const ChanT<Dual<1>> c = eval_channels_t<GEO, LS, Dual<1>>(TanTab{wt, wtn, kp}, det, A.n_modes,
+    const ChanT<Dual<1>> c = eval_channels_t<GEO, LS, 1, Dual<1>>(TanTab{wt, wtn, kp}, det, A.n_modes,
                                                               P.inv_year, P.inv_ptq, br, a, zr, zi);
     const double cv[6] = {c.ar.v, c.ai.v, c.er.v, c.ei.v, c.tr.v, c.ti.v};
     const double cd[6] = {c.ar.d[0], c.ai.d[0], c.er.d[0], c.ei.d[0], c.tr.d[0], c.ti.d[0]};

@@ -63,6 +63,43 @@ __device__ __forceinline__ Dual<1> frac_prod(double f, const Dual<1>& tc) {
   return r;
 }
 
+// Fit classes of the log-likelihood kernel: a wavefront of bins whose link
+// sinc arguments all stay at or below kClassBMax0 (class 0) evaluates the sinc
+// and the arm phases with shorter fits of that range; class 1 is the full
+// range (the short or long sinc fit of the context).  Every fit is at FP64
+// rounding level on its range.
+template <int CLS>
+__device__ __forceinline__ void sincos_small_fit(double x, double& s, double& c) {
+  if constexpr (CLS == 0) {
+    const double t = x * x;
+    s = x * horner(kSinSmallC0, t);
+    c = horner(kCosSmallC0, t);
+  } else {
+    sincos_small(x, s, c);
+  }
+}
+template <int CLS>
+__device__ __forceinline__ void sincos_small_fit(const Dual<1>& x, Dual<1>& s, Dual<1>& c) {
+  static_assert(CLS == 1, "tangent kernels use the full-range fits");
+  sincos_small(x, s, c);
+}
+template <bool LONG, int CLS>
+__device__ __forceinline__ double sinc_fit(double b) {
+  if constexpr (CLS == 0) {
+    return horner(kSincC0, b * b);
+  } else {
+    return sinc<LONG>(b);
+  }
+}
+template <bool LONG, int CLS>
+__device__ __forceinline__ Dual<1> sinc_fit(const Dual<1>& b) {
+  static_assert(CLS == 1, "tangent kernels use the full-range fits");
+  return sinc<LONG>(b);
+}
+// Class of a wavefront whose largest link sinc argument (2 pi f L at its
+// highest frequency) is bmax.
+__device__ __forceinline__ int fit_class(double bmax) { return bmax <= kClassBMax0 ? 0 : 1; }
+
 struct BinRegs {
   double f, f13, fm13, fm76, lnf;
 };
@@ -79,7 +116,7 @@ struct ChanT {
 // Tab: accessor of this walker's constant table (wavefront-uniform); det: the
 // detector block.  S = double (values) or Dual<1> (value and one tangent).
 // GEO selects the geocentric orbit.  a = pi f L, (zr, zi) = e^{-2 pi i f L}.
-template <bool GEO, bool LONG_SINC, class S, class Tab>
+template <bool GEO, bool LONG_SINC, int CLS, class S, class Tab>
 __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n_modes,
                                                     double inv_year, double inv_ptq, const BinRegs& b,
                                                     double a, double zr, double zi) {
@@ -161,12 +198,12 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
     const S cEr = aC2 * cp, cEi = -(aC2 * sp);
     // per-arm phase e^{+i pi f k.Delta_t} of the spacecraft opposite arm t
     S s0, c0, s1, c1;
-    if (LONG_SINC) {
+    if (LONG_SINC && CLS == 1) {
       sincos_cycles(half_f * kd0, s0, c0);
       sincos_cycles(half_f * kd1, s1, c1);
     } else {  // |pi f k.Delta| <= pi f L / sqrt3 < 0.7 whenever the short sinc fit applies
-      sincos_small(pi_f * kd0, s0, c0);
-      sincos_small(pi_f * kd1, s1, c1);
+      sincos_small_fit<CLS>(pi_f * kd0, s0, c0);
+      sincos_small_fit<CLS>(pi_f * kd1, s1, c1);
     }
     const S c2 = fma(c0, c1, -(s0 * s1)), s2 = -fma(s0, c1, c0 * s1);
 
@@ -177,7 +214,7 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
     const S pp = fma(np, np, -(nq * nq)), pc = np * nq;               \
     const S Wr = fma(pp, pEr, -(pc * cEi)), Wi = fma(pp, pEi, pc * cEr); \
     const S Gr = fma(Wr, er, -(Wi * ei)), Gi = fma(Wr, ei, Wi * er); \
-    const S sf = sinc<LONG_SINC>(fma(-a, kn, a)), sb = sinc<LONG_SINC>(fma(a, kn, a)); \
+    const S sf = sinc_fit<LONG_SINC, CLS>(fma(-a, kn, a)), sb = sinc_fit<LONG_SINC, CLS>(fma(a, kn, a)); \
     FR = fma(sf, Gr, FR);                                             \
     FI = fma(sf, Gi, FI);                                             \
     BR = fma(sb, Gr, BR);                                             \
@@ -212,13 +249,22 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
   return c;
 }
 
-template <bool GEO, bool LONG_SINC>
+template <bool GEO, bool LONG_SINC, int CLS = 1>
 __device__ __forceinline__ Chan eval_channels(const double* __restrict__ wt, int det, int n_modes,
                                               double inv_year, double inv_ptq, const BinRegs& b,
                                               double a, double zr, double zi) {
-  const ChanT<double> c = eval_channels_t<GEO, LONG_SINC, double>(ValTab{wt}, det, n_modes, inv_year,
+  const ChanT<double> c = eval_channels_t<GEO, LONG_SINC, CLS, double>(ValTab{wt}, det, n_modes, inv_year,
                                                                   inv_ptq, b, a, zr, zi);
   return Chan{c.ar, c.ai, c.er, c.ei, c.tr, c.ti};
+}
+
+// eval_channels with the fit class chosen at run time (a wave-uniform branch).
+template <bool GEO, bool LONG_SINC>
+__device__ __forceinline__ Chan eval_channels_cls(int cls, const double* __restrict__ wt, int det, int n_modes,
+                                                  double inv_year, double inv_ptq, const BinRegs& b, double a,
+                                                  double zr, double zi) {
+  if (cls == 0) return eval_channels<GEO, LONG_SINC, 0>(wt, det, n_modes, inv_year, inv_ptq, b, a, zr, zi);
+  return eval_channels<GEO, LONG_SINC, 1>(wt, det, n_modes, inv_year, inv_ptq, b, a, zr, zi);
 }
 
 }  // namespace pes

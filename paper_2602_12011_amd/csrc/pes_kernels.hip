@@ -499,7 +499,7 @@ __global__ void __launch_bounds__(1024) plan_kernel(const int* __restrict__ ntil
 // each lane evaluating its bins, then a wavefront reduction and one LDS slot
 // per (walker, wave).  partial[w][tile] = (<d|h>, <h|h>) of that tile.
 template <int BPL, bool LS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     loglike_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                    const double* __restrict__ wtab, const int* __restrict__ ntiles,
                    const int* __restrict__ perm, const int* __restrict__ gstart,
@@ -561,6 +561,10 @@ __global__ void __launch_bounds__(256)
         if (!in[q]) { dar[q] = dai[q] = der[q] = dei[q] = dtr[q] = dti[q] = 0.0; }
       }
       const DetParams& P = A.dt.p[det];
+      // fit class of each of this wave's bin sets (wave-uniform)
+      int cls[BPL];
+#pragma unroll
+      for (int q = 0; q < BPL; ++q) cls[q] = __builtin_amdgcn_readfirstlane(fit_class(2.0 * wave_max(aa[q])));
       for (int s = 0; s < A.wg; ++s) {
         const int idx = g * A.wg + s;
         if (idx >= A.B) break;
@@ -571,8 +575,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int q = 0; q < BPL; ++q) {
           const Chan c = (P.kind == 2)
-                             ? eval_channels<true, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
-                             : eval_channels<false, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
+                             ? eval_channels_cls<true, LS>(cls[q], wt, det, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
+                             : eval_channels_cls<false, LS>(cls[q], wt, det, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
           dh = fma(dar[q], c.ar, dh);
           dh = fma(dai[q], c.ai, dh);
           dh = fma(der[q], c.er, dh);

@@ -84,6 +84,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// 64-lane wavefront maximum (every lane ends with it).
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 // One DPP lane permutation of a double (two 32-bit moves).  Rows outside
 // ROW_MASK receive 0.
 template <int CTRL, int ROW_MASK>
