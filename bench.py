@@ -209,6 +209,77 @@ def graph_leg(torch, pes, steps):
                 graph_ms_per_step=round(t_graph, 4), graph_speedup=round(t_eager / t_graph, 3))
 
 
+def schedule_utilisation(cfg, theta, tile, grid):
+    """Share of the walker-bins a schedule processes that lie below the
+    walker's highest mode cutoff, and the share of its mode slots (walker-bins
+    x modes) that are active."""
+    ns, nmax = mode_bin_counts(cfg, theta)
+    N = cfg["n_bins"]
+    if grid:
+        processed = len(theta) * ((N + tile - 1) // tile) * tile
+    else:   # the kernel's active tiles cover one bin beyond the highest cutoff
+        nact = np.minimum(nmax + 1, N)
+        processed = float((((nact + tile - 1) // tile) * tile).sum())
+    return float(nmax.sum()) / processed, float(ns.sum()) / (processed * len(cfg["modes"]))
+
+
+def config2_leg(torch, pes, reps):
+    """Three detectors, 16384 walkers, 2^20 bins, 5 modes: the persistent
+    queue against a plain grid, the default tuning against the autotuned
+    one, eager calls against one captured-graph replay."""
+    cfg = W.config("cfg2")
+    B = cfg["walkers"]
+    dev = torch.device("cuda:0")
+    theta_np = W.draw_walkers(B, stream=2)
+    ctx = pes.Context(cfg)
+    ctx.reserve(B)
+    th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
+    ctx.set_data(ctx.response(th0)[0].clone())
+    theta = torch.from_numpy(theta_np).to(dev)
+    out = torch.empty(B, dtype=torch.float64, device=dev)
+
+    def run():
+        ctx.loglike(theta, out)
+
+    res = dict(workload="LISA+Taiji+TianQin, 5 modes, 2^20 bins, 16384 walkers")
+    tun0 = ctx.get_tuning()
+    t_default = _time_ms(torch, run, reps)
+    _, tun = ctx.autotune(theta)
+    t_queue = _time_ms(torch, run, reps)
+    L_queue = out.cpu().numpy()
+    ctx.set_schedule("grid")
+    t_grid = _time_ms(torch, run, reps)
+    L_grid = out.cpu().numpy()
+    ctx.set_schedule("queue")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    t_graph = _time_ms(torch, g.replay, reps)
+    L_graph = out.cpu().numpy()
+    ctx.close()
+    tile = 256 * tun["bins_per_lane"]
+    uq = schedule_utilisation(cfg, theta_np, tile, False)
+    ug = schedule_utilisation(cfg, theta_np, tile, True)
+    res.update(
+        default_tuning=tun0, autotuned_tuning=tun,
+        queue_default_tuning_ms=round(t_default, 2), queue_autotuned_ms=round(t_queue, 2),
+        grid_autotuned_ms=round(t_grid, 2), queue_graph_replay_ms=round(t_graph, 2),
+        evals_per_s=round(B / (t_queue * 1e-3), 1),
+        queue_speedup_over_grid=round(t_grid / t_queue, 3),
+        autotune_speedup=round(t_default / t_queue, 3),
+        graph_speedup=round(t_queue / t_graph, 4),
+        queue_walker_bin_utilisation=round(uq[0], 4), queue_mode_slot_utilisation=round(uq[1], 4),
+        grid_walker_bin_utilisation=round(ug[0], 4), grid_mode_slot_utilisation=round(ug[1], 4),
+        grid_bitwise_equal=bool(np.array_equal(L_queue, L_grid)),
+        graph_bitwise_equal=bool(np.array_equal(L_queue, L_graph)))
+    return res
+
+
 def _prior_spec():
     spec = []
     for name in W.PARAM_NAMES:
@@ -338,8 +409,8 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="bins_per_lane,walkers_per_group,blocks_per_cu (skips the autotuner)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="only the headline measurement (no derivative, graph or ESS legs)")
-    ap.add_argument("--extras", default="derivatives,graph,ess",
+                    help="only the headline measurement (no derivative, graph, config-2 or ESS legs)")
+    ap.add_argument("--extras", default="derivatives,graph,config2,ess",
                     help="comma list of the extra legs to run after the headline")
     ap.add_argument("--ess-walkers", type=int, default=1024)
     ap.add_argument("--ess-pilot", type=int, default=1000)
@@ -431,6 +502,9 @@ def main():
     if "graph" in extras:
         print("[bench] sampler graph", file=sys.stderr, flush=True)
         rec["sampler_graph"] = graph_leg(torch, pes, 50)
+    if "config2" in extras:
+        print("[bench] config 2 schedules", file=sys.stderr, flush=True)
+        rec["config2"] = config2_leg(torch, pes, 3)
     if "ess" in extras:
         print("[bench] ESS", file=sys.stderr, flush=True)
         rec["ess"] = ess_leg(torch, pes, args.ess_walkers, args.ess_pilot, args.ess_steps, args.ess_fit_steps)

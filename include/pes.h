@@ -267,10 +267,26 @@ int pes_philox(uint64_t key, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
 int pes_set_tuning(pes_ctx* ctx, int bins_per_lane, int walkers_per_group, int blocks_per_cu);
 int pes_get_tuning(pes_ctx* ctx, int* bins_per_lane, int* walkers_per_group, int* blocks_per_cu);
 
+/* Work schedule of pes_loglike (the batching of many samples per launch that
+ * the paper lists as future work, Sec. 4):
+ *   PES_SCHED_QUEUE (default): walkers sorted by their active tile count
+ *     (bins below the highest mode cutoff), a persistent grid taking
+ *     (walker group, tile) items from an atomic ticket over active tiles only.
+ *   PES_SCHED_GRID: a plain grid of one block per (walker group, tile) over
+ *     every tile of the frequency grid, walkers in batch order (each mode still
+ *     skips the bins beyond its cutoff).  Kept for measuring what the queue
+ *     saves; PES_ESHAPE when the item count exceeds 2^31 - 1.
+ * Both give bitwise the same log-likelihoods.  PES_EINVAL for another value. */
+enum { PES_SCHED_QUEUE = 0, PES_SCHED_GRID = 1 };
+int pes_set_schedule(pes_ctx* ctx, int schedule);
+
 /* Autotuner: runs pes_loglike on the given batch (theta dev [B][11], logl
- * dev [B] receives the results) for every tuning candidate, keeps the
- * fastest and returns its time per call [ms] in *best_ms.  Synchronizes the
- * stream; the results do not depend on the tuning. */
+ * dev [B] receives the results) for every tuning candidate (bins per lane 1
+ * or 2, walkers per item 8, 16, 32 or 64, blocks per CU at the occupancy
+ * limit or half of it): the mean of two calls after a warm-up, then the three
+ * fastest again as the least of three single calls.  Keeps the fastest and
+ * returns its time per call [ms] in *best_ms; on an error the previous tuning
+ * stays.  Synchronizes the stream; the results do not depend on the tuning. */
 int pes_autotune(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double* best_ms,
                  void* stream);
 

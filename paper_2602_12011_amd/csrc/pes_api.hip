@@ -44,6 +44,7 @@ struct pes_ctx {
   int occ[3] = {1, 1, 1};   // occupancy limit per bins-per-lane variant
   int tile = 256;
   int grad_method = PES_GRAD_ADJOINT;
+  int schedule = PES_SCHED_QUEUE;
   int ntmax = 0;            // tiles per walker at the current tile size
   int ntmax_alloc = 0;      // tiles at the smallest tile (partial-buffer sizing)
   // workspace
@@ -336,17 +337,46 @@ int pes_get_tuning(pes_ctx* c, int* bins_per_lane, int* walkers_per_group, int* 
   return PES_OK;
 }
 
+// Time n calls of pes_loglike on the stream; returns the least single-call
+// time [ms] (n_each = 1) or the mean over the n calls (n_each = 0).
+static int time_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* stream, hipEvent_t e0,
+                        hipEvent_t e1, int n, bool n_each, double* ms_out) {
+  hipStream_t s = (hipStream_t)stream;
+  double best = 1e300, total = 0.0;
+  for (int r = 0; r < (n_each ? n : 1); ++r) {
+    if (hipEventRecord(e0, s) != hipSuccess) return PES_EHIP;
+    for (int k = 0; k < (n_each ? 1 : n); ++k) {
+      const int st = pes_loglike(c, theta, B, logl, stream);
+      if (st != PES_OK) return st;
+    }
+    float ms = 0.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return PES_EHIP;
+    best = std::min(best, (double)ms);
+    total += ms;
+  }
+  *ms_out = n_each ? best : total / n;
+  return PES_OK;
+}
+
 int pes_autotune(pes_ctx* c, const double* theta, int64_t B, double* logl, double* best_ms, void* stream) {
   if (!c || !theta || !logl || !best_ms || B < 1) return PES_EINVAL;
   if (!c->has_data) return PES_ESTATE;
-  hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   PES_HIP(c, hipEventCreate(&e0));
   PES_HIP(c, hipEventCreate(&e1));
+  // stage 1: every candidate, one warm-up and the mean of two calls;
+  // stage 2: the three fastest again, the least of three single calls
+  struct Cand {
+    int bpl, wg, bpc;
+    double ms;
+  };
+  Cand cand[16];
+  int nc = 0;
   const int bpls[2] = {1, 2};
   const int wgs[4] = {8, 16, 32, 64};
-  double best = 1e300;
-  int bb = c->bpl, bw = c->wg, bc = c->bpc;
+  const int b0 = c->bpl, w0 = c->wg, c0 = c->bpc;
   int st = PES_OK;
   for (int ib = 0; ib < 2 && st == PES_OK; ++ib)
     for (int iw = 0; iw < 4 && st == PES_OK; ++iw)
@@ -356,28 +386,24 @@ int pes_autotune(pes_ctx* c, const double* theta, int64_t B, double* logl, doubl
         if (half && bpc == occ) continue;
         pes_set_tuning(c, bpls[ib], wgs[iw], bpc);
         st = pes_loglike(c, theta, B, logl, stream);   // warm-up
-        if (st != PES_OK) break;
-        if (hipEventRecord(e0, s) != hipSuccess) { st = PES_EHIP; break; }
-        for (int r = 0; r < 2 && st == PES_OK; ++r) st = pes_loglike(c, theta, B, logl, stream);
-        if (st != PES_OK) break;
-        float ms = 0.f;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-          st = PES_EHIP;
-          break;
-        }
-        if (ms * 0.5 < best) {
-          best = ms * 0.5;
-          bb = bpls[ib];
-          bw = wgs[iw];
-          bc = bpc;
-        }
+        double ms = 0.0;
+        if (st == PES_OK) st = time_loglike(c, theta, B, logl, stream, e0, e1, 2, false, &ms);
+        if (st == PES_OK) cand[nc++] = Cand{bpls[ib], wgs[iw], bpc, ms};
       }
+  std::sort(cand, cand + nc, [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+  for (int k = 0; k < std::min(nc, 3) && st == PES_OK; ++k) {
+    pes_set_tuning(c, cand[k].bpl, cand[k].wg, cand[k].bpc);
+    st = time_loglike(c, theta, B, logl, stream, e0, e1, 3, true, &cand[k].ms);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  pes_set_tuning(c, bb, bw, bc);
-  if (st != PES_OK) return st;
-  *best_ms = best;
+  if (st != PES_OK || nc == 0) {
+    pes_set_tuning(c, b0, w0, c0);
+    return st != PES_OK ? st : PES_EHIP;
+  }
+  std::sort(cand, cand + std::min(nc, 3), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+  pes_set_tuning(c, cand[0].bpl, cand[0].wg, cand[0].bpc);
+  *best_ms = cand[0].ms;
   return PES_OK;
 }
 
@@ -434,8 +460,13 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
   int st = ensure_workspace(c, B);
   if (st != PES_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, setup_args(c), s));
-  PES_HIP(c, launch_plan(c->ntiles, (int)B, c->wg, c->ntmax, c->perm, c->gstart, c->counters, s));
+  const bool grid_mode = c->schedule == PES_SCHED_GRID;
+  const int64_t n_groups = (B + c->wg - 1) / c->wg;
+  if (grid_mode && n_groups * c->ntmax > INT32_MAX) return PES_ESHAPE;
+  SetupArgs sa = setup_args(c);
+  sa.full_tiles = grid_mode ? 1 : 0;
+  PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, sa, s));
+  PES_HIP(c, launch_plan(c->ntiles, (int)B, c->wg, c->ntmax, !grid_mode, c->perm, c->gstart, c->counters, s));
   LoglikeArgs a;
   a.bins = c->bins;
   a.tabs = c->tabs;
@@ -448,13 +479,14 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
   a.N = c->N;
   a.B = (int)B;
   a.wg = c->wg;
-  a.n_groups = (int)((B + c->wg - 1) / c->wg);
+  a.n_groups = (int)n_groups;
   a.ntmax = c->ntmax;
   a.n_modes = c->cfg.n_modes;
   a.n_det = c->cfg.n_det;
   a.dt = c->dt;
   const int bpc = c->bpc > 0 ? std::min(c->bpc, c->occ[c->bpl]) : c->occ[c->bpl];
-  const int grid = c->n_cu * bpc;
+  const int grid = grid_mode ? (int)(n_groups * c->ntmax) : c->n_cu * bpc;
+  a.grid_mode = grid_mode ? 1 : 0;
   const bool rec = c->timing && c->n_ev < kMaxEv;
   if (rec) PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev], s));
   PES_HIP(c, launch_loglike(a, c->bpl, c->long_sinc, grid, s));
@@ -489,6 +521,12 @@ int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* g
   PES_HIP(c, launch_setup_tan(theta, B, c->wtab, c->wtan, c->ntiles, setup_args(c), s));
   PES_HIP(c, launch_grad(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, c->dd, jac_args(c, B, kGradTile),
                          c->long_sinc, c->grad_method == PES_GRAD_ADJOINT, logl, grad, s));
+  return PES_OK;
+}
+
+int pes_set_schedule(pes_ctx* c, int schedule) {
+  if (!c || (schedule != PES_SCHED_QUEUE && schedule != PES_SCHED_GRID)) return PES_EINVAL;
+  c->schedule = schedule;
   return PES_OK;
 }
 

@@ -324,6 +324,7 @@ __device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put)
 }
 
 __device__ int active_tiles(double fmx, const SetupArgs& sa, int tile) {
+  if (sa.full_tiles) return (int)((sa.N + tile - 1) / tile);
   // active bins: f_k < fmax (upper bound; the kernels test each mode exactly)
   double nb = ceil((fmx - sa.f0) / sa.df) + 1.0;
   nb = fmin(fmax(nb, 0.0), (double)sa.N);
@@ -420,53 +421,57 @@ __device__ int block_exclusive_scan(int* __restrict__ a, int n, int* wsum) {
 }
 
 __global__ void __launch_bounds__(1024) plan_kernel(const int* __restrict__ ntiles, int B, int wg,
-                                                    int ntmax, int* __restrict__ perm,
+                                                    int ntmax, int sorted, int* __restrict__ perm,
                                                     int* __restrict__ gstart, int* __restrict__ counters) {
   __shared__ int hist[kPlanKeys];
   __shared__ int wsum[17];
-  int shift = 0;
-  while ((ntmax >> shift) >= kPlanKeys) ++shift;
-  for (int i = threadIdx.x; i < kPlanKeys; i += blockDim.x) hist[i] = 0;
-  __syncthreads();
-  for (int b = threadIdx.x; b < B; b += blockDim.x) {
-    const int key = kPlanKeys - 1 - (ntiles[b] >> shift);   // descending tile counts
-    atomicAdd(&hist[key], 1);
-  }
-  __syncthreads();
-  {  // exclusive scan of the histogram in LDS (8 entries per thread)
-    const int per = kPlanKeys / 1024;
-    const int base = threadIdx.x * per;
-    int local = 0;
-    for (int i = 0; i < per; ++i) local += hist[base + i];
-    int incl = local;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int o = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += o;
-    }
-    if (lane == 63) wsum[wv] = incl;
+  if (sorted) {  // counting sort by descending tile count
+    int shift = 0;
+    while ((ntmax >> shift) >= kPlanKeys) ++shift;
+    for (int i = threadIdx.x; i < kPlanKeys; i += blockDim.x) hist[i] = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int run = 0;
-      for (int i = 0; i < 1024 / 64; ++i) {
-        const int t = wsum[i];
-        wsum[i] = run;
-        run += t;
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+      const int key = kPlanKeys - 1 - (ntiles[b] >> shift);   // descending tile counts
+      atomicAdd(&hist[key], 1);
+    }
+    __syncthreads();
+    {  // exclusive scan of the histogram in LDS (8 entries per thread)
+      const int per = kPlanKeys / 1024;
+      const int base = threadIdx.x * per;
+      int local = 0;
+      for (int i = 0; i < per; ++i) local += hist[base + i];
+      int incl = local;
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+      }
+      if (lane == 63) wsum[wv] = incl;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int run = 0;
+        for (int i = 0; i < 1024 / 64; ++i) {
+          const int t = wsum[i];
+          wsum[i] = run;
+          run += t;
+        }
+      }
+      __syncthreads();
+      int run = incl - local + wsum[wv];
+      for (int i = 0; i < per; ++i) {
+        const int h = hist[base + i];
+        hist[base + i] = run;
+        run += h;
       }
     }
     __syncthreads();
-    int run = incl - local + wsum[wv];
-    for (int i = 0; i < per; ++i) {
-      const int h = hist[base + i];
-      hist[base + i] = run;
-      run += h;
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+      const int key = kPlanKeys - 1 - (ntiles[b] >> shift);
+      const int pos = atomicAdd(&hist[key], 1);
+      perm[pos] = b;
     }
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b < B; b += blockDim.x) {
-    const int key = kPlanKeys - 1 - (ntiles[b] >> shift);
-    const int pos = atomicAdd(&hist[key], 1);
-    perm[pos] = b;
+  } else {  // batch order
+    for (int b = threadIdx.x; b < B; b += blockDim.x) perm[b] = b;
   }
   __syncthreads();
   // each group's tile count (the maximum over its walkers), then the
@@ -511,7 +516,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
   const int tile = 256 * BPL;
   while (true) {
     if (threadIdx.x == 0) {
-      const int it = atomicAdd(&counters[0], 1);
+      const int it = A.grid_mode ? (int)blockIdx.x : atomicAdd(&counters[0], 1);
       int g = -1;
       if (it < counters[1]) {
         // group-major: largest g with gstart[g] <= it
@@ -617,6 +622,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
       }
     }
     __syncthreads();
+    if (A.grid_mode) break;
   }
 }
 
@@ -728,9 +734,10 @@ hipError_t launch_setup(const double* theta, int64_t B, double* wtab, int* ntile
   return hipGetLastError();
 }
 
-hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, int* perm, int* gstart, int* counters,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, ntiles, B, wg, ntmax, perm, gstart, counters);
+hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, bool sorted, int* perm, int* gstart,
+                       int* counters, hipStream_t s) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, ntiles, B, wg, ntmax, sorted ? 1 : 0, perm, gstart,
+                     counters);
   return hipGetLastError();
 }
 

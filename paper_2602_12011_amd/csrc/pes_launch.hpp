@@ -20,6 +20,7 @@ struct SetupArgs {
   double f0, df;
   int64_t N;
   int tile;
+  int full_tiles;   // 1: every valid walker covers the whole grid (plain-grid schedule)
 };
 
 struct LoglikeArgs {
@@ -33,6 +34,7 @@ struct LoglikeArgs {
   double* partial;
   int64_t N;
   int B, wg, n_groups, ntmax, n_modes, n_det;
+  int grid_mode;   // 1: block i takes work item i (plain grid); 0: atomic ticket
   DetTable dt;
 };
 
@@ -68,8 +70,8 @@ hipError_t launch_setup(const double* theta, int64_t B, double* wtab, int* ntile
                         hipStream_t s);
 hipError_t launch_setup_tan(const double* theta, int64_t B, double* wtab, double* wtan, int* ntiles,
                             const SetupArgs& sa, hipStream_t s);
-hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, int* perm, int* gstart, int* counters,
-                       hipStream_t s);
+hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, bool sorted, int* perm, int* gstart,
+                       int* counters, hipStream_t s);
 hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, int grid, hipStream_t s);
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
                            int64_t B, double* logl, hipStream_t s);

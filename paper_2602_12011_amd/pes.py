@@ -40,6 +40,7 @@ class Prior(C.Structure):
 
 
 GRAD_ADJOINT, GRAD_FORWARD = 0, 1
+SCHED_QUEUE, SCHED_GRID = 0, 1
 
 PRIOR_KIND = {"uniform": 0, "loguniform": 1, "cosine_sin": 2, "sin": 2, "arcsin": 3, "cos": 3,
               "periodic": 4, "fixed": 5}
@@ -67,6 +68,7 @@ def lib():
         L.pes_grad.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
         L.pes_fisher.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.pes_set_grad_method.argtypes = [vp, C.c_int]
+        L.pes_set_schedule.argtypes = [vp, C.c_int]
         L.pes_flow_create.argtypes = [C.c_uint64, C.POINTER(vp)]
         L.pes_flow_destroy.argtypes = [vp]
         L.pes_flow_num_params.argtypes = []
@@ -108,6 +110,7 @@ def lib():
         for name in ("pes_create", "pes_destroy", "pes_reserve", "pes_set_data",
                      "pes_response", "pes_loglike", "pes_timing", "pes_timing_read",
                      "pes_set_tuning", "pes_get_tuning", "pes_autotune", "pes_grad", "pes_set_grad_method",
+                     "pes_set_schedule",
                      "pes_flow_create", "pes_flow_destroy", "pes_flow_set_params", "pes_flow_get_params",
                      "pes_flow_set_norm", "pes_flow_set_affine", "pes_flow_get_affine", "pes_flow_set_temperature", "pes_flow_forward", "pes_flow_inverse",
                      "pes_flow_nll_grad", "pes_flow_adam_step", "pes_flow_fit", "pes_sampler_set_flow",
@@ -258,6 +261,12 @@ class Context:
         self._check(lib().pes_grad(self.h, _dev_f64(theta, "theta"), B, _dev_f64(logl, "logl"),
                                    _dev_f64(g, "grad"), _stream(stream)), "pes_grad")
         return logl, g
+
+    def set_schedule(self, schedule):
+        """"queue" (persistent queue over active tiles, the default) or "grid"
+        (plain grid over every tile, batch order)."""
+        code = {"queue": SCHED_QUEUE, "grid": SCHED_GRID}[schedule]
+        self._check(lib().pes_set_schedule(self.h, code), "pes_set_schedule")
 
     def set_grad_method(self, method):
         """"adjoint" (reverse sweep, the default) or "forward" (tangents)."""

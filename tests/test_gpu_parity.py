@@ -223,3 +223,28 @@ def test_every_tuning_matches_oracle(orc, torch_dev, pes, bpl):
     L = ctx.loglike(tht).cpu().numpy()
     _check_loglike(orc, cfg, d, L, th, f"autotuned {tun}")
     ctx.close()
+
+
+def test_plain_grid_schedule_is_bitwise_the_queue(orc, torch_dev, pes):
+    """The plain-grid schedule (every tile, batch order) and the persistent
+    queue (active tiles, sorted walkers) give the same bits; one unphysical
+    walker (q > 1) stays at -inf under both."""
+    torch = torch_dev
+    cfg = _cfg("cfg2", n_bins=7000 + 3)
+    d = orc.response(cfg, W.THETA0)
+    th = W.draw_walkers(100, stream=61)
+    th[7, 1] = 1.5
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(d).to("cuda"))
+    tht = torch.from_numpy(th).to("cuda")
+    assert pes.lib().pes_set_schedule(ctx.h, 7) == -1     # PES_EINVAL
+    for bpl, wg in ((1, 1), (1, 16), (2, 7), (2, 64)):
+        ctx.set_tuning(bpl, wg, 0)
+        ctx.set_schedule("queue")
+        Lq = ctx.loglike(tht).cpu().numpy()
+        ctx.set_schedule("grid")
+        Lg = ctx.loglike(tht).cpu().numpy()
+        assert np.array_equal(Lq, Lg), (bpl, wg)
+        assert np.isneginf(Lg[7])
+    _check_loglike(orc, cfg, d, Lg, th, "plain grid")
+    ctx.close()
