@@ -128,7 +128,19 @@ def measured_traffic(tuning):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(cfg, theta, n_sample, threads):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(cfg, theta, n_sample, threads, n_single=4):
+    """The oracle on the host: n_sample walkers over `threads` threads (OpenMP
+    over walkers), and n_single walkers on one thread."""
     import oracle
     d = oracle.response(cfg, W.THETA0)
     sample = theta[:n_sample]
@@ -136,9 +148,14 @@ def cpu_baseline(cfg, theta, n_sample, threads):
     t0 = time.perf_counter()
     oracle.loglike(cfg, d, sample, nthreads=threads)
     dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.loglike(cfg, d, theta[:n_single], nthreads=1)
+    dt1 = time.perf_counter() - t0
     return dict(value=n_sample / dt, unit="logL evals/s", cores=threads, kind="oracle",
                 sample=f"{n_sample} of the {len(theta)} walkers, full {cfg['n_bins']}-bin grid, "
-                       f"5 modes, {dt:.1f} s wall")
+                       f"5 modes, {dt:.1f} s wall",
+                one_thread=dict(value=n_single / dt1, sample=f"{n_single} walkers, {dt1:.1f} s wall"),
+                cpu_model=_cpu_model(), host_cpus=os.cpu_count())
 
 
 def _time_ms(torch, fn, reps):
@@ -307,13 +324,16 @@ def _fisher_start(ctx, torch, B, seed):
     return np.clip(x, lo + eps, hi - eps)
 
 
-def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps, tau=1.1, fit_batch=1024):
+def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps, tau=1.1, fit_batch=1024, n_ref=3000):
     """ESS/s of the plain DE-MC sampler against the mixture with the learned
     flow (p_flow 0.9, temperature tau), equal numbers of steps from the same
     burned-in ensemble, on the three-detector network (cfg4's likelihood at B
-    walkers).  Accuracy: the largest per-parameter KS distance between the
-    mixture's and the plain run's draws against the one between the plain run
-    and an independent plain run (own start, own burn-in of the same length)."""
+    walkers).  Accuracy: the largest per-parameter KS distance of the
+    mixture's draws from a long plain reference (n_ref further DE steps from
+    the pilot's end, second half, every 10th step) against the one between
+    the plain run and an independent plain run (own start, own burn-in of
+    the same length); the short runs' distances from the plain run are
+    reported too."""
     from paper_2602_12011_amd import diagnostics as D
     cfg = W.config("cfg4")
     dev = torch.device("cuda:0")
@@ -331,6 +351,14 @@ def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps, tau=1.1, fit_batch=1024):
     ch = pilot.read_chain().cpu().numpy()
     state = pilot.state()[0].clone()
     pilot.close()
+    ref = pes.Sampler(ctx, prior, B, 404, chain_len=n_ref)
+    ref.set_state(state)
+    t0 = time.perf_counter()
+    ref.step(n_ref)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    ref_draws = ref.read_chain().cpu().numpy()[n_ref // 2::10].reshape(-1, 11)
+    ref.close()
     half = ch[n_pilot // 2:]
     rhat = float(D.gelman_rubin(half).max())
     # distinct states only (rejected moves repeat a state), 10% held out
@@ -377,7 +405,10 @@ def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps, tau=1.1, fit_batch=1024):
     flat = {k: v[n_run // 2:].reshape(-1, 11) for k, v in chains.items()}
     ks_lp_j = [D.ks_distance(flat["learned"][:, j], flat["plain"][:, j]) for j in range(11)]
     ks_pp_j = [D.ks_distance(flat["plain_independent"][:, j], flat["plain"][:, j]) for j in range(11)]
+    ks_lr_j = [D.ks_distance(flat["learned"][:, j], ref_draws[:, j]) for j in range(11)]
+    ks_pr_j = [D.ks_distance(flat["plain"][:, j], ref_draws[:, j]) for j in range(11)]
     ks_lp, ks_pp = max(ks_lp_j), max(ks_pp_j)
+    ks_lr, ks_pr = max(ks_lr_j), max(ks_pr_j)
     sd_ratio = flat["learned"].std(axis=0) / flat["plain"].std(axis=0)
     gain = results["learned"]["ess_per_s"] / max(results["plain"]["ess_per_s"], 1e-30)
     amort = results["learned"]["ess_min"] / (results["learned"]["seconds"] + t_fit)
@@ -391,11 +422,19 @@ def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps, tau=1.1, fit_batch=1024):
                 plain=results["plain"], learned=results["learned"],
                 plain_independent=results["plain_independent"], gain=round(gain, 2),
                 learned_ess_per_s_with_training=round(amort, 2),
+                reference=dict(steps=n_ref, seconds=round(t_ref, 2), draws=int(len(ref_draws))),
+                ks_learned_vs_reference=round(ks_lr, 4), ks_plain_vs_reference=round(ks_pr, 4),
                 ks_learned_vs_plain=round(ks_lp, 4), ks_independent_plain_vs_plain=round(ks_pp, 4),
-                accuracy_ok=bool(ks_lp <= 1.5 * ks_pp),
+                accuracy_ok=bool(ks_lr <= 1.5 * ks_pp),
+                ks_per_parameter_learned_vs_reference=[round(x, 4) for x in ks_lr_j],
+                ks_per_parameter_plain_vs_reference=[round(x, 4) for x in ks_pr_j],
                 ks_per_parameter_learned_vs_plain=[round(x, 4) for x in ks_lp_j],
                 ks_per_parameter_independent_plain_vs_plain=[round(x, 4) for x in ks_pp_j],
-                sd_ratio_learned_over_plain=[round(float(x), 3) for x in sd_ratio])
+                sd_ratio_learned_over_plain=[round(float(x), 3) for x in sd_ratio],
+                sd_ratio_learned_over_reference=[round(float(x), 3) for x in
+                                                 flat["learned"].std(axis=0) / ref_draws.std(axis=0)],
+                sd_ratio_plain_over_reference=[round(float(x), 3) for x in
+                                               flat["plain"].std(axis=0) / ref_draws.std(axis=0)])
 
 
 def main():
@@ -416,6 +455,7 @@ def main():
     ap.add_argument("--ess-pilot", type=int, default=1000)
     ap.add_argument("--ess-steps", type=int, default=300)
     ap.add_argument("--ess-fit-steps", type=int, default=300)
+    ap.add_argument("--ess-ref-steps", type=int, default=3000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -507,7 +547,8 @@ def main():
         rec["config2"] = config2_leg(torch, pes, 3)
     if "ess" in extras:
         print("[bench] ESS", file=sys.stderr, flush=True)
-        rec["ess"] = ess_leg(torch, pes, args.ess_walkers, args.ess_pilot, args.ess_steps, args.ess_fit_steps)
+        rec["ess"] = ess_leg(torch, pes, args.ess_walkers, args.ess_pilot, args.ess_steps, args.ess_fit_steps,
+                             n_ref=args.ess_ref_steps)
     print(json.dumps(rec), flush=True)
     return 0
 
