@@ -297,6 +297,62 @@ def config2_leg(torch, pes, reps):
     return res
 
 
+EXTRINSIC = (7, 8, 9, 10)   # lambda, beta, psi, t_c
+
+
+def fisher_sampling_leg(torch, pes, B, n_steps, seed=21):
+    """The extrinsic parameters (lambda, beta, psi, t_c) of the noise-free
+    injection on the LISA-like 5-mode 2^20-bin likelihood, the intrinsic ones
+    held at their injected values: the inverse of the Fisher matrix's
+    extrinsic block (pes_fisher) against the covariance of a DE-MC run
+    (pes_loglike) started from that Gaussian, second half of the chain."""
+    cfg = W.config("cfg1")
+    dev = torch.device("cuda:0")
+    ctx = pes.Context(cfg)
+    th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
+    ctx.set_data(ctx.response(th0)[0].clone())
+    S = list(EXTRINSIC)
+    F = ctx.fisher(th0).cpu().numpy()[0]
+    C_f = np.linalg.inv(F[np.ix_(S, S)])
+    C_f = 0.5 * (C_f + C_f.T)
+    prior = _prior_spec()
+    for j in range(11):
+        if j not in S:
+            prior[j] = ("fixed", W.THETA0[j], W.THETA0[j])
+    rng = np.random.default_rng(seed)
+    start = np.tile(W.THETA0, (B, 1))
+    start[:, S] = rng.multivariate_normal(W.THETA0[S], C_f, size=B)
+    smp = pes.Sampler(ctx, prior, B, seed, chain_len=n_steps)
+    smp.set_state(torch.from_numpy(start).to(dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    smp.step(n_steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    acc = smp.state()[2].cpu().numpy().sum() / (B * n_steps)
+    ch = smp.read_chain().cpu().numpy()[n_steps // 2:]
+    smp.close()
+    ctx.close()
+    from paper_2602_12011_amd import diagnostics as D
+    x = ch[:, :, S].reshape(-1, len(S))
+    C_s = np.cov(x.T)
+    sd_f, sd_s = np.sqrt(np.diag(C_f)), np.sqrt(np.diag(C_s))
+    r_f = C_f / np.outer(sd_f, sd_f)
+    r_s = C_s / np.outer(sd_s, sd_s)
+    iu = np.triu_indices(len(S), 1)
+    snr = float(np.sqrt(max(F[4, 4], 0.0)) * W.THETA0[4])   # d ln h / d ln D_L = -1: sqrt(F_DD) D_L
+    return dict(workload="LISA-like, 5 modes, 2^20 bins, noise-free injection; lambda, beta, psi, t_c free, "
+                         f"the rest fixed; {B} walkers, {n_steps} DE steps",
+                snr=round(snr, 1), seconds=round(dt, 2), acceptance=round(float(acc), 4),
+                rhat_max=round(float(D.gelman_rubin(ch[:, :, S]).max()), 4),
+                parameters=["lambda", "beta", "psi", "t_c"],
+                sd_fisher=[float(f"{v:.4g}") for v in sd_f], sd_sampled=[float(f"{v:.4g}") for v in sd_s],
+                sd_ratio_sampled_over_fisher=[round(float(v), 4) for v in sd_s / sd_f],
+                corr_fisher=[round(float(v), 4) for v in r_f[iu]],
+                corr_sampled=[round(float(v), 4) for v in r_s[iu]],
+                mean_offset_in_fisher_sd=[round(float(v), 3) for v in (x.mean(axis=0) - W.THETA0[S]) / sd_f])
+
+
 def _prior_spec():
     spec = []
     for name in W.PARAM_NAMES:
@@ -448,8 +504,8 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="bins_per_lane,walkers_per_group,blocks_per_cu (skips the autotuner)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="only the headline measurement (no derivative, graph, config-2 or ESS legs)")
-    ap.add_argument("--extras", default="derivatives,graph,config2,ess",
+                    help="only the headline measurement (no extra legs)")
+    ap.add_argument("--extras", default="derivatives,graph,config2,fisher_sampling,ess",
                     help="comma list of the extra legs to run after the headline")
     ap.add_argument("--ess-walkers", type=int, default=1024)
     ap.add_argument("--ess-pilot", type=int, default=1000)
@@ -545,6 +601,9 @@ def main():
     if "config2" in extras:
         print("[bench] config 2 schedules", file=sys.stderr, flush=True)
         rec["config2"] = config2_leg(torch, pes, 3)
+    if "fisher_sampling" in extras:
+        print("[bench] Fisher vs sampling, extrinsic parameters", file=sys.stderr, flush=True)
+        rec["fisher_sampling"] = fisher_sampling_leg(torch, pes, 1024, 1000)
     if "ess" in extras:
         print("[bench] ESS", file=sys.stderr, flush=True)
         rec["ess"] = ess_leg(torch, pes, args.ess_walkers, args.ess_pilot, args.ess_steps, args.ess_fit_steps,
