@@ -297,6 +297,93 @@ def config2_leg(torch, pes, reps):
     return res
 
 
+def _pe_walkers(n, stream):
+    """Prior draws with t_c moved to the paper's injection epoch."""
+    th = W.draw_walkers(n, stream=stream)
+    th[:, 10] += W.THETA_PE[10] - W.THETA0[10]
+    return th
+
+
+def _noisy_context(torch, pes, cfg, seed, reserve):
+    """Context with data = response(THETA_PE) + one Gaussian noise realisation."""
+    dev = torch.device("cuda:0")
+    ctx = pes.Context(cfg)
+    ctx.reserve(reserve)
+    thp = torch.from_numpy(W.THETA_PE[None, :].copy()).to(dev)
+    h0 = ctx.response(thp)[0].clone()
+    n = ctx.noise(seed)
+    return ctx, thp, h0, n
+
+
+def paper_pe_leg(torch, pes, batch=1024, n_single=10, reps=5):
+    """The paper's PE set-up (655360 s at 10 s, 32703 bins, its injection, its
+    three scenarios) with Gaussian noise from pes_noise: SNR, log L at the
+    injection against the noise's expectation, and log L evals/s one sample
+    per call (the paper's protocol; eager and as a graph replay) and batched.
+    Then the paper's cost-vs-bins axis: series of 10 s x 2^p samples, p =
+    12..21, LISA-like with five modes, per-sample time at one sample per call
+    and in batches."""
+    dev = torch.device("cuda:0")
+    out = dict(workload="paper's PE grid: 655360 s at 10 s, rfftfreq bins in [1e-4, 5e-2] Hz (32703), "
+                        "its injection (Table tab_pe_res; stand-in waveform), Gaussian noise", scenarios={})
+    th = torch.from_numpy(_pe_walkers(batch, 7)).to(dev)
+    for name in ("pe22", "pehm", "penet"):
+        cfg = W.config(name)
+        ctx, thp, h0, n = _noisy_context(torch, pes, cfg, 2026, batch)
+        far = thp.clone()
+        far[0, 4] = 1e12                      # D_L -> h ~ 0: log L = -<d|d>/2
+        ctx.set_data(h0)
+        snr = math.sqrt(-2.0 * float(ctx.loglike(far)[0]))
+        ctx.set_data(n)
+        nn = -2.0 * float(ctx.loglike(far)[0])
+        ctx.set_data(h0 + n)
+        L_inj = float(ctx.loglike(thp)[0])
+        o1 = torch.empty(1, dtype=torch.float64, device=dev)
+        t_one = np.mean([_time_ms(torch, lambda i=i: ctx.loglike(th[i:i + 1], o1), reps)
+                         for i in range(n_single)])
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        t1 = th[:1].clone()
+        with torch.cuda.stream(s):
+            ctx.loglike(t1, o1)
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx.loglike(t1, o1)
+        t_graph = _time_ms(torch, g.replay, 20)
+        ob = torch.empty(batch, dtype=torch.float64, device=dev)
+        ctx.autotune(th)
+        t_batch = _time_ms(torch, lambda: ctx.loglike(th, ob), reps)
+        ctx.close()
+        n_dof = 2 * 3 * len(cfg["detectors"]) * cfg["n_bins"]
+        out["scenarios"][name] = dict(
+            detectors=[d["kind"] for d in cfg["detectors"]], modes=len(cfg["modes"]), n_bins=cfg["n_bins"],
+            snr=round(snr, 1), noise_nn_over_dof=round(nn / n_dof, 4),
+            loglike_at_injection_over_minus_nn_half=round(L_inj / (-0.5 * nn), 12),
+            one_sample_ms=round(float(t_one), 4), one_sample_graph_ms=round(t_graph, 4),
+            batch=batch, batch_ms=round(t_batch, 3),
+            evals_per_s_one_sample=round(1e3 / float(t_one), 1),
+            evals_per_s_batched=round(batch / (t_batch * 1e-3), 1))
+    sweep = []
+    for p in range(12, 22):
+        T = W.PE_DT * 2 ** p
+        cfg = dict(detectors=[W.LISA], modes=W.MODES_HM, walkers=batch, name=f"series_2^{p}",
+                   **W.grid_series(T))
+        ctx, thp, h0, n = _noisy_context(torch, pes, cfg, 2027, batch)
+        ctx.set_data(h0 + n)
+        o1 = torch.empty(1, dtype=torch.float64, device=dev)
+        t_one = np.mean([_time_ms(torch, lambda i=i: ctx.loglike(th[i:i + 1], o1), reps)
+                         for i in range(n_single)])
+        ob = torch.empty(batch, dtype=torch.float64, device=dev)
+        t_batch = _time_ms(torch, lambda: ctx.loglike(th, ob), reps)
+        ctx.close()
+        sweep.append(dict(series_samples=2 ** p, duration_days=round(T / W.DAY_S, 2), n_bins=cfg["n_bins"],
+                          one_sample_ms=round(float(t_one), 4),
+                          batched_ms_per_sample=round(t_batch / batch, 5)))
+    out["cost_vs_bins"] = sweep
+    return out
+
+
 EXTRINSIC = (7, 8, 9, 10)   # lambda, beta, psi, t_c
 
 
@@ -505,7 +592,7 @@ def main():
                     help="bins_per_lane,walkers_per_group,blocks_per_cu (skips the autotuner)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline measurement (no extra legs)")
-    ap.add_argument("--extras", default="derivatives,graph,config2,fisher_sampling,ess",
+    ap.add_argument("--extras", default="derivatives,graph,config2,fisher_sampling,paper_pe,ess",
                     help="comma list of the extra legs to run after the headline")
     ap.add_argument("--ess-walkers", type=int, default=1024)
     ap.add_argument("--ess-pilot", type=int, default=1000)
@@ -604,6 +691,9 @@ def main():
     if "fisher_sampling" in extras:
         print("[bench] Fisher vs sampling, extrinsic parameters", file=sys.stderr, flush=True)
         rec["fisher_sampling"] = fisher_sampling_leg(torch, pes, 1024, 1000)
+    if "paper_pe" in extras:
+        print("[bench] paper's PE workload", file=sys.stderr, flush=True)
+        rec["paper_pe"] = paper_pe_leg(torch, pes)
     if "ess" in extras:
         print("[bench] ESS", file=sys.stderr, flush=True)
         rec["ess"] = ess_leg(torch, pes, args.ess_walkers, args.ess_pilot, args.ess_steps, args.ess_fit_steps,

@@ -95,6 +95,16 @@ int pes_reserve(pes_ctx* ctx, int64_t max_walkers);
  * after the call's work completes on the stream. */
 int pes_set_data(pes_ctx* ctx, const double* d, void* stream);
 
+/* One realisation of stationary Gaussian noise in the layout of pes_set_data
+ * (Sec. 2.2, eq. eq_diag_Sigma_to_Sn: the noise covariance is diagonal in
+ * frequency with <|n_k|^2> = T S_c(f_k) / 2, T = 1 / df): out (dev)
+ * [n_det][3][n_bins] complex, real and imaginary parts independent
+ * N(0, S_c(f_k) / (4 df)) for channel c of the context's PSD (A and E share
+ * S_A), exactly zero where S_c vanishes.  Philox4x32-10 keyed by seed with
+ * counter (bin, detector, channel, 0xD0), Box-Muller on its two uniform pairs.
+ * Noisy data are the response plus this array. */
+int pes_noise(pes_ctx* ctx, uint64_t seed, double* out, void* stream);
+
 /* Noise-free response: out (dev) [B][n_det][3][n_bins] complex = A, E, T of
  * h(theta_b) (eqs. eq_tf, eq_fd_resp, FD TDI, A/E/T). */
 int pes_response(pes_ctx* ctx, const double* theta, int64_t B, double* out, void* stream);

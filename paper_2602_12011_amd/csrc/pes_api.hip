@@ -433,6 +433,12 @@ static SetupArgs setup_args(const pes_ctx* c) {
   return sa;
 }
 
+int pes_noise(pes_ctx* c, uint64_t seed, double* out, void* stream) {
+  if (!c || !out) return PES_EINVAL;
+  PES_HIP(c, launch_noise(c->tabs, c->N, c->cfg.n_det, seed, out, (hipStream_t)stream));
+  return PES_OK;
+}
+
 int pes_response(pes_ctx* c, const double* theta, int64_t B, double* out, void* stream) {
   if (!c || (B > 0 && (!theta || !out)) || B < 0 || B > 65535) return PES_EINVAL;
   if (B == 0) return PES_OK;

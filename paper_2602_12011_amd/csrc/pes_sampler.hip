@@ -223,6 +223,35 @@ __global__ void flow_mix_kernel(const double* __restrict__ fprop, const double* 
 }
 
 // ---------------------------------------------------------------- launchers
+// Stationary Gaussian noise: Re, Im ~ N(0, 1 / w) with w = 4 df / S_c the
+// channel's weight (0 where S_c = 0: no noise there).
+__global__ void noise_kernel(const double* __restrict__ tabs, int64_t N, int n_det, uint64_t seed,
+                             double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  for (int det = 0; det < n_det; ++det) {
+    const double* t = tabs + (int64_t)det * T_NFIELDS * N;
+    const double wae = t[T_WAE * N + k], wtt = t[T_WTT * N + k];
+    for (int c = 0; c < 3; ++c) {
+      const double w = c < 2 ? wae : wtt;
+      const uint4 r = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)det, (uint32_t)c, 0xD0u),
+                                    (uint32_t)seed, (uint32_t)(seed >> 32));
+      const double rad = sqrt(-2.0 * log(u01(r.x, r.y)));
+      double sn, cs;
+      sincos(6.283185307179586 * u01(r.z, r.w), &sn, &cs);
+      const double sig = w > 0.0 ? sqrt(1.0 / w) : 0.0;
+      double* o = out + (((int64_t)det * 3 + c) * N + k) * 2;
+      o[0] = sig * rad * cs;
+      o[1] = sig * rad * sn;
+    }
+  }
+}
+
+hipError_t launch_noise(const double* tabs, int64_t N, int n_det, uint64_t seed, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(noise_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, tabs, N, n_det, seed, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_philox(uint64_t key, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t* out,
                          hipStream_t s) {
   hipLaunchKernelGGL(philox_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, key, c0, c1, c2, c3, n,

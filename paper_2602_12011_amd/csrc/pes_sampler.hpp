@@ -22,6 +22,7 @@ struct DeArgs {
   PriorArgs prior;
 };
 
+hipError_t launch_noise(const double* tabs, int64_t N, int n_det, uint64_t seed, double* out, hipStream_t s);
 hipError_t launch_philox(uint64_t key, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t* out,
                          hipStream_t s);
 hipError_t launch_de_propose(const double* theta, double* prop, double* qratio, const uint64_t* step,

@@ -69,6 +69,7 @@ def lib():
         L.pes_fisher.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.pes_set_grad_method.argtypes = [vp, C.c_int]
         L.pes_set_schedule.argtypes = [vp, C.c_int]
+        L.pes_noise.argtypes = [vp, C.c_uint64, vp, vp]
         L.pes_flow_create.argtypes = [C.c_uint64, C.POINTER(vp)]
         L.pes_flow_destroy.argtypes = [vp]
         L.pes_flow_num_params.argtypes = []
@@ -110,7 +111,7 @@ def lib():
         for name in ("pes_create", "pes_destroy", "pes_reserve", "pes_set_data",
                      "pes_response", "pes_loglike", "pes_timing", "pes_timing_read",
                      "pes_set_tuning", "pes_get_tuning", "pes_autotune", "pes_grad", "pes_set_grad_method",
-                     "pes_set_schedule",
+                     "pes_set_schedule", "pes_noise",
                      "pes_flow_create", "pes_flow_destroy", "pes_flow_set_params", "pes_flow_get_params",
                      "pes_flow_set_norm", "pes_flow_set_affine", "pes_flow_get_affine", "pes_flow_set_temperature", "pes_flow_forward", "pes_flow_inverse",
                      "pes_flow_nll_grad", "pes_flow_adam_step", "pes_flow_fit", "pes_sampler_set_flow",
@@ -230,6 +231,14 @@ class Context:
             raise PesError(f"data shape {tuple(d.shape)} != {(self.n_det, 3, self.n_bins, 2)}")
         self._data = d  # keep alive until the copy kernels ran
         self._check(lib().pes_set_data(self.h, _dev_f64(d, "d"), _stream(stream)), "pes_set_data")
+
+    def noise(self, seed, out=None, stream=None):
+        """One stationary Gaussian noise realisation [n_det, 3, n_bins, 2] (see pes_noise)."""
+        if out is None:
+            out = torch.empty((self.n_det, 3, self.n_bins, 2), dtype=torch.float64, device="cuda")
+        self._check(lib().pes_noise(self.h, C.c_uint64(seed & (2 ** 64 - 1)), _dev_f64(out, "out"),
+                                    _stream(stream)), "pes_noise")
+        return out
 
     def response(self, theta, out=None, stream=None):
         theta = theta.contiguous()

@@ -39,6 +39,32 @@ THETA0 = np.array([1.0e6, 0.5, 0.2, 0.1, 10.0, math.pi / 3, 0.3, 1.0, 0.2, 0.5,
                    0.5 * YEAR_S])
 
 
+def mtot_from_chirp(mc, q):
+    """Total mass from the chirp mass and q = m2/m1: M = Mc eta^(-3/5), eta = q/(1+q)^2."""
+    eta = q / (1.0 + q) ** 2
+    return mc * eta ** -0.6
+
+
+# The paper's own parameter-estimation set-up (Sec. 3.2): a 655360-s series
+# at 10-s cadence, its rfftfreq bins kept within [1e-4, 5e-2] Hz, and the
+# injection of its Table tab_pe_res (chirp mass 1.256227e6 Msun with q = 0.6,
+# chi1 0.75, chi2 0.62, D_L 56 Gpc, iota 0.4, phi 1.3, lambda 1.375,
+# beta -1.2108, psi 2.659, t_c 524288 s).  The stand-in waveform replaces
+# PhenomXAS/XHM, so posteriors are not comparable with the paper's.
+PE_T = 655360.0
+PE_DT = 10.0
+THETA_PE = np.array([mtot_from_chirp(1.256227e6, 0.6), 0.6, 0.75, 0.62, 56.0, 0.4, 1.3, 1.375,
+                     -1.2108, 2.659, 524288.0])
+
+
+def grid_series(T, f_lo=1e-4, f_hi=5e-2, dt=PE_DT):
+    """rfftfreq bins k / T of a series of duration T at cadence dt, kept within [f_lo, f_hi]."""
+    n_t = int(round(T / dt))
+    k0 = math.ceil(f_lo * T)
+    k1 = min(math.floor(f_hi * T), n_t // 2)
+    return dict(f0=k0 / T, df=1.0 / T, n_bins=int(k1 - k0 + 1))
+
+
 def grid_linear(f_lo, f_hi, n):
     """n bins from f_lo to f_hi inclusive."""
     return dict(f0=float(f_lo), df=(float(f_hi) - float(f_lo)) / (n - 1), n_bins=int(n))
@@ -59,7 +85,10 @@ def config(name, n_bins=None):
     cfg2   LISA + Taiji + TianQin, five modes, 2^20 bins, 16384 walkers;
     cfg3   cfg1's signal, 1024 walkers for gradients, 256 for Fisher matrices;
     cfg4   cfg2's network and grid, 16384 walkers, with the learned proposal
-           (11-D flow, 8 coupling layers of width 256).
+           (11-D flow, 8 coupling layers of width 256);
+    pe22, pehm, penet   the paper's three PE scenarios on its 32703-bin grid
+           (LISA with (2,2) only; LISA with five modes; the three-detector
+           network with five modes), injection THETA_PE.
     ``n_bins`` shortens the grid (same start and spacing) for quick tests.
     """
     if name == "cfg0":
@@ -76,6 +105,10 @@ def config(name, n_bins=None):
     elif name == "cfg4":
         c = dict(detectors=[LISA, TAIJI, TIANQIN], modes=MODES_HM, walkers=16384,
                  flow=dict(layers=8, width=256), **grid_rfft(1 << 20))
+    elif name in ("pe22", "pehm", "penet"):
+        dets = [LISA, TAIJI, TIANQIN] if name == "penet" else [LISA]
+        c = dict(detectors=dets, modes=MODES_22 if name == "pe22" else MODES_HM, walkers=1024,
+                 **grid_series(PE_T))
     else:
         raise KeyError(name)
     c["name"] = name
