@@ -41,6 +41,10 @@ FLOPS_PER_MODE_UNIT = {("helio", False, 1): 442, ("geo", False, 1): 469,
                        ("helio", True, 1): 474, ("geo", True, 1): 501,
                        ("helio", False, 0): 390, ("geo", False, 0): 417,
                        ("helio", True, 0): 390, ("geo", True, 0): 417}
+# A mode with the same m as an earlier one (the first such pair per m) rides on
+# that mode's unit: its amplitude, the rotated polarization factors and the
+# complex products with the phase factor cost 19 flops instead of a unit.
+FLOPS_PER_PAIRED_MODE = 19
 FLOPS_PER_WBD_UNIT = 83
 CLASS_BMAX0 = 0.5
 MF_ISCO = 6.0 ** -1.5 / math.pi
@@ -66,6 +70,20 @@ def active_units(cfg, theta):
     return float(ns.sum()), float(nmax.sum())
 
 
+def paired_modes(modes):
+    """Indices of the modes evaluated on an earlier mode's unit (same m)."""
+    out, seen = set(), set()
+    for j, (l, m) in enumerate(modes):
+        if m in seen:
+            continue
+        seen.add(m)
+        for i in range(j + 1, len(modes)):
+            if modes[i][1] == m:
+                out.add(i)
+                break
+    return out
+
+
 def bin_classes(cfg, det):
     """Fit class of every bin: that of its aligned 64-bin wavefront."""
     N = cfg["n_bins"]
@@ -87,9 +105,12 @@ def algorithmic_flops(cfg, theta):
         long_sinc = (2 * math.pi * f_max * L) ** 2 > 4.9
         orbit = "geo" if d["kind"] == "tianqin" else "helio"
         cls = bin_classes(cfg, d)
+        paired = sorted(paired_modes(cfg["modes"]))
+        units = [j for j in range(ns.shape[1]) if j not in paired]
         for c in range(2):
             cum = np.concatenate([[0], np.cumsum(cls == c)])
-            total += FLOPS_PER_MODE_UNIT[(orbit, long_sinc, c)] * float(cum[ns].sum())
+            total += FLOPS_PER_MODE_UNIT[(orbit, long_sinc, c)] * float(cum[ns[:, units]].sum())
+        total += FLOPS_PER_PAIRED_MODE * float(ns[:, paired].sum())
         total += FLOPS_PER_WBD_UNIT * n_wb
     nd = len(cfg["detectors"])
     return total, n_mode * nd, n_wb * nd

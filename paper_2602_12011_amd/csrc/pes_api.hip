@@ -45,6 +45,7 @@ struct pes_ctx {
   int tile = 256;
   int grad_method = PES_GRAD_ADJOINT;
   int schedule = PES_SCHED_QUEUE;
+  ModePlan plan;            // evaluation units: one per distinct m
   int ntmax = 0;            // tiles per walker at the current tile size
   int ntmax_alloc = 0;      // tiles at the smallest tile (partial-buffer sizing)
   // workspace
@@ -204,6 +205,38 @@ const char* pes_strerror(int s) {
 
 const char* pes_last_error(pes_ctx* ctx) { return ctx ? ctx->err : "null context"; }
 
+// Evaluation units: each mode is paired with the next unpaired mode of the
+// same m (the rotated polarization factors of the table refer to the first
+// mode with that m, so only that one leads a pair); pairs first, then the
+// modes left alone, in the order of the configuration.
+static ModePlan make_mode_plan(const ModeSpec* modes, int n) {
+  ModePlan p;
+  memset(&p, 0, sizeof(p));
+  bool used[kMaxModes] = {false, false, false, false, false};
+  for (int j = 0; j < n; ++j) {
+    bool first_of_m = true;
+    for (int i = 0; i < j; ++i)
+      if (modes[i].m == modes[j].m) first_of_m = false;
+    if (!first_of_m) continue;
+    for (int i = j + 1; i < n; ++i)
+      if (modes[i].m == modes[j].m) {
+        p.lead[p.n_pairs] = j;
+        p.member[p.n_pairs] = i;
+        used[j] = used[i] = true;
+        ++p.n_pairs;
+        break;
+      }
+  }
+  p.n_units = p.n_pairs;
+  for (int j = 0; j < n; ++j)
+    if (!used[j]) {
+      p.lead[p.n_units] = j;
+      p.member[p.n_units] = -1;
+      ++p.n_units;
+    }
+  return p;
+}
+
 int pes_create(const pes_config* cfg, pes_ctx** out) {
   if (!cfg || !out) return PES_EINVAL;
   *out = nullptr;
@@ -240,6 +273,7 @@ int pes_create(const pes_config* cfg, pes_ctx** out) {
     if (bmax * bmax > 4.9) c->long_sinc = true;
   }
   for (int i = 0; i < cfg->n_modes; ++i) c->modes[i] = ModeSpec{cfg->modes[i][0], cfg->modes[i][1]};
+  c->plan = make_mode_plan(c->modes, cfg->n_modes);
   c->tile = 256 * c->bpl;
   c->ntmax = (int)((c->N + c->tile - 1) / c->tile);
   c->ntmax_alloc = (int)((c->N + 255) / 256);
@@ -453,6 +487,7 @@ int pes_response(pes_ctx* c, const double* theta, int64_t B, double* out, void* 
   ra.out = out;
   ra.N = c->N;
   ra.n_modes = c->cfg.n_modes;
+  ra.plan = c->plan;
   ra.n_det = c->cfg.n_det;
   ra.dt = c->dt;
   PES_HIP(c, launch_response(ra, B, c->long_sinc, s));
@@ -488,6 +523,7 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
   a.n_groups = (int)n_groups;
   a.ntmax = c->ntmax;
   a.n_modes = c->cfg.n_modes;
+  a.plan = c->plan;
   a.n_det = c->cfg.n_det;
   a.dt = c->dt;
   const int bpc = c->bpc > 0 ? std::min(c->bpc, c->occ[c->bpl]) : c->occ[c->bpl];
@@ -509,6 +545,7 @@ static JacArgs jac_args(const pes_ctx* c, int64_t B, int tile) {
   A.N = c->N;
   A.B = (int)B;
   A.n_modes = c->cfg.n_modes;
+  A.plan = c->plan;
   A.n_det = c->cfg.n_det;
   A.tile = tile;
   A.f0 = c->cfg.f0;

@@ -54,7 +54,7 @@ __device__ __forceinline__ void jac_det(const double* __restrict__ bins, const d
   const int lane = threadIdx.x;
 #pragma unroll 1
   for (int kp = 0; kp < kNParams; ++kp) {
-    const ChanT<Dual<1>> c = eval_channels_t<GEO, LS, 1, Dual<1>>(TanTab{wt, wtn, kp}, det, A.n_modes,
+    const ChanT<Dual<1>> c = eval_channels_t<GEO, LS, 1, Dual<1>>(TanTab{wt, wtn, kp}, det, A.plan,
                                                               P.inv_year, P.inv_ptq, br, a, zr, zi);
     const double cv[6] = {c.ar.v, c.ai.v, c.er.v, c.ei.v, c.tr.v, c.ti.v};
     const double cd[6] = {c.ar.d[0], c.ai.d[0], c.er.d[0], c.ei.d[0], c.tr.d[0], c.ti.d[0]};
@@ -172,7 +172,7 @@ __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const d
   D[4] = in ? tb[T_DTR * N + kk] : 0.0;
   D[5] = in ? tb[T_DTI * N + kk] : 0.0;
   const DetParams& P = A.dt.p[det];
-  const Chan c = eval_channels<GEO, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br, a, zr, zi);
+  const Chan c = eval_channels<GEO, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi);
   dh = fma(D[0], c.ar, dh);
   dh = fma(D[1], c.ai, dh);
   dh = fma(D[2], c.er, dh);

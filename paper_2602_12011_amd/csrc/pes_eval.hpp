@@ -5,6 +5,7 @@
 // E'' = X - 2Y + Z, T'' = X + Y + Z (Sec. 2.1).  The per-bin common factor G
 // and the channel normalizations are folded into the bin tables.
 #pragma once
+#include <type_traits>
 #include "pes_dual.hpp"
 #include "pes_layout.hpp"
 #include "pes_math.hpp"
@@ -117,7 +118,7 @@ struct ChanT {
 // detector block.  S = double (values) or Dual<1> (value and one tangent).
 // GEO selects the geocentric orbit.  a = pi f L, (zr, zi) = e^{-2 pi i f L}.
 template <bool GEO, bool LONG_SINC, int CLS, class S, class Tab>
-__device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n_modes,
+__device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const ModePlan& plan,
                                                     double inv_year, double inv_ptq, const BinRegs& b,
                                                     double a, double zr, double zi) {
   S yFr0 = 0.0, yFi0 = 0.0, yBr0 = 0.0, yBi0 = 0.0;
@@ -129,7 +130,10 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
   const double pi_f = kPi * b.f;
   const int D0 = W_DET0 + det * W_DET_STRIDE;
 
-  for (int j = 0; j < n_modes; ++j) {
+  // One evaluation unit: mode j and, when PAIR, the mode jm with the same m
+  // added as a complex amplitude on j's phase factor.
+  auto unit = [&](int j, int jm, auto pair) __attribute__((always_inline)) {
+    constexpr bool PAIR = decltype(pair)::value;
     // Walker constants (wavefront-uniform, in scalar registers) enter as
     // multiplicands or plain addends, never as the addend of a fused
     // multiply-add, so no vector copy of a scalar operand is needed.
@@ -137,7 +141,7 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
 #define wm(i) T(M0 + (i))
 #define wd(i) T(D0 + (i))
     const S x = b.f * wm(M_FCI);
-    if (!(val(x) < 1.0)) continue;  // beyond this mode's cutoff (diverges only in the cutoff tile)
+    if (!(val(x) < 1.0)) return;  // beyond this mode's cutoff (diverges only in the cutoff tile)
     const S v = wm(M_CM) * b.f13;
     const S w = wm(M_CMI) * b.fm13;
     const S lnv = b.lnf * (1.0 / 3.0) + wm(M_LNCM);
@@ -163,15 +167,28 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
     tau = fma(wm(M_T2), w6, tau);
     tau = fma(wm(M_T0), w8, tau);
     // amplitude with the C^2 cutoff taper (evaluated only where x > 0.9)
+    S scale = b.fm76;
+    if (val(x) > 0.9) {
+      const S t = (x - 0.9) * 10.0;
+      scale *= fma(-(t * t * t), fma(t, fma(6.0, t, -15.0), 10.0), 1.0);
+    }
     S amp = wm(M_AM1) * v;
     amp = fma(wm(M_AM2), v2, amp) + wm(M_AM0);
-    amp *= b.fm76;
-    if (val(x) > 0.9) {
-      const S u = (x - 0.9) * 10.0;
-      amp *= fma(-(u * u * u), fma(u, fma(6.0, u, -15.0), 10.0), 1.0);
+    amp *= scale;
+    S aP = amp * wm(M_KP);
+    S aC2 = amp * wm(M_KC);   // the table holds 2 K_x
+    // the paired mode: its amplitude on the rotated polarization factors
+    S aPi = 0.0, aCi = 0.0;
+    if (PAIR) {
+      const int N0 = W_MODE0 + jm * W_MODE_STRIDE, R0 = W_ROT0 + R_STRIDE * jm;
+      S am = T(N0 + M_AM1) * v;
+      am = fma(T(N0 + M_AM2), v2, am) + T(N0 + M_AM0);
+      am *= scale;
+      aP = fma(am, T(R0 + R_KPR), aP);
+      aPi = am * T(R0 + R_KPI);
+      aC2 = fma(am, T(R0 + R_KCR), aC2);
+      aCi = am * T(R0 + R_KCI);
     }
-    const S aP = amp * wm(M_KP);
-    const S aC2 = amp * wm(M_KC);   // the table holds 2 K_x
     // spacecraft geometry at t_f
     S sa, ca;
     sincos_cycles(tau * inv_year + wd(D_AO), sa, ca);
@@ -194,8 +211,18 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
     S sp, cp;
     sincos_cycles(fma(b.f, kR, phase), sp, cp);
     // polarization amplitudes times E = (cp, -sp): aP E and 2 aC E
-    const S pEr = aP * cp, pEi = -(aP * sp);
-    const S cEr = aC2 * cp, cEi = -(aC2 * sp);
+    S pEr, pEi, cEr, cEi;
+    if (PAIR) {
+      pEr = fma(aP, cp, aPi * sp);
+      pEi = fma(aPi, cp, -(aP * sp));
+      cEr = fma(aC2, cp, aCi * sp);
+      cEi = fma(aCi, cp, -(aC2 * sp));
+    } else {
+      pEr = aP * cp;
+      pEi = -(aP * sp);
+      cEr = aC2 * cp;
+      cEi = -(aC2 * sp);
+    }
     // per-arm phase e^{+i pi f k.Delta_t} of the spacecraft opposite arm t
     S s0, c0, s1, c1;
     if (LONG_SINC && CLS == 1) {
@@ -226,7 +253,9 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
 #undef PES_ARM
 #undef wm
 #undef wd
-  }
+  };
+  for (int u = 0; u < plan.n_pairs; ++u) unit(plan.lead[u], plan.member[u], std::true_type{});
+  for (int u = plan.n_pairs; u < plan.n_units; ++u) unit(plan.lead[u], -1, std::false_type{});
   // links: arm 0 carries y32 (F) / y23 (B), arm 1 y13 / y31, arm 2 y21 / y12.
   // X = y13 - y12 + z (y31 - y21), Y = y21 - y23 + z (y12 - y32),
   // Z = y32 - y31 + z (y23 - y13)   (the common factor G is in the tables)
@@ -250,21 +279,22 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, int n
 }
 
 template <bool GEO, bool LONG_SINC, int CLS = 1>
-__device__ __forceinline__ Chan eval_channels(const double* __restrict__ wt, int det, int n_modes,
+__device__ __forceinline__ Chan eval_channels(const double* __restrict__ wt, int det, const ModePlan& plan,
                                               double inv_year, double inv_ptq, const BinRegs& b,
                                               double a, double zr, double zi) {
-  const ChanT<double> c = eval_channels_t<GEO, LONG_SINC, CLS, double>(ValTab{wt}, det, n_modes, inv_year,
+  const ChanT<double> c = eval_channels_t<GEO, LONG_SINC, CLS, double>(ValTab{wt}, det, plan, inv_year,
                                                                   inv_ptq, b, a, zr, zi);
   return Chan{c.ar, c.ai, c.er, c.ei, c.tr, c.ti};
 }
 
 // eval_channels with the fit class chosen at run time (a wave-uniform branch).
 template <bool GEO, bool LONG_SINC>
-__device__ __forceinline__ Chan eval_channels_cls(int cls, const double* __restrict__ wt, int det, int n_modes,
+__device__ __forceinline__ Chan eval_channels_cls(int cls, const double* __restrict__ wt, int det,
+                                                  const ModePlan& plan,
                                                   double inv_year, double inv_ptq, const BinRegs& b, double a,
                                                   double zr, double zi) {
-  if (cls == 0) return eval_channels<GEO, LONG_SINC, 0>(wt, det, n_modes, inv_year, inv_ptq, b, a, zr, zi);
-  return eval_channels<GEO, LONG_SINC, 1>(wt, det, n_modes, inv_year, inv_ptq, b, a, zr, zi);
+  if (cls == 0) return eval_channels<GEO, LONG_SINC, 0>(wt, det, plan, inv_year, inv_ptq, b, a, zr, zi);
+  return eval_channels<GEO, LONG_SINC, 1>(wt, det, plan, inv_year, inv_ptq, b, a, zr, zi);
 }
 
 }  // namespace pes

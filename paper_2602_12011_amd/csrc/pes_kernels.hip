@@ -197,6 +197,13 @@ struct TanOut {
   }
 };
 
+// arg of the harmonic factor of mode (l, m) in quarter turns (pi/2 each).
+__host__ __device__ inline int argu_quarters(int l, int m) {
+  if ((l == 2 && m == 1) || (l == 3 && m == 3)) return -1;
+  if ((l == 3 && m == 2) || (l == 4 && m == 4)) return 2;
+  return 0;
+}
+
 // Writes the W_STRIDE entries of a physical theta's table through `put`;
 // returns the highest mode cutoff [Hz].
 template <class T, class Out>
@@ -238,11 +245,7 @@ __device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put)
     // phase in cycles: (m/2) * 3/(128 eta) * sum_k psi_k v^{k-5} / (2 pi)
     const T pref = (0.5 * mm * 3.0 / 128.0 / kTwoPi) / eta;
     // constant phase: -(m/2) phi_c - pi/4 - arg(unit_lm), in cycles
-    double argu = 0.0;
-    if (l == 2 && m == 1) argu = -0.5 * kPi;
-    if (l == 3 && m == 3) argu = -0.5 * kPi;
-    if (l == 3 && m == 2) argu = kPi;
-    if (l == 4 && m == 4) argu = kPi;
+    const double argu = 0.5 * kPi * (double)argu_quarters(l, m);
     put(M0 + M_C0, pref * p5 + (-0.5 * mm / kTwoPi) * phic + (-0.25 * kPi - argu) / kTwoPi);
     put(M0 + M_A0, pref * p0);
     put(M0 + M_A2, pref * p2);
@@ -277,8 +280,21 @@ __device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put)
     T yp, ym;
     ylm_pair(l, m, iota, yp, ym);
     const double sgn = (l & 1) ? -1.0 : 1.0;
-    put(M0 + M_KP, 0.5 * (ym + sgn * yp));
-    put(M0 + M_KC, ym - sgn * yp);   // 2 K_x
+    const T kp = 0.5 * (ym + sgn * yp), kc = ym - sgn * yp;   // K_+, 2 K_x
+    put(M0 + M_KP, kp);
+    put(M0 + M_KC, kc);
+    // the same factors on the phase of the first mode with this m:
+    // rot = e^{i (arg_j - arg_lead)} = i^q exactly
+    int lead = j;
+    for (int i = j - 1; i >= 0; --i)
+      if (sa.modes[i].m == m) lead = i;
+    const int q = (((argu_quarters(l, m) - argu_quarters(sa.modes[lead].l, m)) % 4) + 4) % 4;
+    const double rr = q == 0 ? 1.0 : (q == 2 ? -1.0 : 0.0), ri = q == 1 ? 1.0 : (q == 3 ? -1.0 : 0.0);
+    const int R0 = W_ROT0 + R_STRIDE * j;
+    put(R0 + R_KPR, kp * rr);
+    put(R0 + R_KPI, kp * ri);
+    put(R0 + R_KCR, kc * rr);
+    put(R0 + R_KCI, kc * ri);
     const T fcut = (0.5 * mm * kMfIsco) / M;
     put(M0 + M_FCI, 1.0 / fcut);
     fmx = fmx > val(fcut) ? fmx : val(fcut);
@@ -580,8 +596,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 #pragma unroll
         for (int q = 0; q < BPL; ++q) {
           const Chan c = (P.kind == 2)
-                             ? eval_channels_cls<true, LS>(cls[q], wt, det, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
-                             : eval_channels_cls<false, LS>(cls[q], wt, det, A.n_modes, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
+                             ? eval_channels_cls<true, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
+                             : eval_channels_cls<false, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
           dh = fma(dar[q], c.ar, dh);
           dh = fma(dai[q], c.ai, dh);
           dh = fma(der[q], c.er, dh);
@@ -684,9 +700,9 @@ __global__ void response_kernel(ResponseArgs A) {
     const DetParams& P = A.dt.p[det];
     Chan c = {0, 0, 0, 0, 0, 0};
     if (valid) {
-      c = (P.kind == 2) ? eval_channels<true, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+      c = (P.kind == 2) ? eval_channels<true, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
                                               tb[T_ZR * N + k], tb[T_ZI * N + k])
-                        : eval_channels<false, LS>(wt, det, A.n_modes, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+                        : eval_channels<false, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
                                                tb[T_ZR * N + k], tb[T_ZI * N + k]);
     }
     const double Gr = tb[T_GR * N + k], Gi = tb[T_GI * N + k];

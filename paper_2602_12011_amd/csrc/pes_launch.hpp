@@ -34,6 +34,7 @@ struct LoglikeArgs {
   double* partial;
   int64_t N;
   int B, wg, n_groups, ntmax, n_modes, n_det;
+  ModePlan plan;
   int grid_mode;   // 1: block i takes work item i (plain grid); 0: atomic ticket
   DetTable dt;
 };
@@ -45,12 +46,14 @@ struct ResponseArgs {
   double* out;
   int64_t N;
   int n_modes, n_det;
+  ModePlan plan;
   DetTable dt;
 };
 
 struct JacArgs {
   int64_t N;
   int B, n_modes, n_det;
+  ModePlan plan;
   int tile;           // bins per block (a multiple of 64)
   double f0, df;
   DetTable dt;

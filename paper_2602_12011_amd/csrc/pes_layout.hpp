@@ -20,7 +20,26 @@ enum : int {
   W_MODE_STRIDE = 26,
   W_DET0 = W_MODE0 + kMaxModes * W_MODE_STRIDE,  // 134
   W_DET_STRIDE = 44,
-  W_STRIDE = 272  // >= W_DET0 + kMaxDet * W_DET_STRIDE (266), multiple of 8
+  W_ROT0 = W_DET0 + kMaxDet * W_DET_STRIDE,      // 266
+  W_STRIDE = 288  // >= W_ROT0 + kMaxModes * 4 (286), multiple of 8
+};
+
+// Modes that share m share v, t_f, the orbit, the projections, the arm phases
+// and the sinc values; their phases differ by the constant C0_j - C0_lead, a
+// whole number of quarter cycles (the constant phase of each mode is
+// -(m/2) phi_c - pi/4 - arg of its harmonic factor, a multiple of pi/2).  For
+// mode j, with rot_j = e^{-2 pi i (C0_j - C0_lead)} exactly in {1, i, -1, -i}
+// and lead the first mode of the context with the same m:
+//   W_ROT0 + 4 j + (0, 1, 2, 3) = (KP Re rot, KP Im rot, KC Re rot, KC Im rot).
+enum : int { R_KPR = 0, R_KPI, R_KCR, R_KCI, R_STRIDE };
+
+// Evaluation units of a context.  The first n_pairs units pair a mode (lead)
+// with the next mode of the same m (member), added as a complex amplitude on
+// the lead's phase factor; the remaining units hold one mode each.
+struct ModePlan {
+  int n_units, n_pairs;
+  int lead[kMaxModes];
+  int member[kMaxModes];
 };
 
 // Per mode: v = CM f^{1/3}, 1/v = CMI f^{-1/3}, ln v = LNCM + ln(f)/3.
