@@ -40,3 +40,4 @@ def test_ks_distance_matches_scipy():
     rng = np.random.default_rng(5)
     a, b = rng.normal(size=700), rng.normal(0.1, 1.2, size=900)
     assert abs(D.ks_distance(a, b) - stats.ks_2samp(a, b).statistic) < 1e-12
+
