@@ -50,7 +50,8 @@ using DepTc = Deps<10>;
 // Compact tangent layout: per table entry only the derivatives with respect
 // to the parameters in its mask (bit k: theta_k), in increasing k; entries
 // ordered t_c, then modes 0..4 (26 fields each), then detectors 0..2 (44
-// fields each).  The masks are the parameter lists the reverse sweep uses.
+// fields each), then the rotated polarization factors of modes 0..4 (4 each,
+// iota only).  The masks are the parameter lists the reverse sweep uses.
 constexpr unsigned kBitM = 1u << 0, kBitQ = 1u << 1, kBitChi = (1u << 2) | (1u << 3), kBitD = 1u << 4,
                    kBitIota = 1u << 5, kBitPhi = 1u << 6, kBitSky = (1u << 7) | (1u << 8), kBitPsi = 1u << 9,
                    kBitTc = 1u << 10;
@@ -84,7 +85,8 @@ constexpr int kModeSlots = kTanLayout.mode[W_MODE_STRIDE];   // 49
 constexpr int kDetSlots = kTanLayout.det[W_DET_STRIDE];      // 106
 constexpr int kTanMode0 = 1;
 constexpr int kTanDet0 = kTanMode0 + kMaxModes * kModeSlots;
-constexpr int kTanSlots = kTanDet0 + kMaxDet * kDetSlots;
+constexpr int kTanRot0 = kTanDet0 + kMaxDet * kDetSlots;
+constexpr int kTanSlots = kTanRot0 + kMaxModes * R_STRIDE;
 static_assert(kModeSlots == 49 && kDetSlots == 106, "compact tangent layout");
 template <int F> struct ModeOff { static constexpr int value = kTanLayout.mode[F]; };
 template <int F> struct DetOff { static constexpr int value = kTanLayout.det[F]; };
@@ -93,7 +95,7 @@ template <int F> struct DetOff { static constexpr int value = kTanLayout.det[F];
 // layout, entries split over the n threads of a block.
 __device__ inline void compact_tangents(const double* __restrict__ full, double* __restrict__ out, int tid,
                                         int n) {
-  for (int e = tid; e < 1 + kMaxModes * W_MODE_STRIDE + kMaxDet * W_DET_STRIDE; e += n) {
+  for (int e = tid; e < 1 + kMaxModes * W_MODE_STRIDE + kMaxDet * W_DET_STRIDE + kMaxModes * R_STRIDE; e += n) {
     int entry, slot;
     unsigned mask;
     if (e == 0) {
@@ -106,6 +108,11 @@ __device__ inline void compact_tangents(const double* __restrict__ full, double*
       mask = mode_mask(f);
       slot = kTanMode0 + j * kModeSlots;
       for (int q = 0; q < f; ++q) slot += __builtin_popcount(mode_mask(q));
+    } else if (e >= 1 + kMaxModes * W_MODE_STRIDE + kMaxDet * W_DET_STRIDE) {
+      const int r = e - 1 - kMaxModes * W_MODE_STRIDE - kMaxDet * W_DET_STRIDE;
+      entry = W_ROT0 + r;
+      mask = kBitIota;
+      slot = kTanRot0 + r;
     } else {
       const int r = e - 1 - kMaxModes * W_MODE_STRIDE;
       const int d = r / W_DET_STRIDE, f = r % W_DET_STRIDE;
@@ -185,18 +192,25 @@ __device__ __forceinline__ void adj_arm(const double* yb, double a, double pEr, 
   nqb = fma(-2.0 * nq, ppb, np * pcb);
 }
 
-// Adjoint of mode j's unit of (walker, bin, detector) given the link adjoints
-// yb (12 values: arm-major Fr, Fi, Br, Bi); accumulates d l / d theta into g.  wt: the walker's table; tn: its
-// tangents in the compact layout; ftc = f t_c mod 1.
-template <bool GEO, bool LS>
+// Adjoint of the unit of mode j (and, when PAIR, of mode jm riding on it, as
+// in eval_channels_t) of (walker, bin, detector) given the link adjoints yb
+// (12 values: arm-major Fr, Fi, Br, Bi); accumulates d l / d theta into g.
+// wt: the walker's table; tn: its tangents in the compact layout; ftc = f t_c
+// mod 1.
+template <bool GEO, bool LS, bool PAIR>
 __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const double* __restrict__ tn, int det,
-                                         int j, double inv_year, double inv_ptq, const BinRegs& b, double a,
-                                         double ftc, const double* yb, double* g) {
+                                         int j, int jm, double inv_year, double inv_ptq, const BinRegs& b,
+                                         double a, double ftc, const double* yb, double* g) {
   const int M0 = W_MODE0 + j * W_MODE_STRIDE;
   const int D0 = W_DET0 + det * W_DET_STRIDE;
+  const int N0 = W_MODE0 + jm * W_MODE_STRIDE, R0 = W_ROT0 + R_STRIDE * jm;
 #define wm(i) wt[M0 + (i)]
 #define wd(i) wt[D0 + (i)]
+#define wn(i) wt[N0 + (i)]
+#define wr(i) wt[R0 + (i)]
 #define tm(i) (tn + kTanMode0 + j * kModeSlots + ModeOff<(i)>::value)
+#define tnm(i) (tn + kTanMode0 + jm * kModeSlots + ModeOff<(i)>::value)
+#define tr(i) (tn + kTanRot0 + R_STRIDE * jm + (i))
 #define td(i) (tn + kTanDet0 + det * kDetSlots + DetOff<(i)>::value)
   const double x = b.f * wm(M_FCI);
   if (!(x < 1.0)) return;
@@ -204,7 +218,7 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   // waveform's intermediate powers are not kept through the geometry part:
   // they are recomputed for the waveform reverse below, which keeps the live
   // register set of this function small.
-  double phase, tau, amp0;
+  double phase, tau, amp0, amn0 = 0.0;
   {
     const double v = wm(M_CM) * b.f13;
     const double w = wm(M_CMI) * b.fm13;
@@ -229,6 +243,7 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
     tau = fma(wm(M_T2), w6, tau);
     tau = fma(wm(M_T0), w8, tau);
     amp0 = (fma(wm(M_AM2), v2, wm(M_AM1) * v) + wm(M_AM0)) * b.fm76;
+    if (PAIR) amn0 = (fma(wn(M_AM2), v2, wn(M_AM1) * v) + wn(M_AM0)) * b.fm76;
   }
   double tap = 1.0, dtap = 0.0;   // taper and its derivative in x
   if (x > 0.9) {
@@ -238,7 +253,15 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
     dtap = -300.0 * (u * u) * (um * um);
   }
   const double amp = amp0 * tap;
-  const double aP = amp * wm(M_KP), aC2 = amp * wm(M_KC);   // the table holds 2 K_x
+  double aP = amp * wm(M_KP), aC2 = amp * wm(M_KC);   // the table holds 2 K_x
+  double aPi = 0.0, aCi = 0.0, amn = 0.0;
+  if (PAIR) {
+    amn = amn0 * tap;
+    aP = fma(amn, wr(R_KPR), aP);
+    aPi = amn * wr(R_KPI);
+    aC2 = fma(amn, wr(R_KCR), aC2);
+    aCi = amn * wr(R_KCI);
+  }
   double sa, ca, ua, ub;
   sincos_cycles(tau * inv_year + wd(D_AO), sa, ca);
   if (GEO) {
@@ -257,8 +280,18 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   const double kR = fma(wd(D_KR), ca, wd(D_KR + 1) * sa);
   double sp, cp;
   sincos_cycles(fma(b.f, kR, phase), sp, cp);
-  const double pEr = aP * cp, pEi = -(aP * sp);
-  const double cEr = aC2 * cp, cEi = -(aC2 * sp);
+  double pEr, pEi, cEr, cEi;
+  if (PAIR) {
+    pEr = fma(aP, cp, aPi * sp);
+    pEi = fma(aPi, cp, -(aP * sp));
+    cEr = fma(aC2, cp, aCi * sp);
+    cEi = fma(aCi, cp, -(aC2 * sp));
+  } else {
+    pEr = aP * cp;
+    pEi = -(aP * sp);
+    cEr = aC2 * cp;
+    cEi = -(aC2 * sp);
+  }
   double s0, c0, s1, c1;
   const double pi_f = kPi * b.f;
   if (LS) {
@@ -276,11 +309,18 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   adj_arm<LS>(yb, a, pEr, pEi, cEr, cEi, c0, s0, np0, nq0, kn0, pEbr, pEbi, cEbr, cEbi, cb0, sb0, knb0, npb0, nqb0);
   adj_arm<LS>(yb + 4, a, pEr, pEi, cEr, cEi, c1, s1, np1, nq1, kn1, pEbr, pEbi, cEbr, cEbi, cb1, sb1, knb1, npb1, nqb1);
   adj_arm<LS>(yb + 8, a, pEr, pEi, cEr, cEi, c2, s2, np2, nq2, kn2, pEbr, pEbi, cEbr, cEbi, cb2, sb2, knb2, npb2, nqb2);
-  // aP E, 2 aC E with E = (cp, -sp)
+  // (aP + i aPi) E, (2 aC + i aCi) E with E = (cp, -sp)
   const double aPb = fma(pEbr, cp, -(pEbi * sp));
   const double aCb = fma(cEbr, cp, -(cEbi * sp));
-  const double cpb = fma(pEbr, aP, cEbr * aC2);
-  const double spb = -fma(pEbi, aP, cEbi * aC2);
+  double cpb = fma(pEbr, aP, cEbr * aC2);
+  double spb = -fma(pEbi, aP, cEbi * aC2);
+  double aPib = 0.0, aCib = 0.0;
+  if (PAIR) {
+    aPib = fma(pEbr, sp, pEbi * cp);
+    aCib = fma(cEbr, sp, cEbi * cp);
+    cpb = fma(pEbi, aPi, fma(cEbi, aCi, cpb));
+    spb = fma(pEbr, aPi, fma(cEbr, aCi, spb));
+  }
   // the third arm follows from the other two
   knb0 -= knb2;
   knb1 -= knb2;
@@ -340,9 +380,20 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   DepIota::add(g, aPb * amp, tm(M_KP));
   DepIota::add(g, aCb * amp, tm(M_KC));
   const double ampb = fma(aPb, wm(M_KP), aCb * wm(M_KC));   // aCb: adjoint of 2 aC
-  const double xb = ampb * amp0 * dtap;
+  double xb = ampb * amp0 * dtap;
   const double qa = ampb * tap * b.fm76;
   DepMQD::add(g, qa, tm(M_AM0));
+  double qn = 0.0;
+  if (PAIR) {
+    DepIota::add(g, aPb * amn, tr(R_KPR));
+    DepIota::add(g, aPib * amn, tr(R_KPI));
+    DepIota::add(g, aCb * amn, tr(R_KCR));
+    DepIota::add(g, aCib * amn, tr(R_KCI));
+    const double amnb = fma(aPb, wr(R_KPR), fma(aPib, wr(R_KPI), fma(aCb, wr(R_KCR), aCib * wr(R_KCI))));
+    xb = fma(amnb * amn0, dtap, xb);
+    qn = amnb * tap * b.fm76;
+    DepMQD::add(g, qn, tnm(M_AM0));
+  }
   DepM::add(g, xb * b.f, tm(M_FCI));
   // recompute the waveform powers (from opaque copies of the bin values, so
   // the forward ones are not kept alive)
@@ -354,6 +405,11 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   DepMQD::add(g, qa * v, tm(M_AM1));
   DepMQD::add(g, qa * v2, tm(M_AM2));
   double vb = qa * fma(2.0 * wm(M_AM2), v, wm(M_AM1));
+  if (PAIR) {
+    DepMQD::add(g, qn * v, tnm(M_AM1));
+    DepMQD::add(g, qn * v2, tnm(M_AM2));
+    vb = fma(qn, fma(2.0 * wn(M_AM2), v, wn(M_AM1)), vb);
+  }
   // ---- t_f - t_c
   DepMQ::add(g, taub * w, tm(M_T7));
   DepMQ::add(g, taub * w2, tm(M_T6));
@@ -395,7 +451,11 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   DepM::add(g, lnvb, tm(M_LNCM));
 #undef wm
 #undef wd
+#undef wn
+#undef wr
 #undef tm
+#undef tnm
+#undef tr
 #undef td
 }
 

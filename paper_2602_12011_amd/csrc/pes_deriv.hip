@@ -190,8 +190,11 @@ __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const d
   }
   const double ftc = frac_prod(br.f, wt[W_TC]);
 #pragma unroll 1
-  for (int j = 0; j < A.n_modes; ++j)
-    adj_unit<GEO, LS>(wt, wtn, det, j, P.inv_year, P.inv_ptq, br, a, ftc, ybs, g);
+  for (int u = 0; u < A.plan.n_pairs; ++u)
+    adj_unit<GEO, LS, true>(wt, wtn, det, A.plan.lead[u], A.plan.member[u], P.inv_year, P.inv_ptq, br, a, ftc, ybs, g);
+#pragma unroll 1
+  for (int u = A.plan.n_pairs; u < A.plan.n_units; ++u)
+    adj_unit<GEO, LS, false>(wt, wtn, det, A.plan.lead[u], 0, P.inv_year, P.inv_ptq, br, a, ftc, ybs, g);
 }
 
 // The walker's tangents are staged in LDS in the compact layout (4.5 KiB):
