@@ -527,7 +527,9 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
   a.n_det = c->cfg.n_det;
   a.dt = c->dt;
   const int bpc = c->bpc > 0 ? std::min(c->bpc, c->occ[c->bpl]) : c->occ[c->bpl];
-  const int grid = grid_mode ? (int)(n_groups * c->ntmax) : c->n_cu * bpc;
+  // persistent grid: the resident blocks, but never more than the items can be
+  const int grid = grid_mode ? (int)(n_groups * c->ntmax)
+                             : (int)std::min<int64_t>((int64_t)c->n_cu * bpc, n_groups * c->ntmax);
   a.grid_mode = grid_mode ? 1 : 0;
   const bool rec = c->timing && c->n_ev < kMaxEv;
   if (rec) PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev], s));

@@ -207,8 +207,19 @@ __host__ __device__ inline int argu_quarters(int l, int m) {
 // Writes the W_STRIDE entries of a physical theta's table through `put`;
 // returns the highest mode cutoff [Hz].
 template <class T, class Out>
-__device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put) {
-  for (int i = 0; i < W_STRIDE; ++i) put(i, T(0.0));
+__device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put, int part = -1) {
+  // part < 0: the whole table.  Otherwise one share of it, so that several
+  // threads build one walker's table together: part 0 the header and the
+  // unused blocks, part 1 + j mode j, part 1 + n_modes + d detector d.
+  const bool all = part < 0;
+  if (all) {
+    for (int i = 0; i < W_STRIDE; ++i) put(i, T(0.0));
+  } else if (part == 0) {
+    for (int i = 0; i < W_MODE0; ++i) put(i, T(0.0));
+    for (int i = W_MODE0 + sa.n_modes * W_MODE_STRIDE; i < W_DET0; ++i) put(i, T(0.0));
+    for (int i = W_DET0 + sa.n_det * W_DET_STRIDE; i < W_ROT0; ++i) put(i, T(0.0));
+    for (int i = W_ROT0 + sa.n_modes * R_STRIDE; i < W_STRIDE; ++i) put(i, T(0.0));
+  }
   const T M = th[0] * kMsunS;
   const T q = th[1];
   const T eta = q / ((1.0 + q) * (1.0 + q));
@@ -231,13 +242,18 @@ __device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put)
                76055.0 / 1728.0 * (eta * eta) - 127825.0 / 1296.0 * (eta * eta * eta);
   const double p6l = -6848.0 / 21.0;
   const T p7 = kPi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * (eta * eta));
-  put(W_VALID, T(1.0));
-  put(W_TC, tc);
+  if (all || part == 0) {
+    put(W_VALID, T(1.0));
+    put(W_TC, tc);
+  }
   double fmx = 0.0;
   for (int j = 0; j < sa.n_modes; ++j) {
     const int l = sa.modes[j].l, m = sa.modes[j].m;
     const int M0 = W_MODE0 + j * W_MODE_STRIDE;
     const double mm = (double)m;
+    const T fcut = (0.5 * mm * kMfIsco) / M;
+    fmx = fmx > val(fcut) ? fmx : val(fcut);
+    if (!(all || part == 1 + j)) continue;
     const T cm = cbrt(M * (kTwoPi / mm));
     put(M0 + M_CM, cm);
     put(M0 + M_CMI, 1.0 / cm);
@@ -295,11 +311,10 @@ __device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put)
     put(R0 + R_KPI, kp * ri);
     put(R0 + R_KCR, kc * rr);
     put(R0 + R_KCI, kc * ri);
-    const T fcut = (0.5 * mm * kMfIsco) / M;
     put(M0 + M_FCI, 1.0 / fcut);
-    fmx = fmx > val(fcut) ? fmx : val(fcut);
   }
-  put(W_FMAX, T(fmx));
+  if (all || part == 0) put(W_FMAX, T(fmx));
+  if (!(all || part > sa.n_modes)) return fmx;
   // sky basis: source direction (lam, beta), k = -nhat, axes p, q rotated by psi
   const T cl = cos(lam), sl = sin(lam), cb = cos(beta), sb = sin(beta);
   const T cps = cos(psi), sps = sin(psi);
@@ -312,6 +327,7 @@ __device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put)
     qv[i] = sps * (-1.0 * uu[i]) + cps * vv[i];
   }
   for (int d = 0; d < sa.n_det; ++d) {
+    if (!(all || part == 1 + sa.n_modes + d)) continue;
     const DetParams& P = sa.dt.p[d];
     const int D0 = W_DET0 + d * W_DET_STRIDE;
     put(D0 + D_AO, tc * P.inv_year + P.phase0_cyc);
@@ -348,19 +364,25 @@ __device__ int active_tiles(double fmx, const SetupArgs& sa, int tile) {
   return (int)((nact + tile - 1) / tile);
 }
 
+// One thread per (walker, share of its table), 1 + n_modes + n_det shares:
+// blockIdx.y is the share, so a wavefront runs one share for 64 walkers and
+// the shares of one walker run side by side in different wavefronts.
 __global__ void setup_kernel(const double* __restrict__ theta, int64_t B, double* __restrict__ wtab,
                              int* __restrict__ ntiles, SetupArgs sa) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
+  const int part = blockIdx.y;
   const double* th = theta + 11 * b;
   double* w = wtab + b * W_STRIDE;
   if (!theta_valid(th)) {
-    for (int i = 0; i < W_STRIDE; ++i) w[i] = 0.0;
-    ntiles[b] = 0;
+    if (part == 0) {
+      for (int i = 0; i < W_STRIDE; ++i) w[i] = 0.0;
+      ntiles[b] = 0;
+    }
     return;
   }
-  const double fmx = setup_walker<double>(th, sa, ValOut{w});
-  ntiles[b] = active_tiles(fmx, sa, sa.tile);
+  const double fmx = setup_walker<double>(th, sa, ValOut{w}, part);
+  if (part == 0) ntiles[b] = active_tiles(fmx, sa, sa.tile);
 }
 
 // Values and theta-derivatives of the walker table, wtan[b][i][k] = d w_i / d theta_k:
@@ -745,8 +767,8 @@ hipError_t launch_setup_tan(const double* theta, int64_t B, double* wtab, double
 hipError_t launch_setup(const double* theta, int64_t B, double* wtab, int* ntiles, const SetupArgs& sa,
                         hipStream_t s) {
   const int bs = 64;
-  hipLaunchKernelGGL(setup_kernel, dim3((unsigned)((B + bs - 1) / bs)), dim3(bs), 0, s, theta, B, wtab,
-                     ntiles, sa);
+  hipLaunchKernelGGL(setup_kernel, dim3((unsigned)((B + bs - 1) / bs), 1 + sa.n_modes + sa.n_det), dim3(bs), 0, s,
+                     theta, B, wtab, ntiles, sa);
   return hipGetLastError();
 }
 
