@@ -1,7 +1,8 @@
 // Derivative kernels of libpes (gfx950): the reverse-mode gradient
-// (adj_kernel), the forward-mode gradient and Fisher matrix (jac_kernel, with
-// the J^T J contraction on the FP64 matrix cores) and their per-walker
-// reductions.  Walker tangents come from setup_tan_kernel (pes_kernels.hip).
+// (adj_kernel), the forward-mode gradient (jac_kernel), the Fisher matrix
+// (fisher_kernel: forward-mode tangents with the J^T J contraction on the
+// FP64 matrix cores) and their per-walker reductions.  Walker tangents come
+// from setup_tan_kernel (pes_kernels.hip).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -15,21 +16,20 @@ namespace pes {
 // ---------------------------------------------------------------- derivatives
 // Forward-mode tangents of the channels, one direction per pass: for each
 // 64-bin sub-tile and detector the 11 passes give dC/dtheta_k for the lane's
-// bin.  GRAD accumulates sum (D - W C) . dC/dtheta_k (the gradient of
-// <d|h> - <h|h>/2) together with <d|h> and <h|h>; FISHER stores
-// sqrt(W) dC/dtheta in LDS and accumulates J^T J with FP64 matrix-core
-// operations (16 x 16 x 4 blocks, parameters padded to 16).
+// bin, and the kernel accumulates sum (D - W C) . dC/dtheta_k (the gradient of
+// <d|h> - <h|h>/2) together with <d|h> and <h|h> (PES_GRAD_FORWARD, the
+// cross-check of the reverse sweep).
 __device__ __forceinline__ int64_t active_bins(double fmx, double f0, double df, int64_t N) {
   double nb = ceil((fmx - f0) / df) + 1.0;
   nb = fmin(fmax(nb, 0.0), (double)N);
   return (int64_t)nb;
 }
 
-template <bool LS, bool GEO, bool FISHER>
+template <bool LS, bool GEO>
 __device__ __forceinline__ void jac_det(const double* __restrict__ bins, const double* __restrict__ tb,
                                         const double* __restrict__ wt, const double* __restrict__ wtn,
                                         const JacArgs& A, int det, int64_t k, bool in, double* g,
-                                        double& dh, double& hh, double* J) {
+                                        double& dh, double& hh) {
   const int64_t N = A.N;
   const int64_t kk = in ? k : N - 1;
   BinRegs br;
@@ -51,7 +51,6 @@ __device__ __forceinline__ void jac_det(const double* __restrict__ bins, const d
   D[5] = in ? tb[T_DTI * N + kk] : 0.0;
   const DetParams& P = A.dt.p[det];
   double R[6];
-  const int lane = threadIdx.x;
 #pragma unroll 1
   for (int kp = 0; kp < kNParams; ++kp) {
     const ChanT<Dual<1>> c = eval_channels_t<GEO, LS, 1, Dual<1>>(TanTab{wt, wtn, kp}, det, A.plan,
@@ -66,25 +65,19 @@ __device__ __forceinline__ void jac_det(const double* __restrict__ bins, const d
         R[r] = fma(-W[r], cv[r], D[r]);
       }
     }
-    if (FISHER) {
+    double acc = 0.0;
 #pragma unroll
-      for (int r = 0; r < 6; ++r) J[(6 * lane + r) * kNParams + kp] = sqrt(W[r]) * cd[r];
-    } else {
-      double acc = 0.0;
+    for (int r = 0; r < 6; ++r) acc = fma(R[r], cd[r], acc);
 #pragma unroll
-      for (int r = 0; r < 6; ++r) acc = fma(R[r], cd[r], acc);
-#pragma unroll
-      for (int i = 0; i < kNParams; ++i) g[i] += (i == kp) ? acc : 0.0;   // keeps g in registers
-    }
+    for (int i = 0; i < kNParams; ++i) g[i] += (i == kp) ? acc : 0.0;   // keeps g in registers
   }
 }
 
-template <bool LS, bool FISHER>
+template <bool LS>
 __global__ void __launch_bounds__(64)
     jac_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                const double* __restrict__ wtab, const double* __restrict__ wtan,
                double* __restrict__ partial, JacArgs A) {
-  __shared__ double J[FISHER ? 64 * 6 * kNParams : 1];   // [bin row][parameter], 33 KiB
   const int t = blockIdx.x;
   const int b = blockIdx.y;
   const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
@@ -99,49 +92,95 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
   for (int i = 0; i < kNParams; ++i) g[i] = 0.0;
   double dh = 0.0, hh = 0.0;
-  typedef double v4d __attribute__((ext_vector_type(4)));
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
   for (int64_t s0 = k0; s0 < kend; s0 += 64) {
     const int64_t k = s0 + lane;
     const bool in = k < kend;
     for (int det = 0; det < A.n_det; ++det) {
       const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * A.N;
       if (A.dt.p[det].kind == 2)
-        jac_det<LS, true, FISHER>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, J);
+        jac_det<LS, true>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh);
       else
-        jac_det<LS, false, FISHER>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, J);
-      if (FISHER) {
-        __syncthreads();
-        // acc += Jt^T Jt over the 384 rows of this sub-tile, 4 rows per operation:
-        // operand element (row 4q + lane/16, column lane%16) serves as both A and B.
-        for (int q = 0; q < 96; ++q) {
-          const int col = lane & 15;   // parameters padded to 16 with zeros
-          const double v = col < kNParams ? J[(4 * q + (lane >> 4)) * kNParams + col] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
-        }
-        __syncthreads();
-      }
+        jac_det<LS, false>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh);
     }
   }
   const int64_t slot = (int64_t)t * A.B + b;
-  if (FISHER) {
-    double* p = partial + slot * 256 + lane * 4;
-    p[0] = acc[0];
-    p[1] = acc[1];
-    p[2] = acc[2];
-    p[3] = acc[3];
-  } else {
-    double red[kNParams + 2];
+  double red[kNParams + 2];
 #pragma unroll
-    for (int i = 0; i < kNParams; ++i) red[i] = wave_sum_dpp(g[i]);
-    red[kNParams] = wave_sum_dpp(dh);
-    red[kNParams + 1] = wave_sum_dpp(hh);
-    if (lane == 0) {
-      double* p = partial + slot * (kNParams + 2);
+  for (int i = 0; i < kNParams; ++i) red[i] = wave_sum_dpp(g[i]);
+  red[kNParams] = wave_sum_dpp(dh);
+  red[kNParams + 1] = wave_sum_dpp(hh);
+  if (lane == 0) {
+    double* p = partial + slot * (kNParams + 2);
 #pragma unroll
-      for (int i = 0; i < kNParams + 2; ++i) p[i] = red[i];
+    for (int i = 0; i < kNParams + 2; ++i) p[i] = red[i];
+  }
+}
+
+// Fisher matrix, one (bin, parameter) pair per lane: lane l of a wavefront
+// carries the tangent direction p = l % 16 (p < 11; the other five lanes
+// contribute zeros) of bin l / 16 of its group of four bins, so after one
+// dual-number evaluation every lane holds sqrt(W) dC_r/dtheta_p for its pair,
+// which is at once the A operand (row p, column bin) and the B operand (row
+// bin, column p) of a 16 x 16 x 4 FP64 matrix-core product: six products per
+// group accumulate sum_bins J_r^T J_r with no LDS tile.  The four wavefronts
+// of a block take interleaved groups of the block's bin tile and their
+// accumulators are added in LDS at the end.
+template <bool LS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    fisher_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
+                  const double* __restrict__ wtab, const double* __restrict__ wtan,
+                  double* __restrict__ partial, JacArgs A) {
+  __shared__ double red[4][256];
+  const int t = blockIdx.x;
+  const int b = blockIdx.y;
+  const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
+  const double* __restrict__ wtn = wtan + (int64_t)b * W_STRIDE * kNParams;
+  if (wt[W_VALID] == 0.0) return;
+  const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
+  const int64_t k0 = (int64_t)t * A.tile;
+  if (k0 >= nact) return;
+  const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int p = lane & 15, sub = lane >> 4;
+  const bool pin = p < kNParams;
+  const int64_t N = A.N;
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t s0 = k0 + 4 * wv; s0 < kend; s0 += 16) {
+    const int64_t k = s0 + sub;
+    const bool in = pin && k < kend;
+    const int64_t kk = k < kend ? k : kend - 1;
+    BinRegs br;
+    br.f = bins[B_F * N + kk];
+    br.f13 = bins[B_F13 * N + kk];
+    br.fm13 = bins[B_FM13 * N + kk];
+    br.fm76 = bins[B_FM76 * N + kk];
+    br.lnf = bins[B_LNF * N + kk];
+    for (int det = 0; det < A.n_det; ++det) {
+      const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * N;
+      const double zr = tb[T_ZR * N + kk], zi = tb[T_ZI * N + kk], a = tb[T_A * N + kk];
+      const double sA = in ? sqrt(tb[T_WA * N + kk]) : 0.0;
+      const double sT = in ? sqrt(tb[T_WT * N + kk]) : 0.0;
+      const DetParams& P = A.dt.p[det];
+      const TanTabLane T{wt, wtn, pin ? p : 0};
+      const ChanT<Dual<1>> c = (P.kind == 2)
+                                   ? eval_channels_t<true, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year, P.inv_ptq,
+                                                                          br, a, zr, zi)
+                                   : eval_channels_t<false, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year,
+                                                                           P.inv_ptq, br, a, zr, zi);
+      const double sE = sA * 0.5773502691896258;   // W_E = W_A / 3
+      const double v[6] = {sA * c.ar.d[0], sA * c.ai.d[0], sE * c.er.d[0],
+                           sE * c.ei.d[0], sT * c.tr.d[0], sT * c.ti.d[0]};
+#pragma unroll
+      for (int r = 0; r < 6; ++r) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r], v[r], acc, 0, 0, 0);
     }
   }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) red[wv][4 * lane + e] = acc[e];
+  __syncthreads();
+  const int e = threadIdx.x;
+  const double sum = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+  partial[((int64_t)t * A.B + b) * 256 + e] = sum;
 }
 
 // Reverse-mode gradient: for each (walker, bin, detector) one forward
@@ -307,9 +346,9 @@ hipError_t launch_grad(const double* bins, const double* tabs, const double* wta
     else
       hipLaunchKernelGGL((adj_kernel<false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
   } else if (long_sinc) {
-    hipLaunchKernelGGL((jac_kernel<true, false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+    hipLaunchKernelGGL((jac_kernel<true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
   } else {
-    hipLaunchKernelGGL((jac_kernel<false, false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+    hipLaunchKernelGGL((jac_kernel<false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
   }
   hipLaunchKernelGGL(grad_finalize_kernel, dim3((A.B + 255) / 256), dim3(256), 0, s, partial, wtab, dd, A, logl,
                      grad);
@@ -320,9 +359,9 @@ hipError_t launch_fisher(const double* bins, const double* tabs, const double* w
                          double* partial, const JacArgs& A, bool long_sinc, double* F, hipStream_t s) {
   const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
   if (long_sinc)
-    hipLaunchKernelGGL((jac_kernel<true, true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+    hipLaunchKernelGGL((fisher_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   else
-    hipLaunchKernelGGL((jac_kernel<false, true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+    hipLaunchKernelGGL((fisher_kernel<false>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   hipLaunchKernelGGL(fisher_finalize_kernel, dim3(A.B), dim3(256), 0, s, partial, wtab, A, F);
   return hipGetLastError();
 }

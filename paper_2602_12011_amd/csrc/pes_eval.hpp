@@ -29,6 +29,20 @@ struct TanTab {
   }
 };
 
+// The same with a direction that may differ between lanes (the values stay
+// wavefront-uniform, the tangents are per-lane loads).
+struct TanTabLane {
+  const double* __restrict__ w;
+  const double* __restrict__ t;
+  int k;
+  __device__ __forceinline__ Dual<1> operator()(int i) const {
+    Dual<1> r;
+    r.v = w[i];
+    r.d[0] = t[i * kNParams + k];
+    return r;
+  }
+};
+
 // ---- math on the tangent type (value by the double kernels, derivative by hand)
 __device__ __forceinline__ void sincos_cycles(const Dual<1>& x, Dual<1>& s, Dual<1>& c) {
   sincos_cycles(x.v, s.v, c.v);
