@@ -137,16 +137,16 @@ def measured_traffic(tuning):
         text = open(COUNTER_SUMMARY).read()
     except OSError:
         return None
+    tun = f"{tuning['bins_per_lane']},{tuning['walkers_per_group']},{tuning['blocks_per_cu']}"
     vals = {}
     for line in text.splitlines():
-        if ":" in line and line.split(":")[0].strip() in (
-                "traffic_bytes_per_launch", "kernel_sources_sha256_16", "tuning"):
+        if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    tun = f"{tuning['bins_per_lane']},{tuning['walkers_per_group']},{tuning['blocks_per_cu']}"
-    if vals.get("kernel_sources_sha256_16") != kernel_source_hash() or vals.get("tuning") != tun:
+    if vals.get("kernel_sources_sha256_16") != kernel_source_hash():
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    v = vals.get(f"traffic_bytes_per_launch[{tun}]")
+    return float(v) if v is not None else None
 
 
 def _cpu_model():
