@@ -122,15 +122,18 @@ __global__ void __launch_bounds__(64)
 // dual-number evaluation every lane holds sqrt(W) dC_r/dtheta_p for its pair,
 // which is at once the A operand (row p, column bin) and the B operand (row
 // bin, column p) of a 16 x 16 x 4 FP64 matrix-core product: six products per
-// group accumulate sum_bins J_r^T J_r with no LDS tile.  The four wavefronts
-// of a block take interleaved groups of the block's bin tile and their
-// accumulators are added in LDS at the end.
+// group accumulate sum_bins J_r^T J_r with no Jacobian tile.  The walker's
+// tangent table is staged in LDS once per block (the lanes read different
+// directions of the same entry); the four wavefronts of a block take
+// interleaved groups of the block's bin tile and their accumulators are added
+// in LDS at the end.
 template <bool LS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     fisher_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                   const double* __restrict__ wtab, const double* __restrict__ wtan,
                   double* __restrict__ partial, JacArgs A) {
   __shared__ double red[4][256];
+  __shared__ double tan_s[W_STRIDE * kNParams];   // the walker's tangent table, 25 KiB
   const int t = blockIdx.x;
   const int b = blockIdx.y;
   const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
@@ -139,6 +142,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
   const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
   const int64_t k0 = (int64_t)t * A.tile;
   if (k0 >= nact) return;
+  for (int i = threadIdx.x; i < W_STRIDE * kNParams; i += 256) tan_s[i] = wtn[i];
+  __syncthreads();
   const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int p = lane & 15, sub = lane >> 4;
@@ -162,7 +167,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
       const double sA = in ? sqrt(tb[T_WA * N + kk]) : 0.0;
       const double sT = in ? sqrt(tb[T_WT * N + kk]) : 0.0;
       const DetParams& P = A.dt.p[det];
-      const TanTabLane T{wt, wtn, pin ? p : 0};
+      const TanTabLane T{wt, tan_s, pin ? p : 0};
       const ChanT<Dual<1>> c = (P.kind == 2)
                                    ? eval_channels_t<true, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year, P.inv_ptq,
                                                                           br, a, zr, zi)
