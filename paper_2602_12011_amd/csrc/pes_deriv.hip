@@ -1,8 +1,8 @@
 // Derivative kernels of libpes (gfx950): the reverse-mode gradient
-// (adj_kernel), the forward-mode gradient (jac_kernel), the Fisher matrix
-// (fisher_kernel: forward-mode tangents with the J^T J contraction on the
-// FP64 matrix cores) and their per-walker reductions.  Walker tangents come
-// from setup_tan_kernel (pes_kernels.hip).
+// (adj_kernel), the forward-mode Fisher matrix and gradient (forward_body:
+// one (bin, parameter) tangent per lane, the J^T J contraction on the FP64
+// matrix cores) and their per-walker reductions.  Walker tangents come from
+// setup_tan_kernel (pes_kernels.hip).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -14,109 +14,14 @@
 namespace pes {
 
 // ---------------------------------------------------------------- derivatives
-// Forward-mode tangents of the channels, one direction per pass: for each
-// 64-bin sub-tile and detector the 11 passes give dC/dtheta_k for the lane's
-// bin, and the kernel accumulates sum (D - W C) . dC/dtheta_k (the gradient of
-// <d|h> - <h|h>/2) together with <d|h> and <h|h> (PES_GRAD_FORWARD, the
-// cross-check of the reverse sweep).
 __device__ __forceinline__ int64_t active_bins(double fmx, double f0, double df, int64_t N) {
   double nb = ceil((fmx - f0) / df) + 1.0;
   nb = fmin(fmax(nb, 0.0), (double)N);
   return (int64_t)nb;
 }
 
-template <bool LS, bool GEO>
-__device__ __forceinline__ void jac_det(const double* __restrict__ bins, const double* __restrict__ tb,
-                                        const double* __restrict__ wt, const double* __restrict__ wtn,
-                                        const JacArgs& A, int det, int64_t k, bool in, double* g,
-                                        double& dh, double& hh) {
-  const int64_t N = A.N;
-  const int64_t kk = in ? k : N - 1;
-  BinRegs br;
-  br.f = bins[B_F * N + kk];
-  br.f13 = bins[B_F13 * N + kk];
-  br.fm13 = bins[B_FM13 * N + kk];
-  br.fm76 = bins[B_FM76 * N + kk];
-  br.lnf = bins[B_LNF * N + kk];
-  const double zr = tb[T_ZR * N + kk], zi = tb[T_ZI * N + kk], a = tb[T_A * N + kk];
-  const double wA = in ? tb[T_WA * N + kk] : 0.0;
-  const double wT = in ? tb[T_WT * N + kk] : 0.0;
-  const double W[6] = {wA, wA, wA * (1.0 / 3.0), wA * (1.0 / 3.0), wT, wT};
-  double D[6];
-  D[0] = in ? tb[T_DAR * N + kk] : 0.0;
-  D[1] = in ? tb[T_DAI * N + kk] : 0.0;
-  D[2] = in ? tb[T_DER * N + kk] : 0.0;
-  D[3] = in ? tb[T_DEI * N + kk] : 0.0;
-  D[4] = in ? tb[T_DTR * N + kk] : 0.0;
-  D[5] = in ? tb[T_DTI * N + kk] : 0.0;
-  const DetParams& P = A.dt.p[det];
-  double R[6];
-#pragma unroll 1
-  for (int kp = 0; kp < kNParams; ++kp) {
-    const ChanT<Dual<1>> c = eval_channels_t<GEO, LS, 1, Dual<1>>(TanTab{wt, wtn, kp}, det, A.plan,
-                                                              P.inv_year, P.inv_ptq, br, a, zr, zi);
-    const double cv[6] = {c.ar.v, c.ai.v, c.er.v, c.ei.v, c.tr.v, c.ti.v};
-    const double cd[6] = {c.ar.d[0], c.ai.d[0], c.er.d[0], c.ei.d[0], c.tr.d[0], c.ti.d[0]};
-    if (kp == 0) {
-#pragma unroll
-      for (int r = 0; r < 6; ++r) {
-        dh = fma(D[r], cv[r], dh);
-        hh = fma(W[r] * cv[r], cv[r], hh);
-        R[r] = fma(-W[r], cv[r], D[r]);
-      }
-    }
-    double acc = 0.0;
-#pragma unroll
-    for (int r = 0; r < 6; ++r) acc = fma(R[r], cd[r], acc);
-#pragma unroll
-    for (int i = 0; i < kNParams; ++i) g[i] += (i == kp) ? acc : 0.0;   // keeps g in registers
-  }
-}
-
-template <bool LS>
-__global__ void __launch_bounds__(64)
-    jac_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
-               const double* __restrict__ wtab, const double* __restrict__ wtan,
-               double* __restrict__ partial, JacArgs A) {
-  const int t = blockIdx.x;
-  const int b = blockIdx.y;
-  const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
-  const double* __restrict__ wtn = wtan + (int64_t)b * W_STRIDE * kNParams;
-  if (wt[W_VALID] == 0.0) return;
-  const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
-  const int64_t k0 = (int64_t)t * A.tile;
-  if (k0 >= nact) return;
-  const int lane = threadIdx.x;
-  const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
-  double g[kNParams];
-#pragma unroll
-  for (int i = 0; i < kNParams; ++i) g[i] = 0.0;
-  double dh = 0.0, hh = 0.0;
-  for (int64_t s0 = k0; s0 < kend; s0 += 64) {
-    const int64_t k = s0 + lane;
-    const bool in = k < kend;
-    for (int det = 0; det < A.n_det; ++det) {
-      const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * A.N;
-      if (A.dt.p[det].kind == 2)
-        jac_det<LS, true>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh);
-      else
-        jac_det<LS, false>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh);
-    }
-  }
-  const int64_t slot = (int64_t)t * A.B + b;
-  double red[kNParams + 2];
-#pragma unroll
-  for (int i = 0; i < kNParams; ++i) red[i] = wave_sum_dpp(g[i]);
-  red[kNParams] = wave_sum_dpp(dh);
-  red[kNParams + 1] = wave_sum_dpp(hh);
-  if (lane == 0) {
-    double* p = partial + slot * (kNParams + 2);
-#pragma unroll
-    for (int i = 0; i < kNParams + 2; ++i) p[i] = red[i];
-  }
-}
-
-// Fisher matrix, one (bin, parameter) pair per lane: lane l of a wavefront
+// Forward-mode tangents, one (bin, parameter) pair per lane, for the Fisher
+// matrix (and, with GRAD, the forward-mode gradient): lane l of a wavefront
 // carries the tangent direction p = l % 16 (p < 11; the other five lanes
 // contribute zeros) of bin l / 16 of its group of four bins, so after one
 // dual-number evaluation every lane holds sqrt(W) dC_r/dtheta_p for its pair,
@@ -127,11 +32,13 @@ __global__ void __launch_bounds__(64)
 // directions of the same entry); the four wavefronts of a block take
 // interleaved groups of the block's bin tile and their accumulators are added
 // in LDS at the end.
-template <bool LS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-    fisher_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
-                  const double* __restrict__ wtab, const double* __restrict__ wtan,
-                  double* __restrict__ partial, JacArgs A) {
+// With GRAD the same pairs give the forward-mode gradient instead: each lane
+// accumulates sum_r (D - W C)_r dC_r/dtheta_p, the p = 0 lanes also <d|h> and
+// <h|h>, and the block reduces them to the per-tile partials of the gradient.
+template <bool LS, bool GRAD>
+__device__ __forceinline__ void forward_body(const double* __restrict__ bins, const double* __restrict__ tabs,
+                                             const double* __restrict__ wtab, const double* __restrict__ wtan,
+                                             double* __restrict__ partial, const JacArgs& A) {
   __shared__ double red[4][256];
   __shared__ double tan_s[W_STRIDE * kNParams];   // the walker's tangent table, 25 KiB
   const int t = blockIdx.x;
@@ -151,6 +58,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
   const int64_t N = A.N;
   typedef double v4d __attribute__((ext_vector_type(4)));
   v4d acc = {0.0, 0.0, 0.0, 0.0};
+  double gacc = 0.0, dh = 0.0, hh = 0.0;
   for (int64_t s0 = k0 + 4 * wv; s0 < kend; s0 += 16) {
     const int64_t k = s0 + sub;
     const bool in = pin && k < kend;
@@ -173,19 +81,70 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
                                                                           br, a, zr, zi)
                                    : eval_channels_t<false, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year,
                                                                            P.inv_ptq, br, a, zr, zi);
-      const double sE = sA * 0.5773502691896258;   // W_E = W_A / 3
-      const double v[6] = {sA * c.ar.d[0], sA * c.ai.d[0], sE * c.er.d[0],
-                           sE * c.ei.d[0], sT * c.tr.d[0], sT * c.ti.d[0]};
+      if (GRAD) {
+        const double wA = sA * sA, wT = sT * sT;
+        const double W[6] = {wA, wA, wA * (1.0 / 3.0), wA * (1.0 / 3.0), wT, wT};
+        const double D[6] = {in ? tb[T_DAR * N + kk] : 0.0, in ? tb[T_DAI * N + kk] : 0.0,
+                             in ? tb[T_DER * N + kk] : 0.0, in ? tb[T_DEI * N + kk] : 0.0,
+                             in ? tb[T_DTR * N + kk] : 0.0, in ? tb[T_DTI * N + kk] : 0.0};
+        const double cv[6] = {c.ar.v, c.ai.v, c.er.v, c.ei.v, c.tr.v, c.ti.v};
+        const double cd[6] = {c.ar.d[0], c.ai.d[0], c.er.d[0], c.ei.d[0], c.tr.d[0], c.ti.d[0]};
+        const bool first = p == 0;
 #pragma unroll
-      for (int r = 0; r < 6; ++r) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r], v[r], acc, 0, 0, 0);
+        for (int r = 0; r < 6; ++r) {
+          gacc = fma(fma(-W[r], cv[r], D[r]), cd[r], gacc);
+          dh = first ? fma(D[r], cv[r], dh) : dh;
+          hh = first ? fma(W[r] * cv[r], cv[r], hh) : hh;
+        }
+      } else {
+        const double sE = sA * 0.5773502691896258;   // W_E = W_A / 3
+        const double v[6] = {sA * c.ar.d[0], sA * c.ai.d[0], sE * c.er.d[0],
+                             sE * c.ei.d[0], sT * c.tr.d[0], sT * c.ti.d[0]};
+#pragma unroll
+        for (int r = 0; r < 6; ++r) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r], v[r], acc, 0, 0, 0);
+      }
     }
   }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) red[wv][4 * lane + e] = acc[e];
-  __syncthreads();
   const int e = threadIdx.x;
-  const double sum = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
-  partial[((int64_t)t * A.B + b) * 256 + e] = sum;
+  if (GRAD) {
+    // lane (sub, p) of wave w holds its share of d l / d theta_p; <d|h>, <h|h>
+    // sit in the p = 0 lanes.  Fixed-order sums over waves and sub-lanes.
+    red[wv][lane] = gacc;
+    red[wv][64 + lane] = dh;
+    red[wv][128 + lane] = hh;
+    __syncthreads();
+    if (e < kNParams + 2) {
+      const int base = e < kNParams ? 0 : (e == kNParams ? 64 : 128);
+      const int col = e < kNParams ? e : 0;
+      double sum = 0.0;
+      for (int w = 0; w < 4; ++w)
+        for (int q = 0; q < 4; ++q) sum += red[w][base + 16 * q + col];
+      partial[((int64_t)t * A.B + b) * (kNParams + 2) + e] = sum;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[wv][4 * lane + r] = acc[r];
+    __syncthreads();
+    const double sum = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+    partial[((int64_t)t * A.B + b) * 256 + e] = sum;
+  }
+}
+
+// The Fisher variant fits three waves per SIMD; the gradient variant holds the
+// residual as well and runs two without spilling.
+template <bool LS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+    forward_fisher_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
+                          const double* __restrict__ wtab, const double* __restrict__ wtan,
+                          double* __restrict__ partial, JacArgs A) {
+  forward_body<LS, false>(bins, tabs, wtab, wtan, partial, A);
+}
+template <bool LS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    forward_grad_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
+                        const double* __restrict__ wtab, const double* __restrict__ wtan,
+                        double* __restrict__ partial, JacArgs A) {
+  forward_body<LS, true>(bins, tabs, wtab, wtan, partial, A);
 }
 
 // Reverse-mode gradient: for each (walker, bin, detector) one forward
@@ -351,9 +310,9 @@ hipError_t launch_grad(const double* bins, const double* tabs, const double* wta
     else
       hipLaunchKernelGGL((adj_kernel<false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
   } else if (long_sinc) {
-    hipLaunchKernelGGL((jac_kernel<true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+    hipLaunchKernelGGL((forward_grad_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   } else {
-    hipLaunchKernelGGL((jac_kernel<false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+    hipLaunchKernelGGL((forward_grad_kernel<false>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   }
   hipLaunchKernelGGL(grad_finalize_kernel, dim3((A.B + 255) / 256), dim3(256), 0, s, partial, wtab, dd, A, logl,
                      grad);
@@ -364,9 +323,9 @@ hipError_t launch_fisher(const double* bins, const double* tabs, const double* w
                          double* partial, const JacArgs& A, bool long_sinc, double* F, hipStream_t s) {
   const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
   if (long_sinc)
-    hipLaunchKernelGGL((fisher_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
+    hipLaunchKernelGGL((forward_fisher_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   else
-    hipLaunchKernelGGL((fisher_kernel<false>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
+    hipLaunchKernelGGL((forward_fisher_kernel<false>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   hipLaunchKernelGGL(fisher_finalize_kernel, dim3(A.B), dim3(256), 0, s, partial, wtab, A, F);
   return hipGetLastError();
 }
