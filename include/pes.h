@@ -105,6 +105,25 @@ int pes_set_data(pes_ctx* ctx, const double* d, void* stream);
  * Noisy data are the response plus this array. */
 int pes_noise(pes_ctx* ctx, uint64_t seed, double* out, void* stream);
 
+/* Stages of the response for testing, from the same evaluation code with
+ * hooks that write them out (a plain launch, one thread per (walker, bin),
+ * every mode its own unit; not a fast path).  out (dev), by stage:
+ *   PES_PROBE_MODE  [B][n_modes][n_bins][3]: mode amplitude with the cutoff
+ *     taper (0 beyond the cutoff), SPA phase in cycles mod 1 (the mode's
+ *     h = amplitude e^{-2 pi i phase}, Sec. 2.1), t_f - t_c [s] (eq. eq_tf;
+ *     NaN beyond the cutoff);
+ *   PES_PROBE_GEOM  [B][n_det][n_modes][n_bins][12]: at the mode's t_f, for
+ *     arms t = 0, 1, 2 (arm t opposite spacecraft t): k.n_t, (n_t.p)^2 -
+ *     (n_t.q)^2, (n_t.p)(n_t.q), then k.(x_0 - c), k.(x_1 - c) and k.c [light-s]
+ *     (x_s spacecraft, c the constellation centre; eq. eq_fd_resp's geometry);
+ *   PES_PROBE_LINKS [B][n_det][n_bins][12]: per arm t (Re, Im) of the forward
+ *     and backward link sums of eq. eq_fd_resp over modes, divided by the
+ *     common factor -i pi f L e^{-i pi f L}: arm 0 carries y_32 / y_23, arm 1
+ *     y_13 / y_31, arm 2 y_21 / y_12.
+ * B <= 65535; PES_EINVAL for another stage. */
+enum { PES_PROBE_MODE = 0, PES_PROBE_GEOM = 1, PES_PROBE_LINKS = 2 };
+int pes_probe(pes_ctx* ctx, const double* theta, int64_t B, int stage, double* out, void* stream);
+
 /* Noise-free response: out (dev) [B][n_det][3][n_bins] complex = A, E, T of
  * h(theta_b) (eqs. eq_tf, eq_fd_resp, FD TDI, A/E/T). */
 int pes_response(pes_ctx* ctx, const double* theta, int64_t B, double* out, void* stream);

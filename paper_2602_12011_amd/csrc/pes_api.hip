@@ -473,6 +473,28 @@ int pes_noise(pes_ctx* c, uint64_t seed, double* out, void* stream) {
   return PES_OK;
 }
 
+int pes_probe(pes_ctx* c, const double* theta, int64_t B, int stage, double* out, void* stream) {
+  if (!c || (B > 0 && (!theta || !out)) || B < 0 || B > 65535 || stage < PES_PROBE_MODE || stage > PES_PROBE_LINKS)
+    return PES_EINVAL;
+  if (B == 0) return PES_OK;
+  int st = ensure_workspace(c, B);
+  if (st != PES_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, setup_args(c), s));
+  ResponseArgs ra;
+  ra.bins = c->bins;
+  ra.tabs = c->tabs;
+  ra.wtab = c->wtab;
+  ra.out = out;
+  ra.N = c->N;
+  ra.n_modes = c->cfg.n_modes;
+  ra.n_det = c->cfg.n_det;
+  ra.plan = c->plan;
+  ra.dt = c->dt;
+  PES_HIP(c, launch_probe(ra, B, c->long_sinc, stage, s));
+  return PES_OK;
+}
+
 int pes_response(pes_ctx* c, const double* theta, int64_t B, double* out, void* stream) {
   if (!c || (B > 0 && (!theta || !out)) || B < 0 || B > 65535) return PES_EINVAL;
   if (B == 0) return PES_OK;

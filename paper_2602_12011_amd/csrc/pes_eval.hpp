@@ -128,13 +128,25 @@ struct ChanT {
   S ar, ai, er, ei, tr, ti;
 };
 
+// Hooks into the stages of one evaluation, for the stage probes of the test
+// suite; the hot path passes NoProbe, whose empty hooks compile to nothing.
+struct NoProbe {
+  template <class S>
+  __device__ __forceinline__ void mode(int, const S&, const S&, const S&) const {}
+  template <class S>
+  __device__ __forceinline__ void geom(int, const S*, const S*, const S*, const S*, const S&) const {}
+  template <class S>
+  __device__ __forceinline__ void links(const S*) const {}
+};
+
 // Tab: accessor of this walker's constant table (wavefront-uniform); det: the
 // detector block.  S = double (values) or Dual<1> (value and one tangent).
 // GEO selects the geocentric orbit.  a = pi f L, (zr, zi) = e^{-2 pi i f L}.
-template <bool GEO, bool LONG_SINC, int CLS, class S, class Tab>
+template <bool GEO, bool LONG_SINC, int CLS, class S, class Tab, class Probe = NoProbe>
 __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const ModePlan& plan,
                                                     double inv_year, double inv_ptq, const BinRegs& b,
-                                                    double a, double zr, double zi) {
+                                                    double a, double zr, double zi,
+                                                    const Probe& probe = Probe()) {
   S yFr0 = 0.0, yFi0 = 0.0, yBr0 = 0.0, yBi0 = 0.0;
   S yFr1 = 0.0, yFi1 = 0.0, yBr1 = 0.0, yBi1 = 0.0;
   S yFr2 = 0.0, yFi2 = 0.0, yBr2 = 0.0, yBi2 = 0.0;
@@ -189,6 +201,7 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
     S amp = wm(M_AM1) * v;
     amp = fma(wm(M_AM2), v2, amp) + wm(M_AM0);
     amp *= scale;
+    probe.mode(j, amp, phase, tau);   // amplitude with taper, phase [cycles], t_f - t_c [s]
     S aP = amp * wm(M_KP);
     S aC2 = amp * wm(M_KC);   // the table holds 2 K_x
     // the paired mode: its amplitude on the rotated polarization factors
@@ -221,6 +234,10 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
 #undef PES_LIN
     const S kn2 = -(kn0 + kn1), np2 = -(np0 + np1), nq2 = -(nq0 + nq1);
     const S kR = fma(wd(D_KR), ca, wd(D_KR + 1) * sa);
+    {
+      const S knv[3] = {kn0, kn1, kn2}, npv[3] = {np0, np1, np2}, nqv[3] = {nq0, nq1, nq2}, kdv[2] = {kd0, kd1};
+      probe.geom(j, knv, npv, nqv, kdv, kR);
+    }
     // mode phase plus the Roemer delay of the centre: E = e^{-2 pi i (phase + f k.R)}
     S sp, cp;
     sincos_cycles(fma(b.f, kR, phase), sp, cp);
@@ -270,6 +287,10 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
   };
   for (int u = 0; u < plan.n_pairs; ++u) unit(plan.lead[u], plan.member[u], std::true_type{});
   for (int u = plan.n_pairs; u < plan.n_units; ++u) unit(plan.lead[u], -1, std::false_type{});
+  {
+    const S yv[12] = {yFr0, yFi0, yBr0, yBi0, yFr1, yFi1, yBr1, yBi1, yFr2, yFi2, yBr2, yBi2};
+    probe.links(yv);
+  }
   // links: arm 0 carries y32 (F) / y23 (B), arm 1 y13 / y31, arm 2 y21 / y12.
   // X = y13 - y12 + z (y31 - y21), Y = y21 - y23 + z (y12 - y32),
   // Z = y32 - y31 + z (y23 - y13)   (the common factor G is in the tables)

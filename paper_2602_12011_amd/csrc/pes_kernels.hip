@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "../../include/pes.h"
 #include "pes_eval.hpp"
 #include "pes_launch.hpp"
 
@@ -738,6 +739,89 @@ __global__ void response_kernel(ResponseArgs A) {
   }
 }
 
+// ---------------------------------------------------------------- stage probes
+// The evaluation of the response with hooks that write its stages out, one
+// thread per (walker, bin), every mode its own unit.  Test entry point only.
+struct ProbeWriter {
+  int stage, det, n_modes, n_det;
+  int64_t b, k, N;
+  double* out;
+  __device__ void mode(int j, double amp, double phase, double tau) const {
+    if (stage != PES_PROBE_MODE || det != 0) return;
+    double* o = out + ((b * n_modes + j) * N + k) * 3;
+    o[0] = amp;
+    o[1] = phase - floor(phase);
+    o[2] = tau;
+  }
+  __device__ void geom(int j, const double* kn, const double* np, const double* nq, const double* kd,
+                       double kR) const {
+    if (stage != PES_PROBE_GEOM) return;
+    double* o = out + (((b * n_det + det) * n_modes + j) * N + k) * 12;
+    for (int t = 0; t < 3; ++t) {
+      o[t] = kn[t];
+      o[3 + t] = np[t] * np[t] - nq[t] * nq[t];
+      o[6 + t] = np[t] * nq[t];
+    }
+    o[9] = kd[0];
+    o[10] = kd[1];
+    o[11] = kR;
+  }
+  __device__ void links(const double* y) const {
+    if (stage != PES_PROBE_LINKS) return;
+    double* o = out + ((b * n_det + det) * N + k) * 12;
+    for (int i = 0; i < 12; ++i) o[i] = y[i];
+  }
+};
+
+template <bool LS>
+__global__ void probe_kernel(ResponseArgs A, int64_t B, int stage) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = A.N;
+  if (g >= B * N) return;
+  const int64_t b = g / N, k = g - b * N;
+  const double* __restrict__ wt = A.wtab + b * W_STRIDE;
+  ModePlan plan;
+  plan.n_units = A.n_modes;
+  plan.n_pairs = 0;
+  for (int j = 0; j < kMaxModes; ++j) {
+    plan.lead[j] = j;
+    plan.member[j] = -1;
+  }
+  // stages beyond a mode's cutoff are not evaluated: amplitude 0, NaN elsewhere
+  if (stage == PES_PROBE_MODE)
+    for (int j = 0; j < A.n_modes; ++j) {
+      double* o = A.out + ((b * A.n_modes + j) * N + k) * 3;
+      o[0] = 0.0;
+      o[1] = NAN;
+      o[2] = NAN;
+    }
+  if (stage == PES_PROBE_GEOM)
+    for (int i = 0; i < A.n_det * A.n_modes * 12; ++i) {
+      const int det = i / (A.n_modes * 12), j = (i / 12) % A.n_modes, r = i % 12;
+      A.out[(((b * A.n_det + det) * A.n_modes + j) * N + k) * 12 + r] = NAN;
+    }
+  if (wt[W_VALID] == 0.0) return;
+  BinRegs br;
+  br.f = A.bins[B_F * N + k];
+  br.f13 = A.bins[B_F13 * N + k];
+  br.fm13 = A.bins[B_FM13 * N + k];
+  br.fm76 = A.bins[B_FM76 * N + k];
+  br.lnf = A.bins[B_LNF * N + k];
+  for (int det = 0; det < A.n_det; ++det) {
+    const double* tb = A.tabs + (int64_t)det * T_NFIELDS * N;
+    const DetParams& P = A.dt.p[det];
+    const ProbeWriter pw{stage, det, A.n_modes, A.n_det, b, k, N, A.out};
+    if (P.kind == 2)
+      eval_channels_t<true, LS, 1, double, ValTab, ProbeWriter>(ValTab{wt}, det, plan, P.inv_year, P.inv_ptq, br,
+                                                               tb[T_A * N + k], tb[T_ZR * N + k],
+                                                               tb[T_ZI * N + k], pw);
+    else
+      eval_channels_t<false, LS, 1, double, ValTab, ProbeWriter>(ValTab{wt}, det, plan, P.inv_year, P.inv_ptq, br,
+                                                                tb[T_A * N + k], tb[T_ZR * N + k],
+                                                                tb[T_ZI * N + k], pw);
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_bin_tables(double* bins, double* tabs, int64_t N, double f0, double df, int n_det,
                              const DetTable& dt, hipStream_t s) {
@@ -797,6 +881,16 @@ hipError_t launch_finalize(const double* partial, const int* ntiles, const doubl
                            int64_t B, double* logl, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((B + kFinW - 1) / kFinW)), dim3(kFinW * kFinP), 0, s, partial,
                      ntiles, wtab, dd, B, logl);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, int stage, hipStream_t s) {
+  const int64_t n = B * a.N;
+  const dim3 grid((unsigned)((n + 63) / 64));
+  if (long_sinc)
+    hipLaunchKernelGGL(probe_kernel<true>, grid, dim3(64), 0, s, a, B, stage);
+  else
+    hipLaunchKernelGGL(probe_kernel<false>, grid, dim3(64), 0, s, a, B, stage);
   return hipGetLastError();
 }
 

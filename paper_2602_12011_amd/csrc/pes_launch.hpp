@@ -78,6 +78,7 @@ hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, bool sorted,
 hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, int grid, hipStream_t s);
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
                            int64_t B, double* logl, hipStream_t s);
+hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, int stage, hipStream_t s);
 hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, hipStream_t s);
 int loglike_blocks_per_cu(int bpl, bool long_sinc);
 

@@ -41,6 +41,7 @@ class Prior(C.Structure):
 
 GRAD_ADJOINT, GRAD_FORWARD = 0, 1
 SCHED_QUEUE, SCHED_GRID = 0, 1
+PROBE_MODE, PROBE_GEOM, PROBE_LINKS = 0, 1, 2
 
 PRIOR_KIND = {"uniform": 0, "loguniform": 1, "cosine_sin": 2, "sin": 2, "arcsin": 3, "cos": 3,
               "periodic": 4, "fixed": 5}
@@ -70,6 +71,7 @@ def lib():
         L.pes_set_grad_method.argtypes = [vp, C.c_int]
         L.pes_set_schedule.argtypes = [vp, C.c_int]
         L.pes_noise.argtypes = [vp, C.c_uint64, vp, vp]
+        L.pes_probe.argtypes = [vp, vp, C.c_int64, C.c_int, vp, vp]
         L.pes_flow_create.argtypes = [C.c_uint64, C.POINTER(vp)]
         L.pes_flow_destroy.argtypes = [vp]
         L.pes_flow_num_params.argtypes = []
@@ -111,7 +113,7 @@ def lib():
         for name in ("pes_create", "pes_destroy", "pes_reserve", "pes_set_data",
                      "pes_response", "pes_loglike", "pes_timing", "pes_timing_read",
                      "pes_set_tuning", "pes_get_tuning", "pes_autotune", "pes_grad", "pes_set_grad_method",
-                     "pes_set_schedule", "pes_noise",
+                     "pes_set_schedule", "pes_noise", "pes_probe",
                      "pes_flow_create", "pes_flow_destroy", "pes_flow_set_params", "pes_flow_get_params",
                      "pes_flow_set_norm", "pes_flow_set_affine", "pes_flow_get_affine", "pes_flow_set_temperature", "pes_flow_forward", "pes_flow_inverse",
                      "pes_flow_nll_grad", "pes_flow_adam_step", "pes_flow_fit", "pes_sampler_set_flow",
@@ -164,6 +166,7 @@ class Context:
         self.cfg = cfg
         self.n_det = len(cfg["detectors"])
         self.n_bins = int(cfg["n_bins"])
+        self.n_modes = len(cfg["modes"])
         self._c = make_config(cfg)
         h = C.c_void_p()
         self._check(lib().pes_create(C.byref(self._c), C.byref(h)), "pes_create")
@@ -238,6 +241,19 @@ class Context:
             out = torch.empty((self.n_det, 3, self.n_bins, 2), dtype=torch.float64, device="cuda")
         self._check(lib().pes_noise(self.h, C.c_uint64(seed & (2 ** 64 - 1)), _dev_f64(out, "out"),
                                     _stream(stream)), "pes_noise")
+        return out
+
+    def probe(self, theta, stage, stream=None):
+        """Stages of the response for testing (see pes_probe): stage "mode",
+        "geom" or "links"."""
+        theta = theta.contiguous()
+        B = theta.shape[0]
+        code, shape = {"mode": (PROBE_MODE, (B, self.n_modes, self.n_bins, 3)),
+                       "geom": (PROBE_GEOM, (B, self.n_det, self.n_modes, self.n_bins, 12)),
+                       "links": (PROBE_LINKS, (B, self.n_det, self.n_bins, 12))}[stage]
+        out = torch.empty(shape, dtype=torch.float64, device=theta.device)
+        self._check(lib().pes_probe(self.h, _dev_f64(theta, "theta"), B, code, _dev_f64(out, "out"),
+                                    _stream(stream)), "pes_probe")
         return out
 
     def response(self, theta, out=None, stream=None):
