@@ -34,3 +34,24 @@ def test_strerror_without_gpu():
     assert lib.pes_strerror(-1) == b"invalid argument"
     # a null config is rejected before any device work
     assert lib.pes_create(None, None) == -1
+
+
+def test_argument_checks_without_gpu():
+    """Entry points reject a null context or an unknown mode before any device
+    work (PES_EINVAL = -1)."""
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2602_12011_amd", "libpes.so"))
+    v = ctypes.c_void_p
+    lib.pes_set_schedule.argtypes = [v, ctypes.c_int]
+    lib.pes_set_grad_method.argtypes = [v, ctypes.c_int]
+    lib.pes_set_tuning.argtypes = [v, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.pes_noise.argtypes = [v, ctypes.c_uint64, v, v]
+    lib.pes_probe.argtypes = [v, v, ctypes.c_int64, ctypes.c_int, v, v]
+    lib.pes_loglike.argtypes = [v, v, ctypes.c_int64, v, v]
+    lib.pes_fisher.argtypes = [v, v, ctypes.c_int64, v, v]
+    assert lib.pes_set_schedule(None, 0) == -1
+    assert lib.pes_set_grad_method(None, 0) == -1
+    assert lib.pes_set_tuning(None, 1, 16, 0) == -1
+    assert lib.pes_noise(None, 1, None, None) == -1
+    assert lib.pes_probe(None, None, 1, 0, None, None) == -1
+    assert lib.pes_loglike(None, None, 1, None, None) == -1
+    assert lib.pes_fisher(None, None, 1, None, None) == -1
