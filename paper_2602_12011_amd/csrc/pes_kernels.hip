@@ -467,18 +467,20 @@ __global__ void __launch_bounds__(1024) plan_kernel(const int* __restrict__ ntil
   if (sorted) {  // counting sort by descending tile count
     int shift = 0;
     while ((ntmax >> shift) >= kPlanKeys) ++shift;
-    for (int i = threadIdx.x; i < kPlanKeys; i += blockDim.x) hist[i] = 0;
+    const int nkeys = (ntmax >> shift) + 1;   // tile counts 0 .. ntmax
+    for (int i = threadIdx.x; i < nkeys; i += blockDim.x) hist[i] = 0;
     __syncthreads();
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
-      const int key = kPlanKeys - 1 - (ntiles[b] >> shift);   // descending tile counts
+      const int key = nkeys - 1 - (ntiles[b] >> shift);   // descending tile counts
       atomicAdd(&hist[key], 1);
     }
     __syncthreads();
-    {  // exclusive scan of the histogram in LDS (8 entries per thread)
-      const int per = kPlanKeys / 1024;
+    {  // exclusive scan of the histogram in LDS (a contiguous chunk per thread)
+      const int per = (nkeys + 1023) / 1024;
       const int base = threadIdx.x * per;
       int local = 0;
-      for (int i = 0; i < per; ++i) local += hist[base + i];
+      for (int i = 0; i < per; ++i)
+        if (base + i < nkeys) local += hist[base + i];
       int incl = local;
       const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
       for (int off = 1; off < 64; off <<= 1) {
@@ -498,6 +500,7 @@ __global__ void __launch_bounds__(1024) plan_kernel(const int* __restrict__ ntil
       __syncthreads();
       int run = incl - local + wsum[wv];
       for (int i = 0; i < per; ++i) {
+        if (base + i >= nkeys) break;
         const int h = hist[base + i];
         hist[base + i] = run;
         run += h;
@@ -505,7 +508,7 @@ __global__ void __launch_bounds__(1024) plan_kernel(const int* __restrict__ ntil
     }
     __syncthreads();
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
-      const int key = kPlanKeys - 1 - (ntiles[b] >> shift);
+      const int key = nkeys - 1 - (ntiles[b] >> shift);
       const int pos = atomicAdd(&hist[key], 1);
       perm[pos] = b;
     }
