@@ -192,6 +192,13 @@ int pes_sampler_destroy(pes_sampler* s);
  * prior, zero the acceptance counts and the step counter.  Synchronizes. */
 int pes_sampler_set_state(pes_sampler* s, const double* theta, void* stream);
 
+/* Checkpoint / resume: set the completed-step counter, which keys every
+ * random number of the following steps.  A sampler created with the same
+ * context, prior and seed, given a saved state by pes_sampler_set_state and
+ * the saved step count here, continues the saved run bitwise (the acceptance
+ * counts restart from zero).  Synchronizes the device. */
+int pes_sampler_set_step(pes_sampler* s, uint64_t steps);
+
 /* Advance n_steps steps (asynchronous). */
 int pes_sampler_step(pes_sampler* s, int64_t n_steps, void* stream);
 

@@ -794,6 +794,14 @@ int pes_sampler_set_state(pes_sampler* s, const double* theta, void* stream) {
   return PES_OK;
 }
 
+int pes_sampler_set_step(pes_sampler* s, uint64_t steps) {
+  if (!s) return PES_EINVAL;
+  PES_HIP(s->ctx, hipDeviceSynchronize());
+  const uint64_t v[2] = {steps, steps};
+  PES_HIP(s->ctx, hipMemcpy(s->step, v, sizeof(v), hipMemcpyHostToDevice));
+  return PES_OK;
+}
+
 int pes_sampler_step(pes_sampler* s, int64_t n_steps, void* stream) {
   if (!s || n_steps < 0) return PES_EINVAL;
   for (int64_t n = 0; n < n_steps; ++n) {

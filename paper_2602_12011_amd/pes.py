@@ -72,6 +72,7 @@ def lib():
         L.pes_set_schedule.argtypes = [vp, C.c_int]
         L.pes_noise.argtypes = [vp, C.c_uint64, vp, vp]
         L.pes_probe.argtypes = [vp, vp, C.c_int64, C.c_int, vp, vp]
+        L.pes_sampler_set_step.argtypes = [vp, C.c_uint64]
         L.pes_flow_create.argtypes = [C.c_uint64, C.POINTER(vp)]
         L.pes_flow_destroy.argtypes = [vp]
         L.pes_flow_num_params.argtypes = []
@@ -113,7 +114,7 @@ def lib():
         for name in ("pes_create", "pes_destroy", "pes_reserve", "pes_set_data",
                      "pes_response", "pes_loglike", "pes_timing", "pes_timing_read",
                      "pes_set_tuning", "pes_get_tuning", "pes_autotune", "pes_grad", "pes_set_grad_method",
-                     "pes_set_schedule", "pes_noise", "pes_probe",
+                     "pes_set_schedule", "pes_noise", "pes_probe", "pes_sampler_set_step",
                      "pes_flow_create", "pes_flow_destroy", "pes_flow_set_params", "pes_flow_get_params",
                      "pes_flow_set_norm", "pes_flow_set_affine", "pes_flow_get_affine", "pes_flow_set_temperature", "pes_flow_forward", "pes_flow_inverse",
                      "pes_flow_nll_grad", "pes_flow_adam_step", "pes_flow_fit", "pes_sampler_set_flow",
@@ -368,6 +369,10 @@ class Sampler:
         theta = theta.contiguous()
         self.ctx._check(lib().pes_sampler_set_state(self.h, _dev_f64(theta, "theta"), _stream(stream)),
                         "pes_sampler_set_state")
+
+    def set_step(self, steps):
+        """Resume: the completed-step count of a saved run (see pes_sampler_set_step)."""
+        self.ctx._check(lib().pes_sampler_set_step(self.h, C.c_uint64(int(steps))), "pes_sampler_set_step")
 
     def step(self, n=1, stream=None):
         self.ctx._check(lib().pes_sampler_step(self.h, int(n), _stream(stream)), "pes_sampler_step")

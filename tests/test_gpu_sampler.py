@@ -166,3 +166,36 @@ def test_sampling_matches_fisher_on_extrinsic_subset(orc, torch_dev, pes):
     for j in range(4):
         p = stats.kstest((x[:, j] - W.THETA0[idx[j]]) / sd[j], "norm").pvalue
         assert p > 1e-4, (free[j], p)
+
+
+def test_checkpoint_resume_is_bitwise(orc, torch_dev, pes):
+    """A run of 6 steps against 3 steps, a checkpoint (walker state and step
+    count), and 3 more steps of a fresh sampler resumed from it: the same
+    walkers and log-likelihoods to the bit."""
+    torch = torch_dev
+    cfg = W.config("cfg1", n_bins=5000)
+    d = orc.response(cfg, W.THETA0)
+    prior = _prior_spec(W.PARAM_NAMES)
+    rng = np.random.default_rng(19)
+    th0 = torch.from_numpy(W.THETA0 + 1e-5 * W.prior_widths() * rng.normal(size=(64, 11))).to("cuda")
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(d).to("cuda"))
+    a = pes.Sampler(ctx, prior, 64, 31)
+    a.set_state(th0)
+    a.step(6)
+    ta, La, _, na = a.state()
+    a.close()
+    b = pes.Sampler(ctx, prior, 64, 31)
+    b.set_state(th0)
+    b.step(3)
+    tm, _, _, nm = b.state()
+    b.close()
+    c = pes.Sampler(ctx, prior, 64, 31)
+    c.set_state(tm)
+    c.set_step(nm)
+    c.step(3)
+    tc, Lc, _, nc = c.state()
+    c.close()
+    ctx.close()
+    assert nm == 3 and na == nc == 6
+    assert torch.equal(ta, tc) and torch.equal(La, Lc)
