@@ -144,7 +144,8 @@ int pes_grad(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double*
  *   PES_GRAD_ADJOINT (default): hand-written reverse sweep per bin with the
  *     forward values recomputed (no per-bin storage); adjoints of the walker
  *     table contracted with its theta-derivatives.
- *   PES_GRAD_FORWARD: forward-mode tangents, one parameter direction per pass.
+ *   PES_GRAD_FORWARD: forward-mode tangents, one (bin, parameter direction)
+ *     pair per lane (the evaluation of pes_fisher); the cross-check.
  * PES_EINVAL for another value. */
 enum { PES_GRAD_ADJOINT = 0, PES_GRAD_FORWARD = 1 };
 int pes_set_grad_method(pes_ctx* ctx, int method);
