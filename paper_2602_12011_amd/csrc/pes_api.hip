@@ -120,7 +120,7 @@ int ensure_workspace(pes_ctx* c, int64_t B) {
 }
 
 constexpr int kGradTile = 1024;
-constexpr int kFisherTile = 4096;
+constexpr int kFisherTile = 1024;
 
 void free_jac(pes_ctx* c) {
   (void)hipFree(c->wtan);
@@ -135,7 +135,7 @@ int ensure_jac(pes_ctx* c, int64_t B) {
   if (st != PES_OK) return st;
   const int64_t ng = (c->N + kGradTile - 1) / kGradTile, nf = (c->N + kFisherTile - 1) / kFisherTile;
   const int64_t cap = std::max<int64_t>(B, 16);
-  const int64_t need = std::max(ng * cap * (kNParams + 2), nf * cap * 256);
+  const int64_t need = std::max(ng * cap * (kNParams + 2), nf * cap * kNParams * kNParams);
   if (B <= c->jcap && need <= c->jpart_n) return PES_OK;
   free_jac(c);
   if (hipMalloc(&c->wtan, sizeof(double) * cap * W_STRIDE * kNParams) != hipSuccess ||

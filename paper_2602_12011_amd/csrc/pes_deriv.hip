@@ -125,8 +125,12 @@ __device__ __forceinline__ void forward_body(const double* __restrict__ bins, co
 #pragma unroll
     for (int r = 0; r < 4; ++r) red[wv][4 * lane + r] = acc[r];
     __syncthreads();
+    // accumulator element e: lane e / 4, register e % 4 <-> (row 4 (e % 4) + (e / 4) / 16,
+    // column (e / 4) % 16); the 11 x 11 block is kept, row-major
     const double sum = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
-    partial[((int64_t)t * A.B + b) * 256 + e] = sum;
+    const int row = 4 * (e & 3) + ((e >> 2) >> 4), col = (e >> 2) & 15;
+    if (row < kNParams && col < kNParams)
+      partial[((int64_t)t * A.B + b) * (kNParams * kNParams) + row * kNParams + col] = sum;
   }
 }
 
@@ -279,25 +283,22 @@ __global__ void grad_finalize_kernel(const double* __restrict__ partial, const d
   if (logl) logl[b] = (s[kNParams] - 0.5 * s[kNParams + 1]) - 0.5 * dd[0];
 }
 
-// Fisher matrix: the 16 x 16 FP64 matrix-core accumulator of each tile is held
-// as lane l, element r <-> (row 4 r + l / 16, column l % 16); tiles summed in
-// order, the leading 11 x 11 block written out.
+// Fisher matrix: the per-tile 11 x 11 blocks summed in tile order.
 __global__ void fisher_finalize_kernel(const double* __restrict__ partial, const double* __restrict__ wtab,
                                        JacArgs A, double* __restrict__ F) {
   const int b = blockIdx.x;
-  const int e = threadIdx.x;   // 0..255: lane = e / 4, r = e % 4
+  const int e = threadIdx.x;   // row * 11 + column
+  if (e >= kNParams * kNParams) return;
   const double* wt = wtab + (int64_t)b * W_STRIDE;
-  const int lane = e >> 2, r = e & 3;
-  const int row = 4 * r + (lane >> 4), col = lane & 15;
   double s = 0.0;
   if (wt[W_VALID] != 0.0) {
     const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
     const int nt = (int)((nact + A.tile - 1) / A.tile);
-    for (int t = 0; t < nt; ++t) s += partial[((int64_t)t * A.B + b) * 256 + e];
+    for (int t = 0; t < nt; ++t) s += partial[((int64_t)t * A.B + b) * (kNParams * kNParams) + e];
   } else {
     s = NAN;
   }
-  if (row < kNParams && col < kNParams) F[((int64_t)b * kNParams + row) * kNParams + col] = s;
+  F[(int64_t)b * kNParams * kNParams + e] = s;
 }
 
 hipError_t launch_grad(const double* bins, const double* tabs, const double* wtab, const double* wtan,
@@ -326,7 +327,7 @@ hipError_t launch_fisher(const double* bins, const double* tabs, const double* w
     hipLaunchKernelGGL((forward_fisher_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   else
     hipLaunchKernelGGL((forward_fisher_kernel<false>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
-  hipLaunchKernelGGL(fisher_finalize_kernel, dim3(A.B), dim3(256), 0, s, partial, wtab, A, F);
+  hipLaunchKernelGGL(fisher_finalize_kernel, dim3(A.B), dim3(128), 0, s, partial, wtab, A, F);
   return hipGetLastError();
 }
 
