@@ -86,7 +86,13 @@ int pes_create(const pes_config* cfg, pes_ctx** out);
 int pes_destroy(pes_ctx* ctx);
 
 /* Reserve workspace for batches of up to max_walkers samples so that later
- * compute calls allocate nothing (needed before capturing them in a graph). */
+ * pes_loglike, pes_response, pes_probe and sampler calls allocate nothing
+ * (needed before capturing them in a graph).  pes_grad and pes_fisher keep a
+ * workspace of their own (the tangent table, 25 KiB per walker, and per-tile
+ * partials, under 1 KiB per walker per 1024 bins), grown on a call with a
+ * larger batch than any before: call them once at the largest batch to size
+ * it.
+ * Errors: PES_EINVAL (negative size), PES_ENOMEM. */
 int pes_reserve(pes_ctx* ctx, int64_t max_walkers);
 
 /* Upload the observed data: d (dev) is [n_det][3][n_bins] complex, channels
