@@ -131,12 +131,15 @@ enum { PES_PROBE_MODE = 0, PES_PROBE_GEOM = 1, PES_PROBE_LINKS = 2 };
 int pes_probe(pes_ctx* ctx, const double* theta, int64_t B, int stage, double* out, void* stream);
 
 /* Noise-free response: out (dev) [B][n_det][3][n_bins] complex = A, E, T of
- * h(theta_b) (eqs. eq_tf, eq_fd_resp, FD TDI, A/E/T). */
+ * h(theta_b) (eqs. eq_tf, eq_fd_resp, FD TDI, A/E/T).  theta (dev) [B][11].
+ * B <= 65535; PES_EINVAL otherwise or for a null pointer with B > 0. */
 int pes_response(pes_ctx* ctx, const double* theta, int64_t B, double* out, void* stream);
 
 /* log L(theta_b) = -1/2 sum_det sum_{A,E,T} sum_k 4 df |d - h|^2 / S
  * (eq. eq_ll_fd joint over channels and detectors; constants dropped).
- * theta (dev) [B][11], logl (dev) [B].  Requires pes_set_data. */
+ * theta (dev) [B][11], logl (dev) [B].  Requires pes_set_data (PES_ESTATE
+ * before it).  B <= 2^24; PES_EINVAL otherwise or for a null pointer with
+ * B > 0. */
 int pes_loglike(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void* stream);
 
 /* Gradient of log L with respect to theta (Sec. 2.3 differentiates the
