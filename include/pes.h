@@ -86,12 +86,13 @@ int pes_create(const pes_config* cfg, pes_ctx** out);
 int pes_destroy(pes_ctx* ctx);
 
 /* Reserve workspace for batches of up to max_walkers samples so that later
- * pes_loglike, pes_response, pes_probe and sampler calls allocate nothing
- * (needed before capturing them in a graph).  pes_grad and pes_fisher keep a
- * workspace of their own (the tangent table, 25 KiB per walker, and per-tile
- * partials, under 1 KiB per walker per 1024 bins), grown on a call with a
- * larger batch than any before: call them once at the largest batch to size
- * it.
+ * pes_loglike, pes_response, pes_probe, pes_grad and pes_fisher calls with a
+ * batch of at most that size allocate nothing (needed before capturing them
+ * in a graph).  The derivative part (the walker tangent table, 25 KiB per
+ * walker, and per-tile partial sums, under 1 KiB per walker per 1024 bins) is
+ * sized for min(max_walkers, 65535), the batch limit of pes_grad and
+ * pes_fisher.  Without it those calls grow their workspace on the first call
+ * with a larger batch than any before.
  * Errors: PES_EINVAL (negative size), PES_ENOMEM. */
 int pes_reserve(pes_ctx* ctx, int64_t max_walkers);
 
@@ -139,7 +140,9 @@ int pes_response(pes_ctx* ctx, const double* theta, int64_t B, double* out, void
  * (eq. eq_ll_fd joint over channels and detectors; constants dropped).
  * theta (dev) [B][11], logl (dev) [B].  Requires pes_set_data (PES_ESTATE
  * before it).  B <= 2^24; PES_EINVAL otherwise or for a null pointer with
- * B > 0. */
+ * B > 0.  PES_ESHAPE when the work plan, ceil(B / walkers per item) x
+ * ceil(n_bins / bin tile) items, exceeds 2^31 - 65537 (its int32 counters);
+ * a larger walkers-per-item tuning (pes_set_tuning) lowers the count. */
 int pes_loglike(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void* stream);
 
 /* Gradient of log L with respect to theta (Sec. 2.3 differentiates the
@@ -214,7 +217,13 @@ int pes_sampler_step(pes_sampler* s, int64_t n_steps, void* stream);
 
 /* Capture one step in a HIP graph (kernels only, no allocation or memset) and
  * replay it n_steps times; the replay is bitwise identical to
- * pes_sampler_step.  The graph stays valid until pes_sampler_destroy. */
+ * pes_sampler_step.  The graph's kernels point into the context's and the
+ * flow's workspaces: a later call on the context with a larger batch than the
+ * sampler's (pes_loglike, pes_response, pes_probe, pes_grad, pes_fisher,
+ * pes_reserve) or a flow call with more rows may reallocate them, and
+ * pes_sampler_set_flow may change the flow.  pes_sampler_launch then returns
+ * PES_ESTATE without launching anything; capture again.  pes_reserve before
+ * the capture avoids the reallocation. */
 int pes_sampler_capture(pes_sampler* s, void* stream);
 int pes_sampler_launch(pes_sampler* s, int64_t n_steps, void* stream);
 

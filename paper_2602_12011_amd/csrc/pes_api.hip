@@ -56,6 +56,7 @@ struct pes_ctx {
   int* gstart = nullptr;
   int* counters = nullptr;
   double* partial = nullptr;
+  uint64_t ws_gen = 0;        // bumped whenever the workspace above is reallocated
   // derivative workspace
   int64_t jcap = 0;
   double* wtan = nullptr;      // [jcap][W_STRIDE][11]
@@ -116,10 +117,12 @@ int ensure_workspace(pes_ctx* c, int64_t B) {
     return PES_ENOMEM;
   }
   c->cap = cap;
+  ++c->ws_gen;
   return PES_OK;
 }
 
 constexpr int kGradTile = 1024;
+constexpr int64_t kMaxDerivBatch = 65535;   // batch limit of pes_grad and pes_fisher
 constexpr int kFisherTile = 1024;
 
 void free_jac(pes_ctx* c) {
@@ -443,7 +446,9 @@ int pes_autotune(pes_ctx* c, const double* theta, int64_t B, double* logl, doubl
 
 int pes_reserve(pes_ctx* c, int64_t max_walkers) {
   if (!c || max_walkers < 0) return PES_EINVAL;
-  return ensure_workspace(c, max_walkers);
+  const int st = ensure_workspace(c, max_walkers);
+  if (st != PES_OK || max_walkers == 0) return st;
+  return ensure_jac(c, std::min<int64_t>(max_walkers, kMaxDerivBatch));
 }
 
 int pes_set_data(pes_ctx* c, const double* d, void* stream) {
@@ -516,29 +521,53 @@ int pes_response(pes_ctx* c, const double* theta, int64_t B, double* out, void* 
   return PES_OK;
 }
 
-int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* stream) {
-  if (!c || B < 0 || (B > 0 && (!theta || !logl)) || B > (int64_t(1) << 24)) return PES_EINVAL;
-  if (!c->has_data) return PES_ESTATE;
-  if (B == 0) return PES_OK;
-  int st = ensure_workspace(c, B);
-  if (st != PES_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// Device buffers one log-likelihood launch sequence works in.
+struct LoglikeWork {
+  double* wtab;
+  int* ntiles;
+  int* perm;
+  int* gstart;
+  int* counters;
+  double* partial;
+};
+
+// Items of the (walker group, tile) plan are int32 in the plan, the queue and
+// the ticket; a persistent grid of at most 16 blocks per CU takes one ticket
+// per block beyond the last item, so the bound keeps that headroom too.
+constexpr int64_t kMaxItems = int64_t(INT32_MAX) - 65536;
+
+int check_items(pes_ctx* c, int64_t B) {
+  const int64_t n_groups = (B + c->wg - 1) / c->wg;
+  if (n_groups * (int64_t)c->ntmax > kMaxItems) {
+    snprintf(c->err, sizeof(c->err), "%lld walker groups x %d tiles exceed the int32 work-item plan",
+             (long long)n_groups, c->ntmax);
+    return PES_ESHAPE;
+  }
+  return PES_OK;
+}
+
+// setup -> plan -> persistent log-likelihood kernel -> per-walker reduction
+int run_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, const LoglikeWork& ws,
+                hipStream_t s) {
   const bool grid_mode = c->schedule == PES_SCHED_GRID;
   const int64_t n_groups = (B + c->wg - 1) / c->wg;
-  if (grid_mode && n_groups * c->ntmax > INT32_MAX) return PES_ESHAPE;
   SetupArgs sa = setup_args(c);
   sa.full_tiles = grid_mode ? 1 : 0;
-  PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, sa, s));
-  PES_HIP(c, launch_plan(c->ntiles, (int)B, c->wg, c->ntmax, !grid_mode, c->perm, c->gstart, c->counters, s));
+  PES_HIP(c, launch_setup(theta, B, ws.wtab, ws.ntiles, sa, s));
+  PES_HIP(c, launch_plan(ws.ntiles, (int)B, c->wg, c->ntmax, !grid_mode, ws.perm, ws.gstart, ws.counters, s));
   LoglikeArgs a;
   a.bins = c->bins;
   a.tabs = c->tabs;
-  a.wtab = c->wtab;
-  a.ntiles = c->ntiles;
-  a.perm = c->perm;
-  a.gstart = c->gstart;
-  a.counters = c->counters;
-  a.partial = c->partial;
+  a.wtab = ws.wtab;
+  a.ntiles = ws.ntiles;
+  a.perm = ws.perm;
+  a.gstart = ws.gstart;
+  a.counters = ws.counters;
+  a.partial = ws.partial;
   a.N = c->N;
   a.B = (int)B;
   a.wg = c->wg;
@@ -560,8 +589,24 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
     PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev + 1], s));
     ++c->n_ev;
   }
-  PES_HIP(c, launch_finalize(c->partial, c->ntiles, c->wtab, c->dd, B, logl, s));
+  PES_HIP(c, launch_finalize(ws.partial, ws.ntiles, ws.wtab, c->dd, B, logl, s));
   return PES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* stream) {
+  if (!c || B < 0 || (B > 0 && (!theta || !logl)) || B > (int64_t(1) << 24)) return PES_EINVAL;
+  if (!c->has_data) return PES_ESTATE;
+  if (B == 0) return PES_OK;
+  int st = check_items(c, B);
+  if (st != PES_OK) return st;
+  st = ensure_workspace(c, B);
+  if (st != PES_OK) return st;
+  const LoglikeWork ws{c->wtab, c->ntiles, c->perm, c->gstart, c->counters, c->partial};
+  return run_loglike(c, theta, B, logl, ws, (hipStream_t)stream);
 }
 
 static JacArgs jac_args(const pes_ctx* c, int64_t B, int tile) {
@@ -579,7 +624,7 @@ static JacArgs jac_args(const pes_ctx* c, int64_t B, int tile) {
 }
 
 int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* grad, void* stream) {
-  if (!c || B < 0 || B > 65535 || (B > 0 && (!theta || !grad))) return PES_EINVAL;
+  if (!c || B < 0 || B > kMaxDerivBatch || (B > 0 && (!theta || !grad))) return PES_EINVAL;
   if (!c->has_data) return PES_ESTATE;
   if (B == 0) return PES_OK;
   int st = ensure_jac(c, B);
@@ -604,7 +649,7 @@ int pes_set_grad_method(pes_ctx* c, int method) {
 }
 
 int pes_fisher(pes_ctx* c, const double* theta, int64_t B, double* F, void* stream) {
-  if (!c || B < 0 || B > 65535 || (B > 0 && (!theta || !F))) return PES_EINVAL;
+  if (!c || B < 0 || B > kMaxDerivBatch || (B > 0 && (!theta || !F))) return PES_EINVAL;
   if (B == 0) return PES_OK;
   int st = ensure_jac(c, B);
   if (st != PES_OK) return st;
@@ -635,6 +680,10 @@ struct pes_sampler {
   double *zbuf = nullptr, *fprop = nullptr, *lq_prop = nullptr, *lq_cur = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // what the captured graph's kernels point into: the context's workspace and
+  // the flow's, at the generations current at capture
+  uint64_t cap_ws_gen = 0, cap_flow_gen = 0;
+  pes_flow* cap_flow = nullptr;
 };
 
 namespace {
@@ -758,7 +807,7 @@ int pes_sampler_create(pes_ctx* ctx, const pes_prior* prior, int64_t n_walkers, 
     delete s;
     return PES_ENOMEM;
   }
-  const int rc = pes_reserve(ctx, std::max(B, H));
+  const int rc = ensure_workspace(ctx, std::max(B, H));
   if (rc != PES_OK) {
     sampler_free(s);
     delete s;
@@ -837,12 +886,23 @@ int pes_sampler_capture(pes_sampler* s, void* stream) {
   PES_HIP(s->ctx, e);
   s->graph = g;
   PES_HIP(s->ctx, hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+  s->cap_ws_gen = s->ctx->ws_gen;
+  s->cap_flow = s->flow;
+  s->cap_flow_gen = s->flow ? flow_generation(s->flow) : 0;
   return PES_OK;
 }
 
 int pes_sampler_launch(pes_sampler* s, int64_t n_steps, void* stream) {
   if (!s || n_steps < 0) return PES_EINVAL;
   if (!s->exec) return PES_ESTATE;
+  // the graph holds raw pointers into workspaces that a larger call since the
+  // capture may have reallocated; replaying it then would touch freed memory
+  if (s->ctx->ws_gen != s->cap_ws_gen || s->flow != s->cap_flow ||
+      (s->flow && flow_generation(s->flow) != s->cap_flow_gen)) {
+    snprintf(s->ctx->err, sizeof(s->ctx->err),
+             "workspace reallocated or flow changed since the capture: capture the step again");
+    return PES_ESTATE;
+  }
   for (int64_t n = 0; n < n_steps; ++n) PES_HIP(s->ctx, hipGraphLaunch(s->exec, (hipStream_t)stream));
   return PES_OK;
 }

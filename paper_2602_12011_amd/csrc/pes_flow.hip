@@ -428,6 +428,7 @@ struct pes_flow {
   int64_t t_adam = 0;
   // workspace (rows padded to a multiple of 64)
   int64_t cap = 0;
+  uint64_t gen = 0;     // bumped whenever the workspace is reallocated
   float *x = nullptr, *logdet = nullptr, *xin = nullptr, *O = nullptr;
   __bf16 *Xc = nullptr, *H1 = nullptr, *H2 = nullptr;
   float *gy = nullptr, *gx = nullptr, *gOf = nullptr, *dpf = nullptr, *dXc = nullptr;
@@ -486,6 +487,7 @@ int ensure_ws(pes_flow* f, int64_t n) {
     return PES_ENOMEM;
   }
   f->cap = Mp;
+  ++f->gen;
   return PES_OK;
 }
 
@@ -718,6 +720,8 @@ bool cholesky(const double* C, double* L) {
 namespace pes {
 
 int flow_reserve(pes_flow* f, int64_t n) { return ensure_ws(f, n); }
+
+uint64_t flow_generation(const pes_flow* f) { return f->gen; }
 
 int flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double* logq, hipStream_t s) {
   if (n <= 0) return PES_OK;

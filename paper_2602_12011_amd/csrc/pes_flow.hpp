@@ -16,5 +16,8 @@ int flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double*
 int flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, double* logdet, hipStream_t s);
 // Makes the workspace hold n rows (allocates; not for use under capture).
 int flow_reserve(pes_flow* f, int64_t n);
+// Count of workspace reallocations: a captured graph that reads the workspace
+// is valid only while this is unchanged.
+uint64_t flow_generation(const pes_flow* f);
 
 }  // namespace pes

@@ -1,0 +1,215 @@
+"""The long-sinc kernel variants against the oracle, on grids that reach the
+paper's upper frequency (Sec. 3.2: rfftfreq bins of a 655360-s, 10-s series
+kept within [1e-4, 5e-2] Hz, the grid of Fig. fig_cost).
+
+Where 2 pi f_max L exceeds sqrt(4.9) (LISA above 42.2 mHz, Taiji above
+35.2 mHz) the context evaluates every kernel with the 11-term sinc fit and the
+cycle-reduced arm phases; wavefronts whose bins all have 2 pi f L <= 0.5 keep
+the short-range fits.  These cases put a non-vanishing signal on both sides of
+both boundaries:
+
+  pehm     LISA, five modes, 32703 bins, data h(theta_PE) + seeded Gaussian
+           noise drawn on the host from the oracle's PSD (so <d|h> is not zero
+           above the injection's cutoff), walkers around theta_PE and light
+           walkers from the prior whose modes reach 50 mHz;
+  penet    the same on the LISA + Taiji + TianQin network;
+  lisa_edge  LISA, five modes, 4141 bins straddling 2 pi f L = sqrt(4.9)
+           inside one 64-bin wavefront, injection at M_tot = 1e5 Msun and
+           D_L = 1 Gpc (its
+           (2,2) cutoff taper lies inside the grid, its (3,3) and (4,4) modes
+           cover it).
+
+Tolerances as in the other parity tests: log L to 1e-9 max(|L|, <d|d>/2);
+A/E/T to 1e-9 |h| + 1e-12 max|h| against the long-double oracle; gradients
+|dg_i| s_i <= 1e-6 max_j |g_j s_j|; Fisher |dF_ij| <= 1e-6 sqrt(F_ii F_jj).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2602_12011_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+C_LIGHT = 299792458.0
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pes():
+    from paper_2602_12011_amd import pes as P
+    return P
+
+
+def _edge_grid():
+    """LISA-only grid at the PE spacing whose bin 2070 + 20 sits just above
+    2 pi f L = sqrt(4.9): wavefront 32 (bins 2048..2111) holds both sides."""
+    df = 1.0 / W.PE_T
+    f_edge = math.sqrt(4.9) / (2 * math.pi * W.LISA["arm_m"] / C_LIGHT)
+    k_edge = math.floor(f_edge / df)
+    k0 = k_edge - 2070
+    return dict(detectors=[W.LISA], modes=W.MODES_HM, f0=k0 * df, df=df, n_bins=4096 + 45,
+                name="lisa_edge")
+
+
+def _theta_edge():
+    th = W.THETA_PE.copy()
+    th[0] = 1.0e5
+    th[1] = 0.7
+    th[4] = 1.0
+    return th
+
+
+CASES = {
+    "pehm": (lambda: W.config("pehm"), W.THETA_PE, True),
+    "penet": (lambda: W.config("penet"), W.THETA_PE, True),
+    "lisa_edge": (_edge_grid, _theta_edge(), False),
+}
+
+
+def _host_noise(orc, cfg, seed):
+    """Seeded stationary Gaussian noise: Re, Im ~ N(0, S_c/(4 df)) per bin and channel."""
+    rng = np.random.default_rng(seed)
+    f = cfg["f0"] + np.arange(cfg["n_bins"]) * cfg["df"]
+    n = np.zeros((len(cfg["detectors"]), 3, cfg["n_bins"]), dtype=np.complex128)
+    for d, det in enumerate(cfg["detectors"]):
+        SA, _, ST = orc.psd(det, f)
+        for c, S in enumerate((SA, SA, ST)):
+            sig = np.sqrt(np.where(S > 0, S, 0.0) / (4.0 * cfg["df"]))
+            n[d, c] = sig * (rng.standard_normal(f.size) + 1j * rng.standard_normal(f.size))
+    return n
+
+
+def _data(orc, name):
+    mk, th_inj, noisy = CASES[name]
+    cfg = mk()
+    d = orc.response(cfg, th_inj)
+    if noisy:
+        d = d + _host_noise(orc, cfg, 2602)
+    return cfg, th_inj, d
+
+
+def _walkers(name, th_inj, n_prior, stream):
+    """The injection, two points 1e-5 prior widths away, and prior draws of
+    which the first half are light (1e5 .. 3e5 Msun: modes up to 50 mHz)."""
+    rng = np.random.default_rng(stream)
+    s = W.prior_widths()
+    near = th_inj + 1e-5 * s * rng.standard_normal((2, 11))
+    near[:, 1] = np.minimum(near[:, 1], 1.0)
+    pri = W.draw_walkers(n_prior, stream=stream)
+    pri[: n_prior // 2, 0] = np.geomspace(1.0e5, 3.0e5, n_prior // 2)
+    if name == "lisa_edge":
+        pri[:, 0] = np.geomspace(1.0e5, 2.0e5, n_prior)
+    return np.vstack([th_inj, near, pri])
+
+
+def _long_sinc(cfg):
+    fmax = cfg["f0"] + (cfg["n_bins"] - 1) * cfg["df"]
+    return any((2 * math.pi * fmax * det["arm_m"] / C_LIGHT) ** 2 > 4.9 for det in cfg["detectors"])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_grids_take_the_long_sinc_path(name):
+    cfg = CASES[name][0]()
+    assert _long_sinc(cfg)
+    if name == "lisa_edge":
+        f = cfg["f0"] + np.arange(cfg["n_bins"]) * cfg["df"]
+        b2 = (2 * math.pi * f * W.LISA["arm_m"] / C_LIGHT) ** 2
+        wave = b2[2048:2112]
+        assert wave.min() < 4.9 < wave.max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_loglike_long_sinc(orc, torch_dev, pes, name):
+    torch = torch_dev
+    cfg, th_inj, d = _data(orc, name)
+    th = _walkers(name, th_inj, 12, stream=811)
+    print(f"[long-sinc] loglike {name}: n_bins={cfg['n_bins']} dets={len(cfg['detectors'])} B={len(th)}",
+          flush=True)
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(np.ascontiguousarray(d)).to("cuda"))
+    tht = torch.from_numpy(th).to("cuda")
+    Ls = []
+    for bpl, wg in ((1, 16), (2, 3)):
+        ctx.set_tuning(bpl, wg, 0)
+        Ls.append(ctx.loglike(tht).cpu().numpy())
+    ctx.close()
+    L_or = orc.loglike(cfg, d, th)
+    sigma = 0.5 * orc.inner(cfg, d, d)
+    for L in Ls:
+        err = np.abs(L - L_or)
+        bound = 1e-9 * np.maximum(np.abs(L_or), sigma)
+        w = int(np.argmax(err / bound))
+        assert np.all(err <= bound), (name, w, th[w].tolist(), L[w], L_or[w], err[w] / bound[w])
+    # the light walkers carry signal into the long-sinc bins: far from -<d|d>/2
+    assert np.all(np.abs(L_or + sigma) > 1e-6 * sigma)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_response_long_sinc(orc, torch_dev, pes, name):
+    torch = torch_dev
+    mk, th_inj, _ = CASES[name]
+    cfg = mk()
+    th = _walkers(name, th_inj, 4, stream=812)[[0, 3, 4]]   # injection and two light walkers
+    print(f"[long-sinc] response {name}: n_bins={cfg['n_bins']}", flush=True)
+    ctx = pes.Context(cfg)
+    out = ctx.response(torch.from_numpy(th).to("cuda")).cpu().numpy()
+    ctx.close()
+    h_gpu = out[..., 0] + 1j * out[..., 1]
+    f = cfg["f0"] + np.arange(cfg["n_bins"]) * cfg["df"]
+    for b in range(th.shape[0]):
+        h_or = orc.response(cfg, th[b], prec=1)
+        for det, dd in enumerate(cfg["detectors"]):
+            long_bins = (2 * math.pi * f * dd["arm_m"] / C_LIGHT) ** 2 > 4.9
+            ae = np.sqrt(np.abs(h_or[det, 0]) ** 2 + np.abs(h_or[det, 1]) ** 2)
+            for c in range(3):
+                ref = h_or[det, c]
+                tol = 1e-9 * np.abs(ref) + 1e-12 * np.abs(ref).max()
+                if c == 2:
+                    tol = tol + 1e-11 * ae
+                err = np.abs(h_gpu[b, det, c] - ref)
+                assert np.all(err <= tol), (name, b, det, c, float((err / tol).max()))
+            if b > 0 and np.any(long_bins) and dd["kind"] == "lisa":
+                # the light walkers' LISA signal is non-zero beyond sqrt(4.9)
+                assert np.abs(h_or[det, 0][long_bins]).max() > 0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_grad_fisher_long_sinc(orc, torch_dev, pes, name):
+    torch = torch_dev
+    cfg, th_inj, d = _data(orc, name)
+    th = _walkers(name, th_inj, 2, stream=813)[[1, 3, 4]]   # near the injection, two light walkers
+    if name == "penet":
+        th = th[:2]
+    print(f"[long-sinc] grad/fisher {name}: n_bins={cfg['n_bins']} B={len(th)}", flush=True)
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(np.ascontiguousarray(d)).to("cuda"))
+    tht = torch.from_numpy(th).to("cuda")
+    res = {}
+    for method in ("adjoint", "forward"):
+        ctx.set_grad_method(method)
+        L, g = ctx.grad(tht)
+        res[method] = (L.cpu().numpy(), g.cpu().numpy())
+    F = ctx.fisher(tht).cpu().numpy()
+    ctx.close()
+    L_or, g_or = orc.grad(cfg, d, th)
+    F_or = orc.fisher(cfg, th)
+    sigma = 0.5 * orc.inner(cfg, d, d)
+    s = W.prior_widths()
+    for method, (L, g) in res.items():
+        assert np.all(np.abs(L - L_or) <= 1e-9 * np.maximum(np.abs(L_or), sigma)), method
+        for b in range(th.shape[0]):
+            scale = np.abs(g_or[b] * s).max()
+            err = np.abs(g[b] - g_or[b]) * s
+            assert np.all(err <= 1e-6 * scale), (name, method, b, (err / scale).max())
+    for b in range(th.shape[0]):
+        dg = np.sqrt(np.outer(np.diag(F_or[b]), np.diag(F_or[b])))
+        err = np.abs(F[b] - F_or[b]) / dg
+        assert np.all(err <= 1e-6), (name, b, err.max(), np.unravel_index(err.argmax(), err.shape))

@@ -181,21 +181,29 @@ def test_gpu_injection_data_gives_zero_at_theta0(orc, torch_dev, pes):
 @pytest.mark.parametrize("name", ["cfg1", "cfg2"])
 def test_full_size_sampled(orc, torch_dev, pes, name):
     """The benchmark's launch (all walkers of the workload, 2^20 bins) checked
-    on a sample of walkers that the oracle evaluates one by one."""
+    on a sample of walkers that the oracle evaluates one by one: 64 walkers at
+    evenly spaced ranks of the mass order (the order in which the plan groups
+    them, lightest = most tiles first), including both ends.  Run at the
+    default tuning and at 24 walkers per item, whose last group is partial
+    (4096 = 170 x 24 + 16, 16384 = 682 x 24 + 16), two bins per lane."""
     torch = torch_dev
     cfg = _cfg(name)
     B = cfg["walkers"]
-    n_check = 6 if name == "cfg1" else 3
     print(f"[parity] full-size {name}: B={B} n_bins={cfg['n_bins']}", flush=True)
     d = orc.response(cfg, W.THETA0)
     th = W.draw_walkers(B, stream=1)
-    L = _run_loglike(torch, pes, cfg, d, th)
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(d).to("cuda"))
+    tht = torch.from_numpy(th).to("cuda")
+    L = ctx.loglike(tht).cpu().numpy()
+    ctx.set_tuning(2, 24, 0)
+    L24 = ctx.loglike(tht).cpu().numpy()
+    ctx.close()
     assert np.all(np.isfinite(L)) and np.all(L <= 0)
-    rng = np.random.default_rng(5)
-    # the heaviest (shortest) and lightest (longest) walkers plus random ones
-    idx = np.unique(np.concatenate([[np.argmin(th[:, 0]), np.argmax(th[:, 0])],
-                                    rng.choice(B, n_check, replace=False)]))
+    order = np.argsort(th[:, 0], kind="stable")
+    idx = np.unique(order[np.linspace(0, B - 1, 64).round().astype(int)])
     _check_loglike(orc, cfg, d, L[idx], th[idx], f"{name} sampled")
+    _check_loglike(orc, cfg, d, L24[idx], th[idx], f"{name} sampled, 24 walkers per item")
 
 
 @pytest.mark.parametrize("bpl", [1, 2])
@@ -247,4 +255,23 @@ def test_plain_grid_schedule_is_bitwise_the_queue(orc, torch_dev, pes):
         assert np.array_equal(Lq, Lg), (bpl, wg)
         assert np.isneginf(Lg[7])
     _check_loglike(orc, cfg, d, Lg, th, "plain grid")
+    ctx.close()
+
+
+def test_work_item_bound(torch_dev, pes):
+    """The (walker group, tile) plan is int32: a batch whose item count would
+    exceed it is refused with PES_ESHAPE before any work is queued, under both
+    schedules; a larger walkers-per-item tuning brings it back within range."""
+    torch = torch_dev
+    cfg = _cfg("cfg1", n_bins=1 << 22)          # 16384 tiles of 256 bins
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.zeros((1, 3, cfg["n_bins"], 2), dtype=torch.float64, device="cuda"))
+    B = (1 << 17) + 1                           # 131073 groups of one walker
+    th = torch.from_numpy(W.draw_walkers(B, stream=95)).to("cuda")
+    out = torch.empty(B, dtype=torch.float64, device="cuda")
+    for sched in ("queue", "grid"):
+        ctx.set_schedule(sched)
+        ctx.set_tuning(1, 1, 0)
+        rc = pes.lib().pes_loglike(ctx.h, pes._dev_f64(th, "theta"), B, pes._dev_f64(out, "logl"), None)
+        assert rc == -2, (sched, rc)
     ctx.close()

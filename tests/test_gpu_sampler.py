@@ -199,3 +199,43 @@ def test_checkpoint_resume_is_bitwise(orc, torch_dev, pes):
     ctx.close()
     assert nm == 3 and na == nc == 6
     assert torch.equal(ta, tc) and torch.equal(La, Lc)
+
+
+def test_graph_refuses_replay_after_workspace_growth(orc, torch_dev, pes):
+    """A captured step points into the context's workspace; a larger call on
+    the context reallocates it, after which the replay is refused (PES_ESTATE)
+    until the step is captured again, and the new capture replays bitwise like
+    the eager steps."""
+    torch = torch_dev
+    cfg = W.config("cfg0")
+    d = orc.response(cfg, W.THETA0)
+    prior = _prior_spec(W.PARAM_NAMES)
+    rng = np.random.default_rng(10)
+    th0 = W.THETA0 + 1e-5 * W.prior_widths() * rng.normal(size=(64, 11))
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(d).to("cuda"))
+    a = pes.Sampler(ctx, prior, 64, 78)
+    b = pes.Sampler(ctx, prior, 64, 78)
+    a.set_state(torch.from_numpy(th0).to("cuda"))
+    b.set_state(torch.from_numpy(th0).to("cuda"))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.capture(s)
+    ctx.loglike(torch.from_numpy(W.draw_walkers(500, stream=90)).to("cuda"))   # grows the workspace
+    torch.cuda.synchronize()
+    rc = pes.lib().pes_sampler_launch(b.h, 1, pes._stream(s))
+    assert rc == -5, rc                                                   # PES_ESTATE, nothing launched
+    with torch.cuda.stream(s):
+        b.capture(s)
+    a.step(3)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.launch(1, s)
+        s.synchronize()
+    ta, La, aa, na = a.state()
+    tb, Lb, ab, nb = b.state(s)
+    assert na == nb == 3
+    assert torch.equal(ta, tb) and torch.equal(La, Lb) and torch.equal(aa, ab)
+    a.close()
+    b.close()
+    ctx.close()
