@@ -21,8 +21,11 @@
 // bin, -1/2 sum 4 df |d - h|^2 / S.
 //
 // Parity unpinned (shared stated conventions, nothing in the paper to check
-// them against): the post-Newtonian stand-in for the PhenomX waveform
-// coefficients, the PSD shaping functions, the TianQin plane orientation.
+// them against): the literature values of the leading mode factors |H_lm| and
+// their arguments, the constant part of psi_5 (a constant phase), the quintic
+// shape of the taper between its C^2 joins, the PSD shaping functions, the
+// TianQin plane orientation.  The phase coefficients, the SPA mode and
+// polarization construction and the taper joins are pinned by the tests.
 
 #include "oracle.h"
 

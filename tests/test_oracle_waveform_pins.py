@@ -95,3 +95,158 @@ def test_newtonian_chirp_time(orc):
     resid = dev - (c2 * v ** 2 + c3 * v ** 3)
     assert np.all(np.abs(resid) < 100 * v ** 4)
     assert np.all(np.abs(dev) > 1e-4)
+
+
+EULER_GAMMA = 0.5772156649015328606
+
+
+def _taylor_t2_bracket(v, eta, q, chi1, chi2):
+    """The bracket of the published TaylorT2 time-to-coalescence series,
+    t(v) = t_c - 5 M / (256 eta v^8) [1 + tau_2 v^2 + ... + tau_7 v^7], 3.5PN
+    non-spinning (Blanchet, Living Rev. Relativ. 17, 2 (2014)) with the 1.5PN
+    spin-orbit term written through beta = (1/12) sum_i chi_i (113 (m_i/M)^2 +
+    75 eta) and the 2PN spin-spin term through sigma = eta (721 chi1 chi2 -
+    247 chi1 chi2) / 48 for spins along the orbital angular momentum."""
+    m1, m2 = 1.0 / (1.0 + q), q / (1.0 + q)
+    beta = (chi1 * (113 * m1 * m1 + 75 * eta) + chi2 * (113 * m2 * m2 + 75 * eta)) / 12.0
+    sigma = eta * (721.0 / 48.0 * chi1 * chi2 - 247.0 / 48.0 * chi1 * chi2)
+    pi = math.pi
+    t2 = 743 / 252 + 11 / 3 * eta
+    t3 = -32 / 5 * pi + 8 / 5 * beta
+    t4 = 3058673 / 508032 + 5429 / 504 * eta + 617 / 72 * eta ** 2 - 2 * sigma
+    t5 = (-7729 / 252 + 13 / 3 * eta) * pi
+    t6 = (-10052469856691 / 23471078400 + 128 / 3 * pi ** 2 + 6848 / 105 * EULER_GAMMA
+          + (3147553127 / 3048192 - 451 / 12 * pi ** 2) * eta - 15211 / 1728 * eta ** 2
+          + 25565 / 1296 * eta ** 3 + 3424 / 105 * np.log(16 * v * v))
+    t7 = (-15419335 / 127008 - 75703 / 756 * eta + 14809 / 378 * eta ** 2) * pi
+    return 1 + t2 * v ** 2 + t3 * v ** 3 + t4 * v ** 4 + t5 * v ** 5 + t6 * v ** 6 + t7 * v ** 7
+
+
+@pytest.mark.parametrize("Mtot,q,chi1,chi2", [(1e6, 0.5, 0.2, 0.1), (1e5, 0.15, -0.8, 0.7),
+                                              (3e6, 1.0, 0.9, 0.9), (2e7, 0.3, 0.0, -0.5),
+                                              (4e5, 0.8, 0.6, -0.6)])
+def test_chirp_time_is_taylor_t2_through_35pn(orc, Mtot, q, chi1, chi2):
+    """Under the SPA, t_f of the (2,2) mode is the TaylorT2 time at v =
+    (pi M f)^{1/3} (eq. eq_tf with Psi = 2 pi f t - 2 phi - pi/4).  The oracle
+    derives t_f from its own phase coefficients psi_2..psi_7 and spin terms;
+    the published TaylorT2 series is a separately printed expansion in another
+    algebraic form (mass-weighted beta, sigma), so a slip in any coefficient,
+    the log terms or the spin combinations fails here.  Both are truncations
+    of the same series, equal to rounding at every v up to the cutoff."""
+    th = _theta(M_tot=Mtot, q=q, chi1=chi1, chi2=chi2, t_c=0.0)
+    M = Mtot * MSUN_S
+    eta = q / (1 + q) ** 2
+    fcut = 6 ** -1.5 / math.pi / M
+    f = np.geomspace(1e-3 * fcut, 0.85 * fcut, 12)
+    _, _, tf = orc.mode(th, 2, 2, f)
+    v = (math.pi * M * f) ** (1 / 3)
+    ref = -5 * M / (256 * eta * v ** 8) * _taylor_t2_bracket(v, eta, q, chi1, chi2)
+    np.testing.assert_allclose(tf, ref, rtol=1e-11, atol=0)
+
+
+def _taper_from_amplitude(orc, th, x):
+    """W(x) read off the oracle's (2,2) amplitude: |h(f)| / (|h(f_r)| (f/f_r)^{-7/6})
+    at x = f / f_cut, f_r = 0.5 f_cut (the restricted amplitude is a pure power law)."""
+    M = th[0] * MSUN_S
+    fcut = 6 ** -1.5 / math.pi / M
+    f = np.atleast_1d(x) * fcut
+    h, _, _ = orc.mode(th, 2, 2, f)
+    hr, _, _ = orc.mode(th, 2, 2, np.array([0.5 * fcut]))
+    return np.abs(h) / (np.abs(hr[0]) * (f / (0.5 * fcut)) ** (-7 / 6))
+
+
+def test_taper_joins_are_c2(orc):
+    """The cutoff taper is 1 below 0.9 f_cut and 0 above f_cut, monotone in
+    between, and joins both ends with matching value, first and second
+    derivative: 1 - W(0.9 + e) and W(1 - e) fall as e^3 (a C^1 join would
+    fall as e^2), so the second finite difference at each join vanishes
+    linearly in the step."""
+    th = _theta(q=0.6)
+    x = np.linspace(0.5, 0.9, 9)
+    np.testing.assert_allclose(_taper_from_amplitude(orc, th, x), 1.0, rtol=0, atol=1e-13)
+    assert np.all(_taper_from_amplitude(orc, th, np.array([1.0, 1.001, 1.2])) == 0.0)
+    xs = np.linspace(0.9, 1.0, 201)
+    W_ = _taper_from_amplitude(orc, th, xs)
+    assert np.all(np.diff(W_) <= 1e-15)
+    for eps in (1e-3, 5e-4):
+        lo = 1 - _taper_from_amplitude(orc, th, np.array([0.9 + eps, 0.9 + eps / 2]))
+        hi = _taper_from_amplitude(orc, th, np.array([1 - eps, 1 - eps / 2]))
+        assert lo[0] / lo[1] == pytest.approx(8.0, rel=0.01)
+        assert hi[0] / hi[1] == pytest.approx(8.0, rel=0.01)
+    for x0, sgn in ((0.9, 1.0), (1.0, -1.0)):
+        d2 = []
+        for eps in (2e-3, 1e-3):
+            w3 = _taper_from_amplitude(orc, th, x0 + sgn * eps * np.array([0.0, 1.0, 2.0]))
+            d2.append((w3[2] - 2 * w3[1] + w3[0]) / eps ** 2)
+        # C^2: the second difference over [x0, x0 + 2e] is W'' near x0 + e, which
+        # falls linearly with e; a C^1-only join keeps a jump of order 1/0.1^2
+        assert d2[1] / d2[0] == pytest.approx(0.5, rel=0.05)
+
+
+def _hlm_leading(l, m, v, eta, delta):
+    """Leading post-Newtonian mode factors H_lm of h_lm = (2 M eta x / D)
+    sqrt(16 pi / 5) H_lm e^{-i m phi} (Blanchet 2014; Kidder 2008)."""
+    if (l, m) == (2, 2):
+        return np.ones_like(v) + 0j
+    if (l, m) == (2, 1):
+        return 1j * delta * v / 3
+    if (l, m) == (3, 3):
+        return -0.75j * math.sqrt(15 / 14) * delta * v
+    if (l, m) == (3, 2):
+        return math.sqrt(5 / 7) / 3 * (1 - 3 * eta) * v * v + 0j
+    return -8 / 9 * math.sqrt(5 / 7) * (1 - 3 * eta) * v * v + 0j
+
+
+@pytest.mark.parametrize("F0", [8e-5, 1.4e-4])
+def test_spa_modes_against_numerical_fourier_transform(orc, F0):
+    """The SPA construction of the frequency-domain modes and polarizations
+    against a direct Fourier transform of time-domain signals.
+
+    The time-domain modes are h_lm(t) = (2 M eta x / D) sqrt(16 pi/5) H_lm
+    e^{-i m phi(t)}, x = (2 pi M F)^{2/3}, h_{l,-m} = (-1)^l conj(h_lm), and
+    h_+ - i h_x = h_lm Y_lm + h_{l,-m} Y_{l,-m} for one mode pair.  The orbit
+    (phi, t as functions of the orbital frequency F) is the oracle's own (2,2)
+    phasing, phi = (2 pi 2F t - Psi_22 - pi/4) / 2, t = t_f^{22}(2F).  The real
+    h_+(t), h_x(t) are windowed around F0 and transformed numerically
+    (trapezoid rule in t, e^{-2 pi i f t}) at f = m F0, the frequency whose
+    stationary point is that orbital frequency.  This pins, per mode, the
+    mode-phase scaling, the -pi/4, the sqrt(2/m) and the amplitude
+    normalization of the SPA, and the conjugation rules of the plus/cross
+    projections.  The oracle's amplitude is the restricted one (leading-order
+    chirp rate), the transform's follows the full phasing: their ratio is
+    sqrt(Fdot_Newton / Fdot), the same for every mode, with Fdot = 1 / (dt/dF)
+    from the oracle's t_f and Fdot_Newton = (96/5) eta M^{5/3} (2 pi F)^{11/3} / (2 pi)."""
+    th = np.array([2e5, 0.5, 0.3, -0.2, 1.0, 0.7, 0.4, 1.0, 0.2, 0.5, 0.0])
+    M = th[0] * MSUN_S
+    q = th[1]
+    eta, delta = q / (1 + q) ** 2, (1 - q) / (1 + q)
+    D = th[4] * GPC_S
+    w = 0.15
+    u = np.linspace((F0 * (1 - w)) ** (-8 / 3), (F0 * (1 + w)) ** (-8 / 3), 600000)
+    F = u ** (-3 / 8)                         # t nearly uniform along the chirp
+    _, psi22, t = orc.mode(th, 2, 2, 2 * F)
+    phi = (2 * math.pi * 2 * F * t - psi22 - math.pi / 4) / 2
+    x = np.abs(F - F0) / (w * F0)
+    win = np.where(x <= 0.5, 1.0, np.cos(math.pi * (x - 0.5)) ** 2)
+    h = 1e-5 * F0
+    _, _, tpm = orc.mode(th, 2, 2, np.array([2 * (F0 + h), 2 * (F0 - h)]))
+    fdot = 2 * h / (tpm[0] - tpm[1])
+    fdot_n = 96 / 5 * eta * M ** (5 / 3) * (2 * math.pi * F0) ** (11 / 3) / (2 * math.pi)
+    R = math.sqrt(fdot_n / fdot)
+    v = (2 * math.pi * M * F) ** (1 / 3)
+    dt = np.diff(t)
+    for (l, m) in W.MODES_HM:
+        H = _hlm_leading(l, m, v, eta, delta)
+        hlm = 2 * M * eta * v * v / D * math.sqrt(16 * math.pi / 5) * H * np.exp(-1j * m * phi)
+        hlmm = (-1) ** l * np.conj(hlm)
+        S = hlm * orc.ylm(l, m, th[5]) + hlmm * orc.ylm(l, -m, th[5])
+        e = win * np.exp(-2j * math.pi * m * F0 * t)
+        g_p, g_c = S.real * e, -S.imag * e
+        I_p = np.sum(0.5 * (g_p[1:] + g_p[:-1]) * dt)
+        I_c = np.sum(0.5 * (g_c[1:] + g_c[:-1]) * dt)
+        ho, _, _ = orc.mode(th, l, m, np.array([m * F0]))
+        Kp, Kc = orc.pol_coeffs(l, m, th[5])
+        for I, K in ((I_p, Kp), (I_c, Kc)):
+            r = I / (K * ho[0])
+            assert abs(abs(r) / R - 1) < 1e-4, ((l, m), abs(r) / R - 1)
+            assert abs(np.angle(r)) < 1e-4, ((l, m), np.angle(r))
