@@ -284,6 +284,23 @@ int pes_flow_set_temperature(pes_flow* f, double tau);
 int pes_flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double* logq, void* stream);
 /* theta = inverse map of tau z, z (dev) [n][11]; logdet (dev) [n] or NULL: sum s at theta. */
 int pes_flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, double* logdet, void* stream);
+/* Test entry point: pes_flow_forward (inverse = 0: in = theta, out = z, lq =
+ * logq) or pes_flow_inverse (inverse = 1: in = z, out = theta, lq = logdet or
+ * NULL) through the same kernels, that also writes the FP32 coupling state of
+ * the n rows before the first layer and after every layer, in the order the
+ * layers are applied, to states (dev) FP32 [9][n][11] (slot 0: the
+ * standardized u, or the latent tau z), and the running sum of s at the same
+ * points to logdet (dev) FP32 [9][n].  Slot 8 holds z (forward) or u
+ * (inverse).  acts (dev) FP32 [8][n][576] or NULL receives, for layer l (by
+ * its index, not the order applied), the conditioner's stages as the matrix
+ * cores saw them: columns 0..31 the BF16 input x_C (zero padded), 32..287 and
+ * 288..543 the two BF16 hidden layers, 544..575 the FP32 output (s_hat, t,
+ * zero padded).  Each rounding decision and each layer's map can so be checked
+ * on the values the library itself fed it (the affine coupling of Dinh et al.
+ * 2017, the proposal's definition above).  PES_EINVAL for a null pointer with
+ * n > 0. */
+int pes_flow_probe(pes_flow* f, const double* in, int64_t n, int inverse, double* out, double* lq,
+                   float* states, float* logdet, float* acts, void* stream);
 /* Mean negative log-likelihood of the rows of theta (dev) [n][11] in the
  * standardized space, -(1/n) sum log q_u(u_j), into nll (dev) [1] (may be
  * NULL), and its gradient into grad (dev) FP32 [pes_flow_num_params()]. */

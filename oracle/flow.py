@@ -107,52 +107,116 @@ def init_params(seed, scale_out=0.0):
     return flat
 
 
+def _weights(p, k, rnd):
+    """W_k (BF16-rounded with rnd) and b_k of a layer's parameter dict, FP64."""
+    W = p["W%d" % k]
+    W = bf16(W) if rnd else np.asarray(W, dtype=np.float64)
+    return W, np.asarray(p["b%d" % k], dtype=np.float64)
+
+
+def _dense(p, k, a, rnd):
+    """a W_k + b_k and |a| |W_k| + |b_k| (the scale of the sum's rounding error
+    in any accumulation order)."""
+    W, b = _weights(p, k, rnd)
+    a = np.asarray(a, dtype=np.float64)
+    return a @ W + b, np.abs(a) @ np.abs(W) + np.abs(b)
+
+
+def dense(flat, l, k, a, rnd=True):
+    """Product k (1, 2 or 3) of layer l's conditioner on its input rows a."""
+    return _dense(unflatten(np.asarray(flat))[l], k, a, rnd)
+
+
 def _net(p, xc, rnd):
     """Conditioner forward; returns (s, t, cache)."""
     r = bf16 if rnd else (lambda a: np.asarray(a, dtype=np.float64))
-    W1, W2, W3 = (r(p[k]) for k in ("W1", "W2", "W3"))
-    b1, b2, b3 = (np.asarray(p[k], dtype=np.float64) for k in ("b1", "b2", "b3"))
     a0 = r(xc)
-    a1 = r(np.maximum(a0 @ W1 + b1, 0.0))
-    a2 = r(np.maximum(a1 @ W2 + b2, 0.0))
-    o = a2 @ W3 + b3
+    a1 = r(np.maximum(_dense(p, 1, a0, rnd)[0], 0.0))
+    a2 = r(np.maximum(_dense(p, 2, a1, rnd)[0], 0.0))
+    o = _dense(p, 3, a2, rnd)[0]
     nt = o.shape[1] // 2
     th = np.tanh(o[:, :nt] / S_MAX)
     s = S_MAX * th
     t = o[:, nt:]
-    return s, t, (a0, a1, a2, W1, W2, W3, th)
+    W1, W2, W3 = (_weights(p, k, rnd)[0] for k in (1, 2, 3))
+    return s, t, (a0, a1, a2, W1, W2, W3, th, o)
+
+
+def coupling(l, x, o, inverse=False):
+    """Affine update of layer l on the rows x given its conditioner output o
+    [n, 2 n_T] = (s_hat, t): s = 3 tanh(s_hat / 3); normalizing y_T = x_T e^s + t,
+    inverse x_T = (y_T - t) e^-s.  Returns (new rows, sum of s per row)."""
+    T = trans_set(l)
+    nt = len(T)
+    s = S_MAX * np.tanh(np.asarray(o[:, :nt], dtype=np.float64) / S_MAX)
+    t = np.asarray(o[:, nt:2 * nt], dtype=np.float64)
+    y = np.array(x, dtype=np.float64)
+    y[:, T] = (y[:, T] - t) * np.exp(-s) if inverse else y[:, T] * np.exp(s) + t
+    return y, s.sum(axis=1)
+
+
+def layer(flat, l, x, inverse=False, rnd=True):
+    """One coupling layer l on the rows x [n, 11]; returns (new rows, sum of s
+    per row)."""
+    p = unflatten(np.asarray(flat))[l]
+    x = np.asarray(x, dtype=np.float64)
+    *_, cache = _net(p, x[:, cond_set(l)], rnd)
+    return coupling(l, x, cache[-1], inverse)
+
+
+def layer_order(inverse=False):
+    """Layers in the order a pass applies them."""
+    return list(reversed(range(N_LAYERS))) if inverse else list(range(N_LAYERS))
+
+
+def trace(flat, x0, inverse=False, rnd=True):
+    """A pass with its intermediates: the rows before the first layer and after
+    each layer in the order applied (states [9, n, 11]), the running sum of s at
+    the same points ([9, n]), and for each layer l (by index) its conditioner
+    stages a0, a1, a2 (network input and the two hidden layers, BF16-rounded
+    with rnd) and o (output)."""
+    layers = unflatten(np.asarray(flat))
+    x = np.array(x0, dtype=np.float64)
+    st, ld = [x.copy()], [np.zeros(x.shape[0])]
+    acts = [None] * N_LAYERS
+    for l in layer_order(inverse):
+        *_, cache = _net(layers[l], x[:, cond_set(l)], rnd)
+        acts[l] = dict(a0=cache[0], a1=cache[1], a2=cache[2], o=cache[-1])
+        x, s = coupling(l, x, cache[-1], inverse)
+        st.append(x.copy())
+        ld.append(ld[-1] + s)
+    return np.stack(st), np.stack(ld), acts
+
+
+def states(flat, x0, inverse=False, rnd=True):
+    """(states [9, n, 11], running sum of s [9, n]) of a pass (see trace)."""
+    st, ld, _ = trace(flat, x0, inverse, rnd)
+    return st, ld
 
 
 def forward(flat, u, rnd=True):
     """Normalizing direction: u [n, 11] -> (z [n, 11], log det [n])."""
-    layers = unflatten(np.asarray(flat))
-    x = np.array(u, dtype=np.float64)
-    logdet = np.zeros(x.shape[0])
-    for l, p in enumerate(layers):
-        C, T = cond_set(l), trans_set(l)
-        s, t, _ = _net(p, x[:, C], rnd)
-        x[:, T] = x[:, T] * np.exp(s) + t
-        logdet += s.sum(axis=1)
-    return x, logdet
+    st, ld = states(flat, u, False, rnd)
+    return st[-1], ld[-1]
 
 
 def inverse(flat, z, rnd=True):
     """Generative direction: z -> (u, log det of the normalizing map at u)."""
-    layers = unflatten(np.asarray(flat))
-    x = np.array(z, dtype=np.float64)
-    logdet = np.zeros(x.shape[0])
-    for l in reversed(range(N_LAYERS)):
-        C, T = cond_set(l), trans_set(l)
-        s, t, _ = _net(layers[l], x[:, C], rnd)
-        x[:, T] = (x[:, T] - t) * np.exp(-s)
-        logdet += s.sum(axis=1)
-    return x, logdet
+    st, ld = states(flat, z, True, rnd)
+    return st[-1], ld[-1]
+
+
+def log_base(z, logdet, tau=1.0):
+    """log q_u from the latent rows z and the normalizing map's log det:
+    log N(z; 0, tau^2 I) + log det."""
+    z = np.asarray(z, dtype=np.float64)
+    return (-0.5 * (z * z).sum(axis=1) / (tau * tau) - D * math.log(tau)
+            - 0.5 * D * math.log(2.0 * math.pi) + np.asarray(logdet, dtype=np.float64))
 
 
 def log_prob_u(flat, u, rnd=True, tau=1.0):
     z, ld = forward(flat, u, rnd)
-    return (-0.5 * (z * z).sum(axis=1) / (tau * tau) - D * math.log(tau)
-            - 0.5 * D * math.log(2.0 * math.pi) + ld)
+    return log_base(z, ld, tau)
 
 
 def whitening(sigma):
@@ -207,7 +271,7 @@ def nll_and_grad(flat, u, weight=None, rnd=True):
     gld = -w                                 # d NLL / d log det
     for l in reversed(range(N_LAYERS)):
         C, T = cond_set(l), trans_set(l)
-        xin, s, (a0, a1, a2, W1, W2, W3, th) = tape[l]
+        xin, s, (a0, a1, a2, W1, W2, W3, th, _) = tape[l]
         es = np.exp(s)
         gyT = gy[:, T]
         gx = gy.copy()

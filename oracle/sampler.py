@@ -147,6 +147,7 @@ class DESampler:
                     z.append(math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2))
                 take.append(j)
                 zs.append(z)
+        self.last_latent = (np.array(take, dtype=np.int64), np.array(zs).reshape(-1, 11))
         if not take:
             return props, qratio
         take = np.array(take)

@@ -244,6 +244,39 @@ __global__ void unstandardize_kernel(const float* __restrict__ x, const float* _
   if (ld_out) ld_out[j] = (double)logdet[j];
 }
 
+// Probe hook: the coupling state and running log-determinant of the first n
+// rows into slot k of states [kLayers + 1][n][11] and logdet [kLayers + 1][n].
+__global__ void copy_state_kernel(const float* __restrict__ x, const float* __restrict__ logdet, int64_t n, int k,
+                                  float* __restrict__ states, float* __restrict__ ld_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * kD) return;
+  states[(int64_t)k * n * kD + i] = x[i];
+  if (i % kD == 0) ld_out[(int64_t)k * n + i / kD] = logdet[i / kD];
+}
+
+// Probe: the conditioner stages of every layer (slot l of the stored
+// activations) into acts [kLayers][n][kActCols] as FP32: the BF16 input
+// (kPad columns), the two BF16 hidden layers (kHid each), the FP32 output
+// (kPad columns).
+constexpr int kActCols = kPad + kHid + kHid + kPad;
+
+__global__ void copy_acts_kernel(const __bf16* __restrict__ Xc, const __bf16* __restrict__ H1,
+                                 const __bf16* __restrict__ H2, const float* __restrict__ O, int64_t Mp, int64_t n,
+                                 float* __restrict__ acts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)kLayers * n * kActCols) return;
+  const int c = (int)(i % kActCols);
+  const int64_t r = i / kActCols;        // l * n + row
+  const int64_t l = r / n, j = r - l * n;
+  const int64_t so = l * Mp + j;
+  float v;
+  if (c < kPad) v = (float)Xc[so * kPad + c];
+  else if (c < kPad + kHid) v = (float)H1[so * kHid + (c - kPad)];
+  else if (c < kPad + 2 * kHid) v = (float)H2[so * kHid + (c - kPad - kHid)];
+  else v = O[so * kPad + (c - kPad - 2 * kHid)];
+  acts[i] = v;
+}
+
 // ------------------------------------------------------------------ training
 // Seeds the backward pass of NLL = (1/n) sum_j (|z_j|^2/2 + 11/2 log 2 pi - logdet_j):
 // dNLL/dz = z / n, and the per-row NLL terms.
@@ -524,27 +557,62 @@ int net_forward(pes_flow* f, int l, int64_t Mp, int slot, hipStream_t s) {
 
 // Normalizing pass over f->x (standardized rows); store: keep every layer's
 // input and activations for the backward pass.
-int pass_forward(pes_flow* f, int64_t Mp, bool store, hipStream_t s) {
+// Where a probe call wants the state after every layer (null on every other path).
+struct StateProbe {
+  int64_t n;
+  float* states;
+  float* logdet;
+  float* acts;    // may be null
+};
+
+int probe_state(pes_flow* f, const StateProbe* pr, int k, hipStream_t s) {
+  if (!pr) return PES_OK;
+  hipLaunchKernelGGL(copy_state_kernel, dim3(nblk(pr->n * kD, 256)), dim3(256), 0, s, f->x, f->logdet, pr->n, k,
+                     pr->states, pr->logdet);
+  FL_HIP(f, hipGetLastError());
+  return PES_OK;
+}
+
+int probe_acts(pes_flow* f, const StateProbe* pr, int64_t Mp, hipStream_t s);
+
+int pass_forward(pes_flow* f, int64_t Mp, bool store, hipStream_t s, const StateProbe* pr = nullptr) {
+  int rc = probe_state(f, pr, 0, s);
+  if (rc != PES_OK) return rc;
   for (int l = 0; l < kLayers; ++l) {
-    const int slot = store ? l : 0;
-    int rc = net_forward(f, l, Mp, slot, s);
+    const int slot = store || pr ? l : 0;    // a probe keeps every layer's activations
+    rc = net_forward(f, l, Mp, slot, s);
     if (rc != PES_OK) return rc;
     hipLaunchKernelGGL(couple_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, f->x, f->O + (int64_t)slot * Mp * kPad,
                        f->logdet, store ? f->xin + (int64_t)l * Mp * kD : nullptr, Mp, f->L[l], 0);
     FL_HIP(f, hipGetLastError());
+    rc = probe_state(f, pr, l + 1, s);
+    if (rc != PES_OK) return rc;
   }
+  return probe_acts(f, pr, Mp, s);
+}
+
+int probe_acts(pes_flow* f, const StateProbe* pr, int64_t Mp, hipStream_t s) {
+  if (!pr || !pr->acts) return PES_OK;
+  hipLaunchKernelGGL(copy_acts_kernel, dim3(nblk((int64_t)kLayers * pr->n * kActCols, 256)), dim3(256), 0, s, f->Xc,
+                     f->H1, f->H2, f->O, Mp, pr->n, pr->acts);
+  FL_HIP(f, hipGetLastError());
   return PES_OK;
 }
 
-int pass_inverse(pes_flow* f, int64_t Mp, hipStream_t s) {
+int pass_inverse(pes_flow* f, int64_t Mp, hipStream_t s, const StateProbe* pr = nullptr) {
+  int rc = probe_state(f, pr, 0, s);
+  if (rc != PES_OK) return rc;
   for (int l = kLayers - 1; l >= 0; --l) {
-    int rc = net_forward(f, l, Mp, 0, s);
+    const int slot = pr ? l : 0;    // a probe keeps every layer's activations
+    rc = net_forward(f, l, Mp, slot, s);
     if (rc != PES_OK) return rc;
-    hipLaunchKernelGGL(couple_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, f->x, f->O, f->logdet,
-                       (float*)nullptr, Mp, f->L[l], 1);
+    hipLaunchKernelGGL(couple_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, f->x, f->O + (int64_t)slot * Mp * kPad,
+                       f->logdet, (float*)nullptr, Mp, f->L[l], 1);
     FL_HIP(f, hipGetLastError());
+    rc = probe_state(f, pr, kLayers - l, s);
+    if (rc != PES_OK) return rc;
   }
-  return PES_OK;
+  return probe_acts(f, pr, Mp, s);
 }
 
 // Backward of the mean NLL over the first n rows after pass_forward(store):
@@ -723,14 +791,15 @@ int flow_reserve(pes_flow* f, int64_t n) { return ensure_ws(f, n); }
 
 uint64_t flow_generation(const pes_flow* f) { return f->gen; }
 
-int flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double* logq, hipStream_t s) {
+int flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double* logq, hipStream_t s,
+                 const StateProbe* pr) {
   if (n <= 0) return PES_OK;
   const int64_t Mp = pad_rows(n);
   if (Mp > f->cap) return PES_ESTATE;
   hipLaunchKernelGGL(standardize_kernel, dim3(nblk(Mp, 256)), dim3(256), 0, s, theta, n, Mp, f->nm, f->x,
                      f->logdet);
   FL_HIP(f, hipGetLastError());
-  int rc = pass_forward(f, Mp, false, s);
+  int rc = pass_forward(f, Mp, false, s, pr);
   if (rc != PES_OK) return rc;
   hipLaunchKernelGGL(logq_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, f->x, f->logdet, n, f->lsig, f->tau, logq,
                      z);
@@ -738,19 +807,28 @@ int flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double*
   return PES_OK;
 }
 
-int flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, double* logdet, hipStream_t s) {
+int flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, double* logdet, hipStream_t s,
+                 const StateProbe* pr) {
   if (n <= 0) return PES_OK;
   const int64_t Mp = pad_rows(n);
   if (Mp > f->cap) return PES_ESTATE;
   hipLaunchKernelGGL(load_latent_kernel, dim3(nblk(Mp * kD, 256)), dim3(256), 0, s, z, n, Mp, f->tau, f->x,
                      f->logdet);
   FL_HIP(f, hipGetLastError());
-  int rc = pass_inverse(f, Mp, s);
+  int rc = pass_inverse(f, Mp, s, pr);
   if (rc != PES_OK) return rc;
   hipLaunchKernelGGL(unstandardize_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, f->x, f->logdet, n, f->nm,
                      theta, logdet);
   FL_HIP(f, hipGetLastError());
   return PES_OK;
+}
+
+int flow_forward(pes_flow* f, const double* theta, int64_t n, double* z, double* logq, hipStream_t s) {
+  return flow_forward(f, theta, n, z, logq, s, nullptr);
+}
+
+int flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, double* logdet, hipStream_t s) {
+  return flow_inverse(f, z, n, theta, logdet, s, nullptr);
 }
 
 }  // namespace pes
@@ -881,6 +959,17 @@ int pes_flow_inverse(pes_flow* f, const double* z, int64_t n, double* theta, dou
   int rc = ensure_ws(f, n);
   if (rc != PES_OK) return rc;
   return pes::flow_inverse(f, z, n, theta, logdet, (hipStream_t)stream);
+}
+
+int pes_flow_probe(pes_flow* f, const double* in, int64_t n, int inverse, double* out, double* lq,
+                   float* states, float* logdet, float* acts, void* stream) {
+  if (!f || n < 0 || (inverse != 0 && inverse != 1)) return PES_EINVAL;
+  if (n > 0 && (!in || !out || !states || !logdet || (!inverse && !lq))) return PES_EINVAL;
+  int rc = ensure_ws(f, n);
+  if (rc != PES_OK) return rc;
+  const StateProbe pr{n, states, logdet, acts};
+  return inverse ? pes::flow_inverse(f, in, n, out, lq, (hipStream_t)stream, &pr)
+                 : pes::flow_forward(f, in, n, out, lq, (hipStream_t)stream, &pr);
 }
 
 int pes_flow_nll_grad(pes_flow* f, const double* theta, int64_t n, double* nll, float* grad, void* stream) {

@@ -86,6 +86,7 @@ def lib():
         L.pes_flow_forward.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
         L.pes_flow_inverse.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
         L.pes_flow_nll_grad.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
+        L.pes_flow_probe.argtypes = [vp, vp, C.c_int64, C.c_int, vp, vp, vp, vp, vp, vp]
         L.pes_flow_adam_step.argtypes = [vp, vp, C.c_float, vp]
         L.pes_flow_fit.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_int64, C.c_float, C.c_uint64, C.c_int,
                                    vp, vp]
@@ -117,7 +118,7 @@ def lib():
                      "pes_set_schedule", "pes_noise", "pes_probe", "pes_sampler_set_step",
                      "pes_flow_create", "pes_flow_destroy", "pes_flow_set_params", "pes_flow_get_params",
                      "pes_flow_set_norm", "pes_flow_set_affine", "pes_flow_get_affine", "pes_flow_set_temperature", "pes_flow_forward", "pes_flow_inverse",
-                     "pes_flow_nll_grad", "pes_flow_adam_step", "pes_flow_fit", "pes_sampler_set_flow",
+                     "pes_flow_nll_grad", "pes_flow_probe", "pes_flow_adam_step", "pes_flow_fit", "pes_sampler_set_flow",
                      "pes_sampler_read_chain",
                      "pes_fisher", "pes_sampler_create", "pes_sampler_destroy",
                      "pes_sampler_set_state", "pes_sampler_step", "pes_sampler_capture",
@@ -503,6 +504,23 @@ class Flow:
         self._check(lib().pes_flow_inverse(self.h, _dev_f64(z, "z"), n, _dev_f64(th, "theta"),
                                            _dev_f64(ld, "logdet"), _stream(stream)), "pes_flow_inverse")
         return th, ld
+
+    def probe(self, x, inverse=False, stream=None):
+        """The forward (theta -> z, log q) or inverse (z -> theta, log det) pass
+        with the coupling state at every layer boundary and every layer's
+        conditioner stages: (out [n, 11], lq [n], states float32 [9, n, 11],
+        running log det float32 [9, n], acts float32 [8, n, 576])."""
+        x = x.contiguous()
+        n = x.shape[0]
+        out = torch.empty((n, 11), dtype=torch.float64, device=x.device)
+        lq = torch.empty(n, dtype=torch.float64, device=x.device)
+        st = torch.empty((9, n, 11), dtype=torch.float32, device=x.device)
+        ld = torch.empty((9, n), dtype=torch.float32, device=x.device)
+        acts = torch.empty((8, n, 576), dtype=torch.float32, device=x.device)
+        self._check(lib().pes_flow_probe(self.h, _dev_f64(x, "in"), n, 1 if inverse else 0, _dev_f64(out, "out"),
+                                         _dev_f64(lq, "lq"), C.c_void_p(st.data_ptr()), C.c_void_p(ld.data_ptr()),
+                                         C.c_void_p(acts.data_ptr()), _stream(stream)), "pes_flow_probe")
+        return out, lq, st, ld, acts
 
     def nll_grad(self, theta, stream=None):
         theta = theta.contiguous()

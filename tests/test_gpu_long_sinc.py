@@ -164,6 +164,7 @@ def test_response_long_sinc(orc, torch_dev, pes, name):
     ctx.close()
     h_gpu = out[..., 0] + 1j * out[..., 1]
     f = cfg["f0"] + np.arange(cfg["n_bins"]) * cfg["df"]
+    reach = False
     for b in range(th.shape[0]):
         h_or = orc.response(cfg, th[b], prec=1)
         for det, dd in enumerate(cfg["detectors"]):
@@ -177,8 +178,11 @@ def test_response_long_sinc(orc, torch_dev, pes, name):
                 err = np.abs(h_gpu[b, det, c] - ref)
                 assert np.all(err <= tol), (name, b, det, c, float((err / tol).max()))
             if b > 0 and np.any(long_bins) and dd["kind"] == "lisa":
-                # the light walkers' LISA signal is non-zero beyond sqrt(4.9)
-                assert np.abs(h_or[det, 0][long_bins]).max() > 0
+                reach = reach or bool(np.abs(h_or[det, 0][long_bins]).max() > 0)
+    # the lightest walker (1e5 Msun: its (2,2) cutoff is 44 mHz) carries a LISA
+    # signal beyond 2 pi f L = sqrt(4.9), so the long-sinc bins are compared on
+    # a non-zero response
+    assert reach, name
 
 
 @pytest.mark.parametrize("name", list(CASES))

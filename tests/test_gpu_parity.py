@@ -264,6 +264,7 @@ def test_work_item_bound(torch_dev, pes):
     schedules; a larger walkers-per-item tuning brings it back within range."""
     torch = torch_dev
     cfg = _cfg("cfg1", n_bins=1 << 22)          # 16384 tiles of 256 bins
+    cfg["df"] = cfg["df"] / 4                   # up to 33 mHz: inside the sinc fits' range
     ctx = pes.Context(cfg)
     ctx.set_data(torch.zeros((1, 3, cfg["n_bins"], 2), dtype=torch.float64, device="cuda"))
     B = (1 << 17) + 1                           # 131073 groups of one walker
