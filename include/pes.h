@@ -145,6 +145,22 @@ int pes_response(pes_ctx* ctx, const double* theta, int64_t B, double* out, void
  * a larger walkers-per-item tuning (pes_set_tuning) lowers the count. */
 int pes_loglike(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pes_loglike
+ * with the same arguments, kernels and results, whose workspace is a 64 MiB
+ * device array of the library (one per GPU, held until the process ends)
+ * instead of the context's; it calls no allocator.  A batch needs, rounded up
+ * to 256 bytes per part, 2304 B (walker table) + 12 B (plan) per walker plus
+ * 16 B per walker per bin tile (ceil(n_bins / (256 x bins per lane)) tiles):
+ * about 990 walkers at 2^20 bins and one bin per lane, about 15000 at 32703
+ * bins.  PES_ESHAPE (message in pes_last_error) for a larger batch, PES_EHIP
+ * if the array has no address on the context's device; otherwise as
+ * pes_loglike.  Every call on one GPU works in that GPU's single array: calls
+ * that overlap in time on one GPU (other streams, other contexts, other
+ * threads) race and must be serialized by the caller.  No state carries from
+ * one call to the next (each call writes every scratch entry it reads). */
+int pes_loglike_noalloc(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void* stream);
+
 /* Gradient of log L with respect to theta (Sec. 2.3 differentiates the
  * response in reverse mode): logl (dev) [B] (may be NULL), grad (dev) [B][11]
  * in the units of theta.  Requires pes_set_data.  Unphysical samples:

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "../../include/pes.h"
@@ -15,7 +16,29 @@
 
 using namespace pes;
 
+// Device scratch of pes_loglike_noalloc: one copy per GPU, held until the
+// process ends.  Host code never uses the array's name as an address: the
+// address on each device is looked up once (scratch_address) and kept.
+constexpr int64_t kScratchBytes = int64_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Address of this device's copy of the scratch array (the device must be
+// current); null if the lookup fails.
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch[device] = p;
+  }
+  return g_scratch[device];
+}
 
 constexpr double kC = 299792458.0;
 constexpr double kAU = 149597870700.0;
@@ -57,6 +80,7 @@ struct pes_ctx {
   int* counters = nullptr;
   double* partial = nullptr;
   uint64_t ws_gen = 0;        // bumped whenever the workspace above is reallocated
+  void* scratch = nullptr;    // this device's scratch array (pes_loglike_noalloc)
   // derivative workspace
   int64_t jcap = 0;
   double* wtan = nullptr;      // [jcap][W_STRIDE][11]
@@ -264,6 +288,7 @@ int pes_create(const pes_config* cfg, pes_ctx** out) {
     delete c;
     return PES_EHIP;
   }
+  c->scratch = scratch_address(c->device);
   for (int i = 0; i < cfg->n_det; ++i) fill_geometry(cfg->det[i], c->dt.p[i]);
   // largest link sinc argument pi f L (1 + |k.n|) <= 2 pi f_max L per detector
   const double fmax_grid = cfg->f0 + (double)(cfg->n_bins - 1) * cfg->df;
@@ -606,6 +631,48 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
   st = ensure_workspace(c, B);
   if (st != PES_OK) return st;
   const LoglikeWork ws{c->wtab, c->ntiles, c->perm, c->gstart, c->counters, c->partial};
+  return run_loglike(c, theta, B, logl, ws, (hipStream_t)stream);
+}
+
+// The log-likelihood workspace of B walkers carved out of one buffer (each
+// part 256-byte aligned); returns the bytes it takes.  base may be null to
+// size it only.
+static int64_t carve_loglike_work(char* base, int64_t B, int ntmax, LoglikeWork* ws) {
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  char* wtab = take(sizeof(double) * B * W_STRIDE);
+  char* ntiles = take(sizeof(int) * B);
+  char* perm = take(sizeof(int) * B);
+  char* gstart = take(sizeof(int) * (B + 3));
+  char* counters = take(sizeof(int) * 4);
+  char* partial = take(sizeof(double) * 2 * B * (int64_t)ntmax);
+  if (ws)
+    *ws = LoglikeWork{(double*)wtab, (int*)ntiles, (int*)perm, (int*)gstart, (int*)counters, (double*)partial};
+  return off;
+}
+
+int pes_loglike_noalloc(pes_ctx* c, const double* theta, int64_t B, double* logl, void* stream) {
+  if (!c || B < 0 || (B > 0 && (!theta || !logl)) || B > (int64_t(1) << 24)) return PES_EINVAL;
+  if (!c->has_data) return PES_ESTATE;
+  if (B == 0) return PES_OK;
+  int st = check_items(c, B);
+  if (st != PES_OK) return st;
+  if (!c->scratch) {
+    snprintf(c->err, sizeof(c->err), "the device scratch array has no address on device %d", c->device);
+    return PES_EHIP;
+  }
+  const int64_t need = carve_loglike_work(nullptr, B, c->ntmax, nullptr);
+  if (need > kScratchBytes) {
+    snprintf(c->err, sizeof(c->err), "%lld walkers x %d tiles need %lld bytes of scratch; it holds %lld",
+             (long long)B, c->ntmax, (long long)need, (long long)kScratchBytes);
+    return PES_ESHAPE;
+  }
+  LoglikeWork ws;
+  carve_loglike_work((char*)c->scratch, B, c->ntmax, &ws);
   return run_loglike(c, theta, B, logl, ws, (hipStream_t)stream);
 }
 

@@ -62,6 +62,7 @@ def lib():
         L.pes_set_data.argtypes = [vp, vp, vp]
         L.pes_response.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.pes_loglike.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.pes_loglike_noalloc.argtypes = [vp, vp, C.c_int64, vp, vp]
         ip = C.POINTER(C.c_int)
         L.pes_set_tuning.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.pes_get_tuning.argtypes = [vp, ip, ip, ip]
@@ -113,7 +114,7 @@ def lib():
         L.pes_last_error.argtypes = [vp]
         L.pes_last_error.restype = C.c_char_p
         for name in ("pes_create", "pes_destroy", "pes_reserve", "pes_set_data",
-                     "pes_response", "pes_loglike", "pes_timing", "pes_timing_read",
+                     "pes_response", "pes_loglike", "pes_loglike_noalloc", "pes_timing", "pes_timing_read",
                      "pes_set_tuning", "pes_get_tuning", "pes_autotune", "pes_grad", "pes_set_grad_method",
                      "pes_set_schedule", "pes_noise", "pes_probe", "pes_sampler_set_step",
                      "pes_flow_create", "pes_flow_destroy", "pes_flow_set_params", "pes_flow_get_params",
@@ -277,6 +278,19 @@ class Context:
             out = torch.empty(B, dtype=torch.float64, device=theta.device)
         self._check(lib().pes_loglike(self.h, _dev_f64(theta, "theta"), B, _dev_f64(out, "logl"),
                                       _stream(stream)), "pes_loglike")
+        return out
+
+    def loglike_noalloc(self, theta, out=None, stream=None):
+        """pes_loglike_noalloc: the same log L in the library's device scratch
+        array, with no allocation (the output buffer is the caller's)."""
+        theta = theta.contiguous()
+        if theta.dim() != 2 or theta.shape[1] != 11:
+            raise PesError("theta must be [B, 11]")
+        B = theta.shape[0]
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=theta.device)
+        self._check(lib().pes_loglike_noalloc(self.h, _dev_f64(theta, "theta"), B, _dev_f64(out, "logl"),
+                                              _stream(stream)), "pes_loglike_noalloc")
         return out
 
     def grad(self, theta, stream=None):
