@@ -488,69 +488,80 @@ def _fisher_start(ctx, torch, B, seed):
     return np.clip(x, lo + eps, hi - eps)
 
 
-def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps, tau=1.1, fit_batch=1024, n_ref=3000):
+def ess_leg(torch, pes, B, n_pilot, n_collect, n_run, fit_steps, tau=1.1, fit_batch=4096, ref_walkers=1024,
+            n_ref=3000):
     """ESS/s of the plain DE-MC sampler against the mixture with the learned
-    flow (p_flow 0.9, temperature tau), equal numbers of steps from the same
-    burned-in ensemble, on the three-detector network (cfg4's likelihood at B
-    walkers).  Accuracy: the largest per-parameter KS distance of the
-    mixture's draws from a long plain reference (n_ref further DE steps from
-    the pilot's end, second half, every 10th step) against the one between
-    the plain run and an independent plain run (own start, own burn-in of
-    the same length); the short runs' distances from the plain run are
-    reported too."""
+    flow (p_flow 0.9, temperature tau) on the three-detector network with five
+    modes at 2^20 bins (cfg4), B walkers.
+
+    A plain DE pilot from the Fisher start burns in for n_pilot steps; the
+    states of its last n_collect steps (every walker, repeats included, 10% of
+    the walkers held out) train the flow.  Both arms then run n_run steps from
+    the pilot's end state.  The reference is a long plain run of ref_walkers
+    walkers from the same state (n_ref steps, second half, every 10th step).
+    Accuracy of an arm: the largest per-parameter two-sample KS distance of
+    its second-half draws from the reference; the bound is 1.5 times the KS
+    distance between the reference's two walker halves (independent chains).
+    Each arm's seconds to reach the bound are measured on a grid of run
+    lengths (draws from the second half of the first t steps)."""
     from paper_2602_12011_amd import diagnostics as D
     cfg = W.config("cfg4")
     dev = torch.device("cuda:0")
     ctx = pes.Context(cfg)
     th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
     ctx.set_data(ctx.response(th0)[0].clone())
+    ctx.reserve(B)
     prior = _prior_spec()
-    # pilot DE run: burn-in and training samples
-    pilot = pes.Sampler(ctx, prior, B, 101, chain_len=n_pilot)
+    pilot = pes.Sampler(ctx, prior, B, 101, chain_len=n_collect)
     pilot.set_state(torch.from_numpy(_fisher_start(ctx, torch, B, 12)).to(dev))
-    t0 = time.perf_counter()
-    pilot.step(n_pilot)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(0, n_pilot, 50):
+        pilot.step(min(50, n_pilot - k))
+        torch.cuda.synchronize()
+        print(f"[ess] pilot {min(k + 50, n_pilot)}/{n_pilot} steps, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     t_pilot = time.perf_counter() - t0
-    ch = pilot.read_chain().cpu().numpy()
+    ch = pilot.read_chain().cpu().numpy()                  # [n_collect, B, 11]
     state = pilot.state()[0].clone()
+    pilot_acc = float(pilot.state()[2].cpu().numpy().sum()) / (B * n_pilot)
     pilot.close()
-    ref = pes.Sampler(ctx, prior, B, 404, chain_len=n_ref)
-    ref.set_state(state)
+    rhat = float(D.gelman_rubin(ch).max())
+    n_val_w = B // 10
+    train = np.ascontiguousarray(ch[:, n_val_w:].reshape(-1, 11))
+    val = np.ascontiguousarray(ch[:, :n_val_w].reshape(-1, 11))
+    del ch
+    # long plain reference
+    ref = pes.Sampler(ctx, prior, ref_walkers, 404, chain_len=n_ref)
+    ref.set_state(state[:ref_walkers].contiguous())
     t0 = time.perf_counter()
-    ref.step(n_ref)
-    torch.cuda.synchronize()
+    for k in range(0, n_ref, 500):
+        ref.step(min(500, n_ref - k))
+        torch.cuda.synchronize()
+        print(f"[ess] reference {min(k + 500, n_ref)}/{n_ref} steps, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     t_ref = time.perf_counter() - t0
-    ref_draws = ref.read_chain().cpu().numpy()[n_ref // 2::10].reshape(-1, 11)
+    rch = ref.read_chain().cpu().numpy()[n_ref // 2::10]   # [n, ref_walkers, 11]
     ref.close()
-    half = ch[n_pilot // 2:]
-    rhat = float(D.gelman_rubin(half).max())
-    # distinct states only (rejected moves repeat a state), 10% held out
-    uniq = np.unique(half.reshape(-1, 11), axis=0)
-    rng = np.random.default_rng(5)
-    rng.shuffle(uniq)
-    n_val = max(len(uniq) // 10, 1)
-    val, train = uniq[:n_val], uniq[n_val:]
+    ref_draws = rch.reshape(-1, 11)
+    h = ref_walkers // 2
+    ks_split = max(D.ks_distance(rch[:, :h, j].ravel(), rch[:, h:, j].ravel()) for j in range(11))
+    bound = 1.5 * ks_split
+    # the learned proposal
     flow = pes.Flow(seed=7)
+    tr = torch.from_numpy(train).to(dev)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    loss = flow.fit(torch.from_numpy(train).to(dev), steps=fit_steps, batch=min(fit_batch, len(train)), lr=1e-3,
-                    seed=3)
+    loss = flow.fit(tr, steps=fit_steps, batch=fit_batch, lr=1e-3, seed=3)
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t0
-    nll_val = float(flow.nll_grad(torch.from_numpy(val).to(dev))[0].cpu())
+    del tr
+    nll_val = float(flow.nll_grad(torch.from_numpy(val[::8].copy()).to(dev))[0].cpu())
     flow.set_temperature(tau)
     results, chains = {}, {}
-    runs = (("plain", 202, False, state), ("learned", 202, True, state),
-            ("plain_independent", 303, False, None))
-    for name, seed, use_flow, start in runs:
-        if start is None:   # independent run: own Fisher start and burn-in
-            burn = pes.Sampler(ctx, prior, B, seed + 1)
-            burn.set_state(torch.from_numpy(_fisher_start(ctx, torch, B, 13)).to(dev))
-            burn.step(n_pilot)
-            start = burn.state()[0].clone()
-            burn.close()
+    for name, seed, use_flow in (("plain", 202, False), ("learned", 202, True)):
         smp = pes.Sampler(ctx, prior, B, seed, chain_len=n_run)
-        smp.set_state(start)
+        smp.set_state(state)
         if use_flow:
             smp.set_flow(flow, 0.9)
         torch.cuda.synchronize()
@@ -558,47 +569,51 @@ def ess_leg(torch, pes, B, n_pilot, n_run, fit_steps, tau=1.1, fit_batch=1024, n
         smp.step(n_run)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        print(f"[ess] {name}: {n_run} steps in {dt:.1f} s", file=sys.stderr, flush=True)
         acc = smp.state()[2].cpu().numpy().sum() / (B * n_run)
         chains[name] = smp.read_chain().cpu().numpy()
         smp.close()
         e = D.ess(chains[name])
+        c = chains[name]
+        draws = c[n_run // 2:].reshape(-1, 11)
+        ks_j = [D.ks_distance(draws[:, j], ref_draws[:, j]) for j in range(11)]
+        # seconds to reach the accuracy bound: second half of the first t steps
+        t_acc = None
+        for t in range(10, n_run + 1, 10):
+            sub = c[t // 2:t, ::4].reshape(-1, 11)
+            if max(D.ks_distance(sub[:, j], ref_draws[:, j]) for j in range(11)) <= bound:
+                t_acc = t
+                break
         results[name] = dict(seconds=round(dt, 3), acceptance=round(float(acc), 4),
-                             ess_min=round(float(e.min()), 1), ess_per_s=round(float(e.min()) / dt, 2))
+                             ess_min=round(float(e.min()), 1), ess_per_s=round(float(e.min()) / dt, 2),
+                             ks_vs_reference=round(max(ks_j), 4),
+                             ks_per_parameter_vs_reference=[round(x, 4) for x in ks_j],
+                             accuracy_ok=bool(max(ks_j) <= bound),
+                             steps_to_accuracy=t_acc,
+                             seconds_to_accuracy=None if t_acc is None else round(dt * t_acc / n_run, 3),
+                             sd_ratio_vs_reference=[round(float(x), 3) for x in
+                                                    draws.std(axis=0) / ref_draws.std(axis=0)])
     flow.close()
     ctx.close()
-    flat = {k: v[n_run // 2:].reshape(-1, 11) for k, v in chains.items()}
-    ks_lp_j = [D.ks_distance(flat["learned"][:, j], flat["plain"][:, j]) for j in range(11)]
-    ks_pp_j = [D.ks_distance(flat["plain_independent"][:, j], flat["plain"][:, j]) for j in range(11)]
-    ks_lr_j = [D.ks_distance(flat["learned"][:, j], ref_draws[:, j]) for j in range(11)]
-    ks_pr_j = [D.ks_distance(flat["plain"][:, j], ref_draws[:, j]) for j in range(11)]
-    ks_lp, ks_pp = max(ks_lp_j), max(ks_pp_j)
-    ks_lr, ks_pr = max(ks_lr_j), max(ks_pr_j)
-    sd_ratio = flat["learned"].std(axis=0) / flat["plain"].std(axis=0)
     gain = results["learned"]["ess_per_s"] / max(results["plain"]["ess_per_s"], 1e-30)
+    both = results["learned"]["accuracy_ok"] and results["plain"]["accuracy_ok"]
+    ta, tp = results["learned"]["seconds_to_accuracy"], results["plain"]["seconds_to_accuracy"]
     amort = results["learned"]["ess_min"] / (results["learned"]["seconds"] + t_fit)
     return dict(workload=f"LISA+Taiji+TianQin, 5 modes, 2^20 bins, {B} walkers, noise-free injection; "
-                         f"{n_pilot}-step DE pilot (distinct states of its second half train the flow), "
-                         f"then {n_run} steps each",
-                pilot_seconds=round(t_pilot, 2), pilot_rhat_max=round(rhat, 4),
-                train_rows=int(len(train)), fit_seconds=round(t_fit, 2),
+                         f"{n_pilot}-step plain DE pilot, the states of its last {n_collect} steps train the "
+                         f"flow; then {n_run} steps of each arm from the pilot's end",
+                pilot_seconds=round(t_pilot, 2), pilot_acceptance=round(pilot_acc, 4),
+                pilot_rhat_max=round(rhat, 4), train_rows=int(len(train)), heldout_rows=int(len(val)),
+                fit_steps=fit_steps, fit_batch=fit_batch, fit_seconds=round(t_fit, 2),
                 fit_loss_first_last=[round(float(loss[0]), 3), round(float(loss[-1]), 3)],
                 heldout_nll=round(nll_val, 3), temperature=tau,
                 plain=results["plain"], learned=results["learned"],
-                plain_independent=results["plain_independent"], gain=round(gain, 2),
+                gain=round(gain, 2), gain_at_matched_accuracy=round(gain, 2) if both else None,
+                seconds_to_accuracy_ratio=(round(tp / ta, 2) if (ta and tp) else None),
                 learned_ess_per_s_with_training=round(amort, 2),
-                reference=dict(steps=n_ref, seconds=round(t_ref, 2), draws=int(len(ref_draws))),
-                ks_learned_vs_reference=round(ks_lr, 4), ks_plain_vs_reference=round(ks_pr, 4),
-                ks_learned_vs_plain=round(ks_lp, 4), ks_independent_plain_vs_plain=round(ks_pp, 4),
-                accuracy_ok=bool(ks_lr <= 1.5 * ks_pp),
-                ks_per_parameter_learned_vs_reference=[round(x, 4) for x in ks_lr_j],
-                ks_per_parameter_plain_vs_reference=[round(x, 4) for x in ks_pr_j],
-                ks_per_parameter_learned_vs_plain=[round(x, 4) for x in ks_lp_j],
-                ks_per_parameter_independent_plain_vs_plain=[round(x, 4) for x in ks_pp_j],
-                sd_ratio_learned_over_plain=[round(float(x), 3) for x in sd_ratio],
-                sd_ratio_learned_over_reference=[round(float(x), 3) for x in
-                                                 flat["learned"].std(axis=0) / ref_draws.std(axis=0)],
-                sd_ratio_plain_over_reference=[round(float(x), 3) for x in
-                                               flat["plain"].std(axis=0) / ref_draws.std(axis=0)])
+                reference=dict(walkers=ref_walkers, steps=n_ref, seconds=round(t_ref, 2),
+                               draws=int(len(ref_draws)), ks_between_walker_halves=round(ks_split, 4)),
+                accuracy_bound=round(bound, 4))
 
 
 def main():
@@ -615,10 +630,13 @@ def main():
                     help="only the headline measurement (no extra legs)")
     ap.add_argument("--extras", default="derivatives,graph,config2,fisher_sampling,paper_pe,ess",
                     help="comma list of the extra legs to run after the headline")
-    ap.add_argument("--ess-walkers", type=int, default=1024)
-    ap.add_argument("--ess-pilot", type=int, default=1000)
-    ap.add_argument("--ess-steps", type=int, default=300)
-    ap.add_argument("--ess-fit-steps", type=int, default=300)
+    ap.add_argument("--ess-walkers", type=int, default=16384)
+    ap.add_argument("--ess-pilot", type=int, default=300)
+    ap.add_argument("--ess-collect", type=int, default=72,
+                    help="last pilot steps whose states (all walkers) train the flow")
+    ap.add_argument("--ess-steps", type=int, default=150)
+    ap.add_argument("--ess-fit-steps", type=int, default=1000)
+    ap.add_argument("--ess-ref-walkers", type=int, default=1024)
     ap.add_argument("--ess-ref-steps", type=int, default=3000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
@@ -717,8 +735,8 @@ def main():
         rec["paper_pe"] = paper_pe_leg(torch, pes)
     if "ess" in extras:
         print("[bench] ESS", file=sys.stderr, flush=True)
-        rec["ess"] = ess_leg(torch, pes, args.ess_walkers, args.ess_pilot, args.ess_steps, args.ess_fit_steps,
-                             n_ref=args.ess_ref_steps)
+        rec["ess"] = ess_leg(torch, pes, args.ess_walkers, args.ess_pilot, args.ess_collect, args.ess_steps,
+                             args.ess_fit_steps, ref_walkers=args.ess_ref_walkers, n_ref=args.ess_ref_steps)
     print(json.dumps(rec), flush=True)
     return 0
 

@@ -1,8 +1,8 @@
 // Derivative kernels of libpes (gfx950): the reverse-mode gradient
-// (adj_kernel), the forward-mode Fisher matrix and gradient (forward_body:
-// one (bin, parameter) tangent per lane, the J^T J contraction on the FP64
-// matrix cores) and their per-walker reductions.  Walker tangents come from
-// setup_tan_kernel (pes_kernels.hip).
+// (adj_kernel), the forward-mode Fisher matrix (fisher_dense_body: one (bin,
+// parameter) tangent per lane, the J^T J contraction on the FP64 matrix cores)
+// and gradient (forward_grad_body), and their per-walker reductions.  Walker
+// tangents come from setup_tan_kernel (pes_kernels.hip).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -20,25 +20,19 @@ __device__ __forceinline__ int64_t active_bins(double fmx, double f0, double df,
   return (int64_t)nb;
 }
 
-// Forward-mode tangents, one (bin, parameter) pair per lane, for the Fisher
-// matrix (and, with GRAD, the forward-mode gradient): lane l of a wavefront
-// carries the tangent direction p = l % 16 (p < 11; the other five lanes
-// contribute zeros) of bin l / 16 of its group of four bins, so after one
-// dual-number evaluation every lane holds sqrt(W) dC_r/dtheta_p for its pair,
-// which is at once the A operand (row p, column bin) and the B operand (row
-// bin, column p) of a 16 x 16 x 4 FP64 matrix-core product: six products per
-// group accumulate sum_bins J_r^T J_r with no Jacobian tile.  The walker's
-// tangent table is staged in LDS once per block (the lanes read different
-// directions of the same entry); the four wavefronts of a block take
-// interleaved groups of the block's bin tile and their accumulators are added
-// in LDS at the end.
-// With GRAD the same pairs give the forward-mode gradient instead: each lane
-// accumulates sum_r (D - W C)_r dC_r/dtheta_p, the p = 0 lanes also <d|h> and
-// <h|h>, and the block reduces them to the per-tile partials of the gradient.
-template <bool LS, bool GRAD>
-__device__ __forceinline__ void forward_body(const double* __restrict__ bins, const double* __restrict__ tabs,
-                                             const double* __restrict__ wtab, const double* __restrict__ wtan,
-                                             double* __restrict__ partial, const JacArgs& A) {
+// Forward-mode gradient (the cross-check of the reverse sweep), one (bin,
+// parameter) pair per lane: lane l of a wavefront carries the tangent
+// direction p = l % 16 (p < 11; the other five lanes contribute zeros) of bin
+// l / 16 of its group of four bins and accumulates sum_r (D - W C)_r
+// dC_r/dtheta_p; the p = 0 lanes also <d|h> and <h|h>, and the block reduces
+// them to the per-tile partials of the gradient.  The walker's tangent table
+// is staged in LDS once per block (the lanes read different directions of the
+// same entry); the four wavefronts of a block take interleaved groups of the
+// block's bin tile.
+template <bool LS>
+__device__ __forceinline__ void forward_grad_body(const double* __restrict__ bins, const double* __restrict__ tabs,
+                                                  const double* __restrict__ wtab, const double* __restrict__ wtan,
+                                                  double* __restrict__ partial, const JacArgs& A) {
   __shared__ double red[4][256];
   __shared__ double tan_s[W_STRIDE * kNParams];   // the walker's tangent table, 25 KiB
   const int t = blockIdx.x;
@@ -56,8 +50,6 @@ __device__ __forceinline__ void forward_body(const double* __restrict__ bins, co
   const int p = lane & 15, sub = lane >> 4;
   const bool pin = p < kNParams;
   const int64_t N = A.N;
-  typedef double v4d __attribute__((ext_vector_type(4)));
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
   double gacc = 0.0, dh = 0.0, hh = 0.0;
   for (int64_t s0 = k0 + 4 * wv; s0 < kend; s0 += 16) {
     const int64_t k = s0 + sub;
@@ -72,8 +64,8 @@ __device__ __forceinline__ void forward_body(const double* __restrict__ bins, co
     for (int det = 0; det < A.n_det; ++det) {
       const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * N;
       const double zr = tb[T_ZR * N + kk], zi = tb[T_ZI * N + kk], a = tb[T_A * N + kk];
-      const double sA = in ? sqrt(tb[T_WA * N + kk]) : 0.0;
-      const double sT = in ? sqrt(tb[T_WT * N + kk]) : 0.0;
+      const double wA = in ? tb[T_WA * N + kk] : 0.0;
+      const double wT = in ? tb[T_WT * N + kk] : 0.0;
       const DetParams& P = A.dt.p[det];
       const TanTabLane T{wt, tan_s, pin ? p : 0};
       const ChanT<Dual<1>> c = (P.kind == 2)
@@ -81,74 +73,151 @@ __device__ __forceinline__ void forward_body(const double* __restrict__ bins, co
                                                                           br, a, zr, zi)
                                    : eval_channels_t<false, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year,
                                                                            P.inv_ptq, br, a, zr, zi);
-      if (GRAD) {
-        const double wA = sA * sA, wT = sT * sT;
-        const double W[6] = {wA, wA, wA * (1.0 / 3.0), wA * (1.0 / 3.0), wT, wT};
-        const double D[6] = {in ? tb[T_DAR * N + kk] : 0.0, in ? tb[T_DAI * N + kk] : 0.0,
-                             in ? tb[T_DER * N + kk] : 0.0, in ? tb[T_DEI * N + kk] : 0.0,
-                             in ? tb[T_DTR * N + kk] : 0.0, in ? tb[T_DTI * N + kk] : 0.0};
-        const double cv[6] = {c.ar.v, c.ai.v, c.er.v, c.ei.v, c.tr.v, c.ti.v};
-        const double cd[6] = {c.ar.d[0], c.ai.d[0], c.er.d[0], c.ei.d[0], c.tr.d[0], c.ti.d[0]};
-        const bool first = p == 0;
+      const double W[6] = {wA, wA, wA * (1.0 / 3.0), wA * (1.0 / 3.0), wT, wT};
+      const double D[6] = {in ? tb[T_DAR * N + kk] : 0.0, in ? tb[T_DAI * N + kk] : 0.0,
+                           in ? tb[T_DER * N + kk] : 0.0, in ? tb[T_DEI * N + kk] : 0.0,
+                           in ? tb[T_DTR * N + kk] : 0.0, in ? tb[T_DTI * N + kk] : 0.0};
+      const double cv[6] = {c.ar.v, c.ai.v, c.er.v, c.ei.v, c.tr.v, c.ti.v};
+      const double cd[6] = {c.ar.d[0], c.ai.d[0], c.er.d[0], c.ei.d[0], c.tr.d[0], c.ti.d[0]};
+      const bool first = p == 0;
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
-          gacc = fma(fma(-W[r], cv[r], D[r]), cd[r], gacc);
-          dh = first ? fma(D[r], cv[r], dh) : dh;
-          hh = first ? fma(W[r] * cv[r], cv[r], hh) : hh;
-        }
-      } else {
-        const double sE = sA * 0.5773502691896258;   // W_E = W_A / 3
-        const double v[6] = {sA * c.ar.d[0], sA * c.ai.d[0], sE * c.er.d[0],
-                             sE * c.ei.d[0], sT * c.tr.d[0], sT * c.ti.d[0]};
-#pragma unroll
-        for (int r = 0; r < 6; ++r) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r], v[r], acc, 0, 0, 0);
+      for (int r = 0; r < 6; ++r) {
+        gacc = fma(fma(-W[r], cv[r], D[r]), cd[r], gacc);
+        dh = first ? fma(D[r], cv[r], dh) : dh;
+        hh = first ? fma(W[r] * cv[r], cv[r], hh) : hh;
       }
     }
   }
+  // lane (sub, p) of wave w holds its share of d l / d theta_p; <d|h>, <h|h>
+  // sit in the p = 0 lanes.  Fixed-order sums over waves and sub-lanes.
   const int e = threadIdx.x;
-  if (GRAD) {
-    // lane (sub, p) of wave w holds its share of d l / d theta_p; <d|h>, <h|h>
-    // sit in the p = 0 lanes.  Fixed-order sums over waves and sub-lanes.
-    red[wv][lane] = gacc;
-    red[wv][64 + lane] = dh;
-    red[wv][128 + lane] = hh;
-    __syncthreads();
-    if (e < kNParams + 2) {
-      const int base = e < kNParams ? 0 : (e == kNParams ? 64 : 128);
-      const int col = e < kNParams ? e : 0;
-      double sum = 0.0;
-      for (int w = 0; w < 4; ++w)
-        for (int q = 0; q < 4; ++q) sum += red[w][base + 16 * q + col];
-      partial[((int64_t)t * A.B + b) * (kNParams + 2) + e] = sum;
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) red[wv][4 * lane + r] = acc[r];
-    __syncthreads();
-    // accumulator element e: lane e / 4, register e % 4 <-> (row 4 (e % 4) + (e / 4) / 16,
-    // column (e / 4) % 16); the 11 x 11 block is kept, row-major
-    const double sum = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
-    const int row = 4 * (e & 3) + ((e >> 2) >> 4), col = (e >> 2) & 15;
-    if (row < kNParams && col < kNParams)
-      partial[((int64_t)t * A.B + b) * (kNParams * kNParams) + row * kNParams + col] = sum;
+  red[wv][lane] = gacc;
+  red[wv][64 + lane] = dh;
+  red[wv][128 + lane] = hh;
+  __syncthreads();
+  if (e < kNParams + 2) {
+    const int base = e < kNParams ? 0 : (e == kNParams ? 64 : 128);
+    const int col = e < kNParams ? e : 0;
+    double sum = 0.0;
+    for (int w = 0; w < 4; ++w)
+      for (int q = 0; q < 4; ++q) sum += red[w][base + 16 * q + col];
+    partial[((int64_t)t * A.B + b) * (kNParams + 2) + e] = sum;
   }
 }
 
-// The Fisher variant fits three waves per SIMD; the gradient variant holds the
-// residual as well and runs two without spilling.
+// Fisher matrix with every lane busy: the 11 tangent directions of a bin are
+// spread over consecutive lanes, pair i = 64 r + lane of a wave's chunk of 64
+// bins is (bin i / 11, direction i % 11), so eleven rounds of 64 lanes cover
+// the chunk with no idle lane.  After each round the lanes write
+// sqrt(W) dC_r/dtheta_p into a per-wave LDS ring of bins, and every complete
+// group of four bins is read back in the 16 x 16 x 4 matrix-core layout
+// (lane 16 sub + p: bin sub, direction p; p >= 11 reads zero) for the six
+// products of the contraction.  A round completes floor(64 (r + 1) / 11) bins,
+// so at most three complete bins wait for a group, six more complete in a
+// round and one is partly written: twelve ring slots suffice.
+constexpr int kRing = 12;
+
 template <bool LS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__device__ __forceinline__ void fisher_dense_body(const double* __restrict__ bins, const double* __restrict__ tabs,
+                                                  const double* __restrict__ wtab, const double* __restrict__ wtan,
+                                                  double* __restrict__ partial, const JacArgs& A) {
+  __shared__ double tan_s[W_STRIDE * kNParams];             // the walker's tangent table, 25 KiB
+  __shared__ double ring[4][kRing][6][kNParams];            // per wave; reused for the final sums
+  const int t = blockIdx.x;
+  const int b = blockIdx.y;
+  const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
+  const double* __restrict__ wtn = wtan + (int64_t)b * W_STRIDE * kNParams;
+  if (wt[W_VALID] == 0.0) return;
+  const int64_t nact = active_bins(wt[W_FMAX], A.f0, A.df, A.N);
+  const int64_t k0 = (int64_t)t * A.tile;
+  if (k0 >= nact) return;
+  for (int i = threadIdx.x; i < W_STRIDE * kNParams; i += 256) tan_s[i] = wtn[i];
+  __syncthreads();
+  const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int sub = lane >> 4, pq = lane & 15;
+  const int64_t N = A.N;
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  double(*rw)[6][kNParams] = ring[wv];
+  for (int det = 0; det < A.n_det; ++det) {   // each detector's channels are rows of their own
+    const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * N;
+    const DetParams& P = A.dt.p[det];
+    for (int64_t c0 = k0 + 64 * wv; c0 < kend; c0 += 256) {   // this wave's chunks of 64 bins
+      int used = 0;
+      for (int r = 0; r < kNParams; ++r) {
+        const int i = 64 * r + lane;
+        const int bl = i / kNParams, p = i - kNParams * bl;
+        const int64_t k = c0 + bl;
+        const bool in = k < kend;
+        const int64_t kk = in ? k : kend - 1;
+        BinRegs br;
+        br.f = bins[B_F * N + kk];
+        br.f13 = bins[B_F13 * N + kk];
+        br.fm13 = bins[B_FM13 * N + kk];
+        br.fm76 = bins[B_FM76 * N + kk];
+        br.lnf = bins[B_LNF * N + kk];
+        const double zr = tb[T_ZR * N + kk], zi = tb[T_ZI * N + kk], a = tb[T_A * N + kk];
+        const double sA = in ? sqrt(tb[T_WA * N + kk]) : 0.0;
+        const double sT = in ? sqrt(tb[T_WT * N + kk]) : 0.0;
+        const TanTabLane T{wt, tan_s, p};
+        const ChanT<Dual<1>> c = (P.kind == 2)
+                                     ? eval_channels_t<true, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year, P.inv_ptq,
+                                                                            br, a, zr, zi)
+                                     : eval_channels_t<false, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year,
+                                                                             P.inv_ptq, br, a, zr, zi);
+        const double sE = sA * 0.5773502691896258;   // W_E = W_A / 3
+        const double v[6] = {sA * c.ar.d[0], sA * c.ai.d[0], sE * c.er.d[0],
+                             sE * c.ei.d[0], sT * c.tr.d[0], sT * c.ti.d[0]};
+        const int slot = bl % kRing;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 6; ++q) rw[slot][q][p] = v[q];
+        __builtin_amdgcn_wave_barrier();
+        // bins whose 11 directions are all written, contracted four at a time
+        const int done = (64 * (r + 1)) / kNParams;
+        for (; used + 4 <= done; used += 4) {
+          const int bs = (used + sub) % kRing;
+#pragma unroll
+          for (int q = 0; q < 6; ++q) {
+            const double x = pq < kNParams ? rw[bs][q][pq] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  }
+  __syncthreads();
+  double* red = &ring[0][0][0][0];   // [4 waves][256]
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wv * 256 + 4 * lane + r] = acc[r];
+  __syncthreads();
+  // accumulator element e: lane e / 4, register e % 4 <-> (row 4 (e % 4) + (e / 4) / 16,
+  // column (e / 4) % 16); the 11 x 11 block is kept, row-major
+  const int e = threadIdx.x;
+  const double sum = (red[e] + red[256 + e]) + (red[512 + e] + red[768 + e]);
+  const int row = 4 * (e & 3) + ((e >> 2) >> 4), col = (e >> 2) & 15;
+  if (row < kNParams && col < kNParams)
+    partial[((int64_t)t * A.B + b) * (kNParams * kNParams) + row * kNParams + col] = sum;
+}
+
+// Two waves per SIMD: the dense Fisher body needs about 200 registers (held
+// to 168 for a third wave it spills 30 of them, and measures the same); the
+// gradient variant holds the residual as well and runs two without spilling.
+template <bool LS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     forward_fisher_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                           const double* __restrict__ wtab, const double* __restrict__ wtan,
                           double* __restrict__ partial, JacArgs A) {
-  forward_body<LS, false>(bins, tabs, wtab, wtan, partial, A);
+  fisher_dense_body<LS>(bins, tabs, wtab, wtan, partial, A);
 }
 template <bool LS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     forward_grad_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                         const double* __restrict__ wtab, const double* __restrict__ wtan,
                         double* __restrict__ partial, JacArgs A) {
-  forward_body<LS, true>(bins, tabs, wtab, wtan, partial, A);
+  forward_grad_body<LS>(bins, tabs, wtab, wtan, partial, A);
 }
 
 // Reverse-mode gradient: for each (walker, bin, detector) one forward

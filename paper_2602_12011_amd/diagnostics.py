@@ -14,6 +14,21 @@ def autocorr_function(x):
     return acf / acf[0] if acf[0] > 0 else np.zeros(n)
 
 
+def _mean_autocorr(x):
+    """Walker average of the normalized autocorrelation functions of the
+    columns of x [T, walkers] (FFT along time, zero-padded); a constant walker
+    contributes zeros."""
+    T = x.shape[0]
+    f = np.fft.rfft(x - x.mean(axis=0), n=2 * T, axis=0)
+    acf = np.fft.irfft(f * np.conj(f), axis=0)[:T]
+    a0 = acf[0]
+    ok = a0 > 0
+    rho = np.zeros(T)
+    if ok.any():
+        rho = (acf[:, ok] / a0[ok]).sum(axis=1)
+    return rho / x.shape[1]
+
+
 def integrated_time(chain, c=5.0):
     """tau of each parameter for chain [T, walkers, d]: the autocorrelation
     function averaged over walkers, summed up to the smallest window M with
@@ -23,8 +38,8 @@ def integrated_time(chain, c=5.0):
     taus = np.empty(d)
     for j in range(d):
         rho = np.zeros(T)
-        for b in range(B):
-            rho += autocorr_function(chain[:, b, j])
+        for b0 in range(0, B, 4096):
+            rho += _mean_autocorr(chain[:, b0:b0 + 4096, j]) * min(4096, B - b0)
         rho /= B
         tau_m = 2.0 * np.cumsum(rho) - 1.0
         m = np.arange(T)
