@@ -397,12 +397,55 @@ def paper_pe_leg(torch, pes, batch=1024, n_single=10, reps=5):
                          for i in range(n_single)])
         ob = torch.empty(batch, dtype=torch.float64, device=dev)
         t_batch = _time_ms(torch, lambda: ctx.loglike(th, ob), reps)
+        ctx.set_precision(32)      # the paper's second precision (Fig. fig_cost)
+        t_one32 = np.mean([_time_ms(torch, lambda i=i: ctx.loglike(th[i:i + 1], o1), reps)
+                           for i in range(n_single)])
+        t_batch32 = _time_ms(torch, lambda: ctx.loglike(th, ob), reps)
         ctx.close()
         sweep.append(dict(series_samples=2 ** p, duration_days=round(T / W.DAY_S, 2), n_bins=cfg["n_bins"],
                           one_sample_ms=round(float(t_one), 4),
-                          batched_ms_per_sample=round(t_batch / batch, 5)))
+                          batched_ms_per_sample=round(t_batch / batch, 5),
+                          one_sample_ms_fp32=round(float(t_one32), 4),
+                          batched_ms_per_sample_fp32=round(t_batch32 / batch, 5)))
     out["cost_vs_bins"] = sweep
     return out
+
+
+def fp32_leg(torch, pes, steps, L64_ref=None):
+    """The headline workload (LISA-like, five modes, 2^20 bins, 4096 prior
+    walkers) with the single-precision kernels: evals/s at the autotuned
+    tuning, and the deviation from the FP64 path on the same batch relative to
+    max(|L|, <d|d>/2)."""
+    cfg = W.config("cfg1")
+    B = cfg["walkers"]
+    dev = torch.device("cuda:0")
+    ctx = pes.Context(cfg)
+    ctx.reserve(B)
+    th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
+    ctx.set_data(ctx.response(th0)[0].clone())
+    theta = torch.from_numpy(W.draw_walkers(B, stream=1)).to(dev)
+    out = torch.empty(B, dtype=torch.float64, device=dev)
+    far = th0.clone()
+    far[0, 4] = 1e12
+    sigma = -float(ctx.loglike(far)[0])           # <d|d>/2
+    ctx.autotune(theta)
+    t64 = _time_ms(torch, lambda: ctx.loglike(theta, out), steps)
+    L64 = out.cpu().numpy().copy()
+    ctx.set_precision(32)
+    _, tuning = ctx.autotune(theta)
+    ctx.timing(True)
+    t32 = _time_ms(torch, lambda: ctx.loglike(theta, out), steps)
+    kern_ms, launches = ctx.timing_read()
+    ctx.timing(False)
+    L32 = out.cpu().numpy()
+    ctx.close()
+    rel = np.abs(L32 - L64) / np.maximum(np.abs(L64), sigma)
+    return dict(workload="LISA-like, 5 modes, 2^20 bins (df=1/yr), 4096 walkers, noise-free injection",
+                tuning=tuning, ms_per_call=round(t32, 3), evals_per_s=round(B / (t32 * 1e-3), 1),
+                kernel_ms=round(kern_ms / launches, 3),
+                fp64_ms_per_call_same_run=round(t64, 3), speedup_over_fp64=round(t64 / t32, 3),
+                max_rel_dev_from_fp64=float(f"{rel.max():.3e}"),
+                median_rel_dev_from_fp64=float(f"{np.median(rel):.3e}"))
 
 
 EXTRINSIC = (7, 8, 9, 10)   # lambda, beta, psi, t_c
@@ -628,7 +671,7 @@ def main():
                     help="bins_per_lane,walkers_per_group,blocks_per_cu (skips the autotuner)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline measurement (no extra legs)")
-    ap.add_argument("--extras", default="derivatives,graph,config2,fisher_sampling,paper_pe,ess",
+    ap.add_argument("--extras", default="derivatives,graph,config2,fp32,fisher_sampling,paper_pe,ess",
                     help="comma list of the extra legs to run after the headline")
     ap.add_argument("--ess-walkers", type=int, default=16384)
     ap.add_argument("--ess-pilot", type=int, default=300)
@@ -727,6 +770,9 @@ def main():
     if "config2" in extras:
         print("[bench] config 2 schedules", file=sys.stderr, flush=True)
         rec["config2"] = config2_leg(torch, pes, 3)
+    if "fp32" in extras:
+        print("[bench] single precision", file=sys.stderr, flush=True)
+        rec["fp32"] = fp32_leg(torch, pes, 10)
     if "fisher_sampling" in extras:
         print("[bench] Fisher vs sampling, extrinsic parameters", file=sys.stderr, flush=True)
         rec["fisher_sampling"] = fisher_sampling_leg(torch, pes, 1024, 1000)

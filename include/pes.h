@@ -150,16 +150,27 @@ int pes_loglike(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void
  * with the same arguments, kernels and results, whose workspace is a 64 MiB
  * device array of the library (one per GPU, held until the process ends)
  * instead of the context's; it calls no allocator.  A batch needs, rounded up
- * to 256 bytes per part, 2304 B (walker table) + 12 B (plan) per walker plus
- * 16 B per walker per bin tile (ceil(n_bins / (256 x bins per lane)) tiles):
- * about 990 walkers at 2^20 bins and one bin per lane, about 15000 at 32703
- * bins.  PES_ESHAPE (message in pes_last_error) for a larger batch, PES_EHIP
+ * to 256 bytes per part, 3456 B (walker tables, FP64 and FP32) + 12 B (plan)
+ * per walker plus 16 B per walker per bin tile (ceil(n_bins / (256 x bins per
+ * lane)) tiles): about 970 walkers at 2^20 bins and one bin per lane, about
+ * 12000 at 32703 bins.  PES_ESHAPE (message in pes_last_error) for a larger batch, PES_EHIP
  * if the array has no address on the context's device; otherwise as
  * pes_loglike.  Every call on one GPU works in that GPU's single array: calls
  * that overlap in time on one GPU (other streams, other contexts, other
  * threads) race and must be serialized by the caller.  No state carries from
  * one call to the next (each call writes every scratch entry it reads). */
 int pes_loglike_noalloc(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void* stream);
+
+/* Arithmetic of pes_loglike and pes_response (and of the sampler's
+ * likelihood): bits = 64 (default) evaluates everything in FP64; bits = 32
+ * keeps in FP64 only what needs more than 24 bits -- each mode's SPA phase
+ * and t_f series (eq. eq_tf), f t_c, the cutoff test, the exact removal of
+ * whole cycles before every sine and cosine, and the noise-weighted inner
+ * products -- and evaluates the amplitudes, orbits, projections, link
+ * transfer functions (eq. eq_fd_resp) and TDI combinations in FP32 with FP32
+ * fits (the paper compares both precisions, Sec. 3.1, Fig. fig_cost).
+ * Gradients and Fisher matrices stay FP64.  PES_EINVAL for other values. */
+int pes_set_precision(pes_ctx* ctx, int bits);
 
 /* Gradient of log L with respect to theta (Sec. 2.3 differentiates the
  * response in reverse mode): logl (dev) [B] (may be NULL), grad (dev) [B][11]

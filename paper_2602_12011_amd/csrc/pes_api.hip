@@ -64,7 +64,8 @@ struct pes_ctx {
   bool long_sinc = false;   // a detector's largest sinc argument exceeds the short fit
   int wg = 16;              // walkers per work item
   int bpc = 0;              // resident blocks per CU requested (0: occupancy limit)
-  int occ[3] = {1, 1, 1};   // occupancy limit per bins-per-lane variant
+  int occ[2][3] = {{1, 1, 1}, {1, 1, 1}};   // occupancy limit per precision (FP64, FP32) and bins per lane
+  bool f32 = false;         // single-precision log-likelihood and response kernels
   int tile = 256;
   int grad_method = PES_GRAD_ADJOINT;
   int schedule = PES_SCHED_QUEUE;
@@ -74,6 +75,7 @@ struct pes_ctx {
   // workspace
   int64_t cap = 0;
   double* wtab = nullptr;
+  float* wtab32 = nullptr;    // FP32 copy of wtab (single-precision kernels)
   int* ntiles = nullptr;
   int* perm = nullptr;
   int* gstart = nullptr;
@@ -114,12 +116,14 @@ bool mode_ok(int l, int m) {
 
 void free_workspace(pes_ctx* c) {
   (void)hipFree(c->wtab);
+  (void)hipFree(c->wtab32);
   (void)hipFree(c->ntiles);
   (void)hipFree(c->perm);
   (void)hipFree(c->gstart);
   (void)hipFree(c->counters);
   (void)hipFree(c->partial);
   c->wtab = nullptr;
+  c->wtab32 = nullptr;
   c->ntiles = c->perm = c->gstart = c->counters = nullptr;
   c->partial = nullptr;
   c->cap = 0;
@@ -131,6 +135,7 @@ int ensure_workspace(pes_ctx* c, int64_t B) {
   free_workspace(c);
   const int64_t ng = (cap + 1) / 1 + 1;  // groups <= walkers
   if (hipMalloc(&c->wtab, sizeof(double) * cap * W_STRIDE) != hipSuccess ||
+      hipMalloc(&c->wtab32, sizeof(float) * cap * W_STRIDE) != hipSuccess ||
       hipMalloc(&c->ntiles, sizeof(int) * cap) != hipSuccess ||
       hipMalloc(&c->perm, sizeof(int) * cap) != hipSuccess ||
       hipMalloc(&c->gstart, sizeof(int) * (ng + 1)) != hipSuccess ||
@@ -305,8 +310,8 @@ int pes_create(const pes_config* cfg, pes_ctx** out) {
   c->tile = 256 * c->bpl;
   c->ntmax = (int)((c->N + c->tile - 1) / c->tile);
   c->ntmax_alloc = (int)((c->N + 255) / 256);
-  c->occ[1] = std::max(1, loglike_blocks_per_cu(1, c->long_sinc));
-  c->occ[2] = std::max(1, loglike_blocks_per_cu(2, c->long_sinc));
+  for (int p = 0; p < 2; ++p)
+    for (int bpl = 1; bpl <= 2; ++bpl) c->occ[p][bpl] = std::max(1, loglike_blocks_per_cu(bpl, c->long_sinc, p == 1));
   const int64_t nb = (c->N + 255) / 256;
   if (hipMalloc(&c->bins, sizeof(double) * B_NFIELDS * c->N) != hipSuccess ||
       hipMalloc(&c->tabs, sizeof(double) * T_NFIELDS * c->N * cfg->n_det) != hipSuccess ||
@@ -395,7 +400,7 @@ int pes_get_tuning(pes_ctx* c, int* bins_per_lane, int* walkers_per_group, int* 
   if (!c || !bins_per_lane || !walkers_per_group || !blocks_per_cu) return PES_EINVAL;
   *bins_per_lane = c->bpl;
   *walkers_per_group = c->wg;
-  *blocks_per_cu = c->bpc > 0 ? std::min(c->bpc, c->occ[c->bpl]) : c->occ[c->bpl];
+  *blocks_per_cu = c->bpc > 0 ? std::min(c->bpc, c->occ[c->f32][c->bpl]) : c->occ[c->f32][c->bpl];
   return PES_OK;
 }
 
@@ -443,7 +448,7 @@ int pes_autotune(pes_ctx* c, const double* theta, int64_t B, double* logl, doubl
   for (int ib = 0; ib < 2 && st == PES_OK; ++ib)
     for (int iw = 0; iw < 4 && st == PES_OK; ++iw)
       for (int half = 0; half < 2 && st == PES_OK; ++half) {
-        const int occ = c->occ[bpls[ib]];
+        const int occ = c->occ[c->f32][bpls[ib]];
         const int bpc = half ? std::max(1, occ / 2) : 0;
         if (half && bpc == occ) continue;
         pes_set_tuning(c, bpls[ib], wgs[iw], bpc);
@@ -511,10 +516,11 @@ int pes_probe(pes_ctx* c, const double* theta, int64_t B, int stage, double* out
   if (st != PES_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, setup_args(c), s));
-  ResponseArgs ra;
+  ResponseArgs ra;   // the stage probes evaluate in FP64 whatever the precision setting
   ra.bins = c->bins;
   ra.tabs = c->tabs;
   ra.wtab = c->wtab;
+  ra.wtab32 = nullptr;
   ra.out = out;
   ra.N = c->N;
   ra.n_modes = c->cfg.n_modes;
@@ -532,17 +538,19 @@ int pes_response(pes_ctx* c, const double* theta, int64_t B, double* out, void* 
   if (st != PES_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, setup_args(c), s));
+  if (c->f32) PES_HIP(c, launch_table32(c->wtab, B, c->wtab32, s));
   ResponseArgs ra;
   ra.bins = c->bins;
   ra.tabs = c->tabs;
   ra.wtab = c->wtab;
+  ra.wtab32 = c->f32 ? c->wtab32 : nullptr;
   ra.out = out;
   ra.N = c->N;
   ra.n_modes = c->cfg.n_modes;
   ra.plan = c->plan;
   ra.n_det = c->cfg.n_det;
   ra.dt = c->dt;
-  PES_HIP(c, launch_response(ra, B, c->long_sinc, s));
+  PES_HIP(c, launch_response(ra, B, c->long_sinc, c->f32, s));
   return PES_OK;
 }
 
@@ -553,6 +561,7 @@ namespace {
 // Device buffers one log-likelihood launch sequence works in.
 struct LoglikeWork {
   double* wtab;
+  float* wtab32;
   int* ntiles;
   int* perm;
   int* gstart;
@@ -583,11 +592,13 @@ int run_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, const 
   SetupArgs sa = setup_args(c);
   sa.full_tiles = grid_mode ? 1 : 0;
   PES_HIP(c, launch_setup(theta, B, ws.wtab, ws.ntiles, sa, s));
+  if (c->f32) PES_HIP(c, launch_table32(ws.wtab, B, ws.wtab32, s));
   PES_HIP(c, launch_plan(ws.ntiles, (int)B, c->wg, c->ntmax, !grid_mode, ws.perm, ws.gstart, ws.counters, s));
   LoglikeArgs a;
   a.bins = c->bins;
   a.tabs = c->tabs;
   a.wtab = ws.wtab;
+  a.wtab32 = ws.wtab32;
   a.ntiles = ws.ntiles;
   a.perm = ws.perm;
   a.gstart = ws.gstart;
@@ -602,14 +613,14 @@ int run_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, const 
   a.plan = c->plan;
   a.n_det = c->cfg.n_det;
   a.dt = c->dt;
-  const int bpc = c->bpc > 0 ? std::min(c->bpc, c->occ[c->bpl]) : c->occ[c->bpl];
+  const int bpc = c->bpc > 0 ? std::min(c->bpc, c->occ[c->f32][c->bpl]) : c->occ[c->f32][c->bpl];
   // persistent grid: the resident blocks, but never more than the items can be
   const int grid = grid_mode ? (int)(n_groups * c->ntmax)
                              : (int)std::min<int64_t>((int64_t)c->n_cu * bpc, n_groups * c->ntmax);
   a.grid_mode = grid_mode ? 1 : 0;
   const bool rec = c->timing && c->n_ev < kMaxEv;
   if (rec) PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev], s));
-  PES_HIP(c, launch_loglike(a, c->bpl, c->long_sinc, grid, s));
+  PES_HIP(c, launch_loglike(a, c->bpl, c->long_sinc, c->f32, grid, s));
   if (rec) {
     PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev + 1], s));
     ++c->n_ev;
@@ -630,7 +641,7 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
   if (st != PES_OK) return st;
   st = ensure_workspace(c, B);
   if (st != PES_OK) return st;
-  const LoglikeWork ws{c->wtab, c->ntiles, c->perm, c->gstart, c->counters, c->partial};
+  const LoglikeWork ws{c->wtab, c->wtab32, c->ntiles, c->perm, c->gstart, c->counters, c->partial};
   return run_loglike(c, theta, B, logl, ws, (hipStream_t)stream);
 }
 
@@ -645,13 +656,15 @@ static int64_t carve_loglike_work(char* base, int64_t B, int ntmax, LoglikeWork*
     return p;
   };
   char* wtab = take(sizeof(double) * B * W_STRIDE);
+  char* wtab32 = take(sizeof(float) * B * W_STRIDE);
   char* ntiles = take(sizeof(int) * B);
   char* perm = take(sizeof(int) * B);
   char* gstart = take(sizeof(int) * (B + 3));
   char* counters = take(sizeof(int) * 4);
   char* partial = take(sizeof(double) * 2 * B * (int64_t)ntmax);
   if (ws)
-    *ws = LoglikeWork{(double*)wtab, (int*)ntiles, (int*)perm, (int*)gstart, (int*)counters, (double*)partial};
+    *ws = LoglikeWork{(double*)wtab,  (float*)wtab32,   (int*)ntiles,   (int*)perm,
+                      (int*)gstart,   (int*)counters,   (double*)partial};
   return off;
 }
 
@@ -700,6 +713,12 @@ int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* g
   PES_HIP(c, launch_setup_tan(theta, B, c->wtab, c->wtan, c->ntiles, setup_args(c), s));
   PES_HIP(c, launch_grad(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, c->dd, jac_args(c, B, kGradTile),
                          c->long_sinc, c->grad_method == PES_GRAD_ADJOINT, logl, grad, s));
+  return PES_OK;
+}
+
+int pes_set_precision(pes_ctx* c, int bits) {
+  if (!c || (bits != 32 && bits != 64)) return PES_EINVAL;
+  c->f32 = bits == 32;
   return PES_OK;
 }
 

@@ -7,6 +7,7 @@
 
 #include "../../include/pes.h"
 #include "pes_eval.hpp"
+#include "pes_eval32.hpp"
 #include "pes_launch.hpp"
 
 namespace pes {
@@ -545,7 +546,7 @@ __global__ void __launch_bounds__(1024) plan_kernel(const int* __restrict__ ntil
 // ticket.  Lanes own bins; the walkers of the group are processed in turn,
 // each lane evaluating its bins, then a wavefront reduction and one LDS slot
 // per (walker, wave).  partial[w][tile] = (<d|h>, <h|h>) of that tile.
-template <int BPL, bool LS>
+template <int BPL, bool LS, bool F32>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     loglike_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                    const double* __restrict__ wtab, const int* __restrict__ ntiles,
@@ -621,9 +622,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
         double dh = 0.0, hh = 0.0;
 #pragma unroll
         for (int q = 0; q < BPL; ++q) {
-          const Chan c = (P.kind == 2)
-                             ? eval_channels_cls<true, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
-                             : eval_channels_cls<false, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
+          Chan c;
+          if constexpr (F32) {
+            const float* __restrict__ ws = A.wtab32 + (int64_t)w * W_STRIDE;
+            const ChanT<float> cf =
+                (P.kind == 2)
+                    ? eval_channels_f32_cls<true, LS>(cls[q], wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br[q],
+                                                      (float)aa[q], (float)zr[q], (float)zi[q])
+                    : eval_channels_f32_cls<false, LS>(cls[q], wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br[q],
+                                                       (float)aa[q], (float)zr[q], (float)zi[q]);
+            c = Chan{cf.ar, cf.ai, cf.er, cf.ei, cf.tr, cf.ti};
+          } else {
+            c = (P.kind == 2)
+                    ? eval_channels_cls<true, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
+                    : eval_channels_cls<false, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
+          }
           dh = fma(dar[q], c.ar, dh);
           dh = fma(dai[q], c.ai, dh);
           dh = fma(der[q], c.er, dh);
@@ -707,7 +720,7 @@ __global__ void __launch_bounds__(kFinW * kFinP)
 
 // ---------------------------------------------------------------- response
 // out[b][det][c][k] = n_c G(f_k) C''_c for one walker per blockIdx.y.
-template <bool LS>
+template <bool LS, bool F32>
 __global__ void response_kernel(ResponseArgs A) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t b = blockIdx.y;
@@ -726,10 +739,19 @@ __global__ void response_kernel(ResponseArgs A) {
     const DetParams& P = A.dt.p[det];
     Chan c = {0, 0, 0, 0, 0, 0};
     if (valid) {
-      c = (P.kind == 2) ? eval_channels<true, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
-                                              tb[T_ZR * N + k], tb[T_ZI * N + k])
-                        : eval_channels<false, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
-                                               tb[T_ZR * N + k], tb[T_ZI * N + k]);
+      if constexpr (F32) {
+        const float* __restrict__ ws = A.wtab32 + b * W_STRIDE;
+        const float a = (float)tb[T_A * N + k], zr = (float)tb[T_ZR * N + k], zi = (float)tb[T_ZI * N + k];
+        const ChanT<float> cf =
+            (P.kind == 2) ? eval_channels_f32<true, LS, 1>(wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi)
+                          : eval_channels_f32<false, LS, 1>(wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi);
+        c = Chan{cf.ar, cf.ai, cf.er, cf.ei, cf.tr, cf.ti};
+      } else {
+        c = (P.kind == 2) ? eval_channels<true, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+                                                tb[T_ZR * N + k], tb[T_ZI * N + k])
+                          : eval_channels<false, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+                                                 tb[T_ZR * N + k], tb[T_ZI * N + k]);
+      }
     }
     const double Gr = tb[T_GR * N + k], Gi = tb[T_GI * N + k];
     const double nrm[3] = {0.70710678118654752440, 0.40824829046386301637, 0.57735026918962576451};
@@ -740,6 +762,12 @@ __global__ void response_kernel(ResponseArgs A) {
       o[1] = valid ? nrm[ch] * (Gr * ci[ch] + Gi * cr[ch]) : NAN;
     }
   }
+}
+
+// FP32 copy of the walker tables for the single-precision kernels.
+__global__ void table32_kernel(const double* __restrict__ wtab, int64_t n, float* __restrict__ wtab32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) wtab32[i] = (float)wtab[i];
 }
 
 // ---------------------------------------------------------------- stage probes
@@ -866,17 +894,32 @@ hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, bool sorted,
   return hipGetLastError();
 }
 
-template <int BPL, bool LS>
+template <int BPL, bool LS, bool F32>
 static void launch_ll(const LoglikeArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((loglike_kernel<BPL, LS>), dim3(grid), dim3(256), 0, s, a.bins, a.tabs, a.wtab,
+  hipLaunchKernelGGL((loglike_kernel<BPL, LS, F32>), dim3(grid), dim3(256), 0, s, a.bins, a.tabs, a.wtab,
                      a.ntiles, a.perm, a.gstart, a.counters, a.partial, a);
 }
 
-hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, int grid, hipStream_t s) {
+template <bool F32>
+static void launch_ll_f(const LoglikeArgs& a, int bpl, bool long_sinc, int grid, hipStream_t s) {
   if (bpl == 2)
-    long_sinc ? launch_ll<2, true>(a, grid, s) : launch_ll<2, false>(a, grid, s);
+    long_sinc ? launch_ll<2, true, F32>(a, grid, s) : launch_ll<2, false, F32>(a, grid, s);
   else
-    long_sinc ? launch_ll<1, true>(a, grid, s) : launch_ll<1, false>(a, grid, s);
+    long_sinc ? launch_ll<1, true, F32>(a, grid, s) : launch_ll<1, false, F32>(a, grid, s);
+}
+
+hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, bool f32, int grid, hipStream_t s) {
+  if (f32 && !a.wtab32) return hipErrorInvalidValue;   // the FP32 kernels read the FP32 walker tables
+  if (f32)
+    launch_ll_f<true>(a, bpl, long_sinc, grid, s);
+  else
+    launch_ll_f<false>(a, bpl, long_sinc, grid, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_table32(const double* wtab, int64_t B, float* wtab32, hipStream_t s) {
+  const int64_t n = B * W_STRIDE;
+  hipLaunchKernelGGL(table32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, wtab, n, wtab32);
   return hipGetLastError();
 }
 
@@ -897,26 +940,39 @@ hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, int st
   return hipGetLastError();
 }
 
-hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, hipStream_t s) {
+hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, bool f32, hipStream_t s) {
+  if (f32 && !a.wtab32) return hipErrorInvalidValue;   // the FP32 kernel reads the FP32 walker tables
   const int bs = 256;
   const dim3 grid((unsigned)((a.N + bs - 1) / bs), (unsigned)B);
-  if (long_sinc)
-    hipLaunchKernelGGL(response_kernel<true>, grid, dim3(bs), 0, s, a);
-  else
-    hipLaunchKernelGGL(response_kernel<false>, grid, dim3(bs), 0, s, a);
+  if (f32) {
+    if (long_sinc)
+      hipLaunchKernelGGL((response_kernel<true, true>), grid, dim3(bs), 0, s, a);
+    else
+      hipLaunchKernelGGL((response_kernel<false, true>), grid, dim3(bs), 0, s, a);
+  } else {
+    if (long_sinc)
+      hipLaunchKernelGGL((response_kernel<true, false>), grid, dim3(bs), 0, s, a);
+    else
+      hipLaunchKernelGGL((response_kernel<false, false>), grid, dim3(bs), 0, s, a);
+  }
   return hipGetLastError();
 }
 
-int loglike_blocks_per_cu(int bpl, bool long_sinc) {
+template <bool F32>
+static int blocks_per_cu(int bpl, bool long_sinc) {
   int nb = 0;
   hipError_t e;
   if (bpl == 2)
-    e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2, true>, 256, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2, false>, 256, 0);
+    e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2, true, F32>, 256, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2, false, F32>, 256, 0);
   else
-    e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, true>, 256, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, false>, 256, 0);
+    e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, true, F32>, 256, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, false, F32>, 256, 0);
   return e == hipSuccess ? nb : 1;
+}
+
+int loglike_blocks_per_cu(int bpl, bool long_sinc, bool f32) {
+  return f32 ? blocks_per_cu<true>(bpl, long_sinc) : blocks_per_cu<false>(bpl, long_sinc);
 }
 
 }  // namespace pes

@@ -27,6 +27,7 @@ struct LoglikeArgs {
   const double* bins;
   const double* tabs;
   const double* wtab;
+  const float* wtab32;   // FP32 copy of the walker tables (single-precision kernels only)
   const int* ntiles;
   const int* perm;
   const int* gstart;
@@ -43,6 +44,7 @@ struct ResponseArgs {
   const double* bins;
   const double* tabs;
   const double* wtab;
+  const float* wtab32;   // FP32 copy of the walker tables (single-precision kernels only)
   double* out;
   int64_t N;
   int n_modes, n_det;
@@ -75,11 +77,12 @@ hipError_t launch_setup_tan(const double* theta, int64_t B, double* wtab, double
                             const SetupArgs& sa, hipStream_t s);
 hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, bool sorted, int* perm, int* gstart,
                        int* counters, hipStream_t s);
-hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, int grid, hipStream_t s);
+hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, bool f32, int grid, hipStream_t s);
+hipError_t launch_table32(const double* wtab, int64_t B, float* wtab32, hipStream_t s);
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
                            int64_t B, double* logl, hipStream_t s);
 hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, int stage, hipStream_t s);
-hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, hipStream_t s);
-int loglike_blocks_per_cu(int bpl, bool long_sinc);
+hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, bool f32, hipStream_t s);
+int loglike_blocks_per_cu(int bpl, bool long_sinc, bool f32);
 
 }  // namespace pes

@@ -56,6 +56,46 @@ __device__ __forceinline__ void sincos_small(double x, double& s, double& c) {
   c = horner(kCosSmall, t);
 }
 
+// ---- FP32 versions for the single-precision log-likelihood kernel (fits at
+// FP32 accuracy, fewer terms).
+template <int N>
+__device__ __forceinline__ float horner(const float (&c)[N], float t) {
+  float p = c[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) p = fmaf(p, t, c[i]);
+  return p;
+}
+
+// sin(2 pi x), cos(2 pi x) for x in cycles given as the FP32 residue r of an
+// exact FP64 reduction (|r| <= 1/2): quadrant and polynomial as in the FP64
+// version.
+__device__ __forceinline__ void sincos_rev_f(float r, float& s, float& c) {
+  const float q = rintf(4.0f * r);
+  const float y = fmaf(-0.25f, q, r);
+  const float t = y * y;
+  const float sy = y * horner(kSin2piF, t);
+  const float cy = horner(kCos2piF, t);
+  const float aq = fabsf(q);
+  const float cq = 1.0f - aq;
+  const float sq = q * (2.0f - aq);
+  s = fmaf(sy, cq, cy * sq);
+  c = fmaf(cy, cq, -(sy * sq));
+}
+// The same for any FP64 argument: the integer part is removed exactly in FP64.
+__device__ __forceinline__ void sincos_cycles_f(double x, float& s, float& c) {
+  sincos_rev_f((float)(x - rint(x)), s, c);
+}
+template <bool LONG>
+__device__ __forceinline__ float sinc_f(float b) {
+  const float t = b * b;
+  return LONG ? horner(kSincLongF, t) : horner(kSincShortF, t);
+}
+__device__ __forceinline__ void sincos_small_f(float x, float& s, float& c) {
+  const float t = x * x;
+  s = x * horner(kSinSmallF, t);
+  c = horner(kCosSmallF, t);
+}
+
 // Derivative-carrying versions for the tangent (forward-mode) kernels.
 template <int N> struct Dual;
 

@@ -71,6 +71,7 @@ def lib():
         L.pes_fisher.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.pes_set_grad_method.argtypes = [vp, C.c_int]
         L.pes_set_schedule.argtypes = [vp, C.c_int]
+        L.pes_set_precision.argtypes = [vp, C.c_int]
         L.pes_noise.argtypes = [vp, C.c_uint64, vp, vp]
         L.pes_probe.argtypes = [vp, vp, C.c_int64, C.c_int, vp, vp]
         L.pes_sampler_set_step.argtypes = [vp, C.c_uint64]
@@ -116,7 +117,7 @@ def lib():
         for name in ("pes_create", "pes_destroy", "pes_reserve", "pes_set_data",
                      "pes_response", "pes_loglike", "pes_loglike_noalloc", "pes_timing", "pes_timing_read",
                      "pes_set_tuning", "pes_get_tuning", "pes_autotune", "pes_grad", "pes_set_grad_method",
-                     "pes_set_schedule", "pes_noise", "pes_probe", "pes_sampler_set_step",
+                     "pes_set_schedule", "pes_set_precision", "pes_noise", "pes_probe", "pes_sampler_set_step",
                      "pes_flow_create", "pes_flow_destroy", "pes_flow_set_params", "pes_flow_get_params",
                      "pes_flow_set_norm", "pes_flow_set_affine", "pes_flow_get_affine", "pes_flow_set_temperature", "pes_flow_forward", "pes_flow_inverse",
                      "pes_flow_nll_grad", "pes_flow_probe", "pes_flow_adam_step", "pes_flow_fit", "pes_sampler_set_flow",
@@ -308,6 +309,11 @@ class Context:
         (plain grid over every tile, batch order)."""
         code = {"queue": SCHED_QUEUE, "grid": SCHED_GRID}[schedule]
         self._check(lib().pes_set_schedule(self.h, code), "pes_set_schedule")
+
+    def set_precision(self, bits):
+        """64 (default) or 32: the arithmetic of loglike and response (see
+        pes_set_precision)."""
+        self._check(lib().pes_set_precision(self.h, int(bits)), "pes_set_precision")
 
     def set_grad_method(self, method):
         """"adjoint" (reverse sweep, the default) or "forward" (tangents)."""

@@ -16,6 +16,9 @@ def _tables():
     text = open(POLY).read()
     arrays = {m.group(1): [float(x) for x in m.group(3).replace("\n", " ").split(",") if x.strip()]
               for m in re.finditer(r"constexpr double (\w+)\[(\d+)\] = \{([^}]*)\}", text)}
+    arrays.update({m.group(1): [float(x.strip().rstrip("f")) for x in m.group(3).replace("\n", " ").split(",")
+                                if x.strip()]
+                   for m in re.finditer(r"constexpr float (\w+)\[(\d+)\] = \{([^}]*)\}", text)})
     scalars = {m.group(1): float(m.group(2))
                for m in re.finditer(r"constexpr double (\w+) = ([-+0-9.eE]+);", text)}
     return arrays, scalars
@@ -64,3 +67,33 @@ def test_short_range_class_is_narrower():
     assert X_SMALL0 ** 2 <= SCAL["kSmallTMax"]
     assert len(ARR["kSincC0"]) < len(ARR["kSincShort"])
     assert len(ARR["kSinSmallC0"]) < len(ARR["kSinSmall"])
+
+
+# FP32 tables of the single-precision kernels: evaluated by the same Horner
+# scheme in float32 (coefficients rounded to float32 as the device holds them)
+CASES_F32 = [
+    ("kSin2piF", lambda y: mp.sin(2 * mp.pi * y) / y, 0.125),
+    ("kCos2piF", lambda y: mp.cos(2 * mp.pi * y), 0.125),
+    ("kSincShortF", lambda b: mp.sin(b) / b, math.sqrt(SCAL["kSincShortTMax"])),
+    ("kSincLongF", lambda b: mp.sin(b) / b, math.sqrt(SCAL["kSincLongTMax"])),
+    ("kSinSmallF", lambda x: mp.sin(x) / x, math.sqrt(SCAL["kSmallTMax"])),
+    ("kCosSmallF", lambda x: mp.cos(x), math.sqrt(SCAL["kSmallTMax"])),
+    ("kSincC0F", lambda b: mp.sin(b) / b, SCAL["kClassBMax0"]),
+    ("kSinSmallC0F", lambda x: mp.sin(x) / x, X_SMALL0),
+    ("kCosSmallC0F", lambda x: mp.cos(x), X_SMALL0),
+]
+
+
+@pytest.mark.parametrize("name,fn,vmax", CASES_F32, ids=[c[0] for c in CASES_F32])
+def test_fit_accuracy_f32(name, fn, vmax):
+    v = np.linspace(vmax * 1e-6, vmax, 2001).astype(np.float32)
+    c = np.asarray(ARR[name], dtype=np.float32)
+    t = v * v
+    acc = np.full_like(t, c[0])
+    for k in c[1:]:
+        acc = (acc * t + k).astype(np.float32)
+    ref = np.array([float(fn(mp.mpf(float(x)))) for x in v])
+    err = np.max(np.abs(acc.astype(np.float64) - ref)) / np.max(np.abs(ref))
+    # fit error (<= 3e-8) plus the rounding of a float32 Horner evaluation
+    assert err < 4e-7, (name, err)
+    assert len(ARR[name]) < len(ARR[name[:-1]])    # fewer terms than the FP64 fit of the same function
