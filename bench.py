@@ -117,7 +117,7 @@ def algorithmic_flops(cfg, theta):
 
 
 KERNEL_SOURCES = ("pes_eval.hpp", "pes_kernels.hip", "pes_math.hpp", "pes_poly.hpp",
-                  "pes_layout.hpp", "pes_launch.hpp")
+                  "pes_layout.hpp", "pes_launch.hpp", "pes_eval32.hpp")
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "loglike_kernel_cfg1_counters.md")
 
 

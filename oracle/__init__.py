@@ -36,7 +36,7 @@ class Detector(C.Structure):
     _fields_ = [("kind", C.c_int), ("tdi_gen", C.c_int), ("arm_m", C.c_double),
                 ("phase0", C.c_double), ("tq_period_s", C.c_double),
                 ("tq_lon", C.c_double), ("tq_lat", C.c_double),
-                ("oms_asd", C.c_double), ("acc_asd", C.c_double)]
+                ("oms_asd", C.c_double), ("acc_asd", C.c_double), ("orbit", C.c_int)]
 
 
 class Config(C.Structure):
@@ -86,11 +86,13 @@ def _f64(a):
 
 def make_detector(d):
     """dict -> Detector.  Keys: kind ('lisa'|'taiji'|'tianqin'), arm_m,
-    phase0, tdi_gen, oms_asd, acc_asd, and for TianQin tq_period_s, tq_lon, tq_lat."""
+    phase0, tdi_gen, oms_asd, acc_asd, for TianQin tq_period_s, tq_lon, tq_lat,
+    and orbit ('first_order', the default, or 'kepler': exact ellipses)."""
     return Detector(KIND[d["kind"]], int(d.get("tdi_gen", 20)), float(d["arm_m"]),
                     float(d.get("phase0", 0.0)), float(d.get("tq_period_s", 0.0)),
                     float(d.get("tq_lon", 0.0)), float(d.get("tq_lat", 0.0)),
-                    float(d["oms_asd"]), float(d["acc_asd"]))
+                    float(d["oms_asd"]), float(d["acc_asd"]),
+                    {"first_order": 0, "kepler": 1}[d.get("orbit", "first_order")])
 
 
 def make_config(cfg):

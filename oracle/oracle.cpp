@@ -338,7 +338,8 @@ ModeVal<T> mode_eval(const Source<T>& s, int l, int m, const T& f) {
 // them).  Heliocentric: the first-order-in-eccentricity Keplerian orbit of
 // three spacecraft, e = L/(2 sqrt(3) AU), guiding centre at 1 AU with
 // revolution phase alpha = 2 pi t / yr + phase0; this triangle is exactly
-// equilateral with side L.  Geocentric: a ring of radius L/sqrt(3) about the
+// equilateral with side L.  With orbit = 1 the same three Kepler ellipses
+// exactly (the arms then flex at order e^2 AU).  Geocentric: a ring of radius L/sqrt(3) about the
 // Earth (circular 1-AU orbit), normal to (tq_lon, tq_lat), period tq_period_s.
 // Output in light-seconds.
 template <class T>
@@ -364,6 +365,32 @@ void orbit(const or_detector& d, const T& t, T x[3][3]) {
     return;
   }
   const T e = K<T>((long double)d.arm_m / (2.0L * sqrtl(3.0L) * kAU));
+  if (d.orbit == 1) {
+    // Exact Kepler ellipses with the elements whose first-order expansion in
+    // e is the triangle below: semi-major axis 1 AU (period 1 yr), eccentricity
+    // e, inclination sin(i) = sqrt(3) e = L / (2 AU), longitude of perihelion
+    // b_n = 2 pi n / 3, ascending node b_n + pi/2 (argument of perihelion
+    // -pi/2); mean anomaly alpha - b_n.  Kepler's equation E - e sin E = M by
+    // Newton's method to the working precision.
+    using std::fabs;
+    const T si = sqrt(K<T>(3)) * e, ci = sqrt(K<T>(1) - si * si);
+    const T sq = sqrt(K<T>(1) - e * e);
+    for (int n = 0; n < 3; ++n) {
+      const T b = K<T>(2.0L * kPi * n / 3.0L);
+      const T M = alpha - b;
+      T E = M + e * sin(M);
+      for (int it = 0; it < 8; ++it) E = E - (E - e * sin(E) - M) / (K<T>(1) - e * cos(E));
+      const T xo = AUc * (cos(E) - e), yo = AUc * sq * sin(E);
+      // argument of perihelion -pi/2: (xo, yo) -> (yo, -xo) in the orbital plane
+      const T u = yo, v = -xo;
+      const T Om = b + K<T>(0.5L * kPi);
+      const T cO = cos(Om), sO = sin(Om);
+      x[n][0] = u * cO - v * ci * sO;
+      x[n][1] = u * sO + v * ci * cO;
+      x[n][2] = v * si;
+    }
+    return;
+  }
   for (int n = 0; n < 3; ++n) {
     const T b = K<T>(2.0L * kPi * n / 3.0L);
     x[n][0] = AUc * cos(alpha) + K<T>(0.5L) * e * AUc * (cos(K<T>(2) * alpha - b) - K<T>(3) * cos(b));
@@ -376,16 +403,26 @@ void orbit(const or_detector& d, const T& t, T x[3][3]) {
 // eq. (eq_fd_resp): y_rs(f) = -i pi f L sinc[pi f L (1 - k.n_rs)]
 //   exp{-i pi f [L + k.(x_r + x_s)]} n_rs . h(f) . n_rs, n_rs = (x_r - x_s)/L,
 // added into y[r][s] for every ordered pair r != s.
+// With unit = true the link direction is the unit vector of the actual
+// separation (exact orbits, whose arms flex); the transfer function keeps the
+// nominal L (the paper evaluates the response on the rigid equilateral
+// approximation and lets the flexing enter only the laser-noise TDI).
 template <class T>
 void add_links(const T& f, const T& L, const T k[3], const T x[3][3], const Cx<T> H[3][3],
-               Cx<T> y[3][3]) {
-  using std::sin;
+               Cx<T> y[3][3], bool unit = false) {
+  using std::sin; using std::sqrt;
   const T pi = K<T>(kPi);
   for (int r = 0; r < 3; ++r)
     for (int s = 0; s < 3; ++s) {
       if (r == s) continue;
       T n[3];
-      for (int i = 0; i < 3; ++i) n[i] = (x[r][i] - x[s][i]) / L;
+      T Ln = L;
+      if (unit) {
+        T d2 = K<T>(0);
+        for (int i = 0; i < 3; ++i) d2 = d2 + (x[r][i] - x[s][i]) * (x[r][i] - x[s][i]);
+        Ln = sqrt(d2);
+      }
+      for (int i = 0; i < 3; ++i) n[i] = (x[r][i] - x[s][i]) / Ln;
       T kn = K<T>(0), kx = K<T>(0);
       for (int i = 0; i < 3; ++i) { kn = kn + k[i] * n[i]; kx = kx + k[i] * (x[r][i] + x[s][i]); }
       Cx<T> nhn;
@@ -443,7 +480,7 @@ void response_at(const Source<T>& s, const or_config& cfg, const or_detector& d,
       for (int j = 0; j < 3; ++j) H[i][j] = s.ep[i][j] * hp + s.ec[i][j] * hc;
     T x[3][3];
     orbit(d, mv.tf, x);
-    add_links(f, L, s.k, x, H, y);
+    add_links(f, L, s.k, x, H, y, d.kind != OR_TIANQIN && d.orbit == 1);
   }
   Cx<T> xyz[3];
   tdi(f, L, d.tdi_gen, y, xyz, aet);

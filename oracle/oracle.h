@@ -33,6 +33,7 @@ typedef struct {
   double tq_lat;       /* TianQin: ecliptic latitude of the plane normal [rad] */
   double oms_asd;      /* optical-metrology displacement ASD [m/sqrt(Hz)] */
   double acc_asd;      /* test-mass acceleration ASD [m/s^2/sqrt(Hz)] */
+  int orbit;           /* heliocentric kinds: 0 first order in eccentricity, 1 exact Kepler ellipses */
 } or_detector;
 
 typedef struct {
