@@ -448,6 +448,35 @@ def fp32_leg(torch, pes, steps, L64_ref=None):
                 median_rel_dev_from_fp64=float(f"{np.median(rel):.3e}"))
 
 
+def kepler_leg(torch, pes, steps):
+    """The headline workload with the heliocentric detector on exact Kepler
+    ellipses (arms flexing at order e^2 AU) instead of the first-order
+    triangle: evals/s at the autotuned tuning and the cost relative to the
+    first-order orbit in the same run."""
+    out = {}
+    for orbit in ("first_order", "kepler"):
+        cfg = W.config("cfg1")
+        cfg["detectors"] = [dict(d, orbit=orbit) for d in cfg["detectors"]]
+        B = cfg["walkers"]
+        dev = torch.device("cuda:0")
+        ctx = pes.Context(cfg)
+        ctx.reserve(B)
+        th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
+        ctx.set_data(ctx.response(th0)[0].clone())
+        theta = torch.from_numpy(W.draw_walkers(B, stream=1)).to(dev)
+        o = torch.empty(B, dtype=torch.float64, device=dev)
+        _, tuning = ctx.autotune(theta)
+        out[orbit] = dict(ms_per_call=round(_time_ms(torch, lambda: ctx.loglike(theta, o), steps), 3),
+                          tuning=tuning)
+        ctx.close()
+    k, f = out["kepler"], out["first_order"]
+    return dict(workload="LISA-like on exact Kepler ellipses, 5 modes, 2^20 bins (df=1/yr), 4096 walkers, "
+                         "noise-free injection",
+                ms_per_call=k["ms_per_call"], evals_per_s=round(4096 / (k["ms_per_call"] * 1e-3), 1),
+                tuning=k["tuning"], first_order_ms_per_call_same_run=f["ms_per_call"],
+                cost_over_first_order=round(k["ms_per_call"] / f["ms_per_call"], 3))
+
+
 EXTRINSIC = (7, 8, 9, 10)   # lambda, beta, psi, t_c
 
 
@@ -671,7 +700,7 @@ def main():
                     help="bins_per_lane,walkers_per_group,blocks_per_cu (skips the autotuner)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline measurement (no extra legs)")
-    ap.add_argument("--extras", default="derivatives,graph,config2,fp32,fisher_sampling,paper_pe,ess",
+    ap.add_argument("--extras", default="derivatives,graph,config2,fp32,kepler,fisher_sampling,paper_pe,ess",
                     help="comma list of the extra legs to run after the headline")
     ap.add_argument("--ess-walkers", type=int, default=16384)
     ap.add_argument("--ess-pilot", type=int, default=300)
@@ -773,6 +802,9 @@ def main():
     if "fp32" in extras:
         print("[bench] single precision", file=sys.stderr, flush=True)
         rec["fp32"] = fp32_leg(torch, pes, 10)
+    if "kepler" in extras:
+        print("[bench] exact Kepler orbits", file=sys.stderr, flush=True)
+        rec["kepler"] = kepler_leg(torch, pes, 10)
     if "fisher_sampling" in extras:
         print("[bench] Fisher vs sampling, extrinsic parameters", file=sys.stderr, flush=True)
         rec["fisher_sampling"] = fisher_sampling_leg(torch, pes, 1024, 1000)

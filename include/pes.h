@@ -50,6 +50,11 @@ typedef enum {
 } pes_status;
 
 enum { PES_LISA = 0, PES_TAIJI = 1, PES_TIANQIN = 2 };
+/* Heliocentric orbit model: the first-order-in-eccentricity Keplerian
+ * triangle (exactly equilateral), or the exact Kepler ellipses whose first
+ * order it is (arms flexing at order e^2 AU).  Sec. 2.1 names Keplerian
+ * heliocentric orbits. */
+enum { PES_ORBIT_FIRST_ORDER = 0, PES_ORBIT_KEPLER = 1 };
 
 typedef struct {
   int kind;            /* PES_LISA / PES_TAIJI: heliocentric orbit; PES_TIANQIN: geocentric */
@@ -61,6 +66,13 @@ typedef struct {
   double tq_lat;       /* TianQin: ecliptic latitude of the plane normal [rad] */
   double oms_asd;      /* optical-metrology noise ASD [m / sqrt(Hz)] */
   double acc_asd;      /* test-mass acceleration noise ASD [m s^-2 / sqrt(Hz)] */
+  int orbit;           /* PES_LISA / PES_TAIJI: PES_ORBIT_FIRST_ORDER or PES_ORBIT_KEPLER (every
+                          heliocentric detector of a context takes the same); TianQin: 0.
+                          With PES_ORBIT_KEPLER the link directions are the unit separations
+                          of the spacecraft at t_f, the transfer function and the TDI factor
+                          keep the nominal L; such a context evaluates log L and the response
+                          in FP64 (pes_grad, pes_fisher, pes_probe and pes_set_precision(32)
+                          return PES_EINVAL). */
 } pes_detector;
 
 typedef struct {

@@ -64,8 +64,10 @@ struct pes_ctx {
   bool long_sinc = false;   // a detector's largest sinc argument exceeds the short fit
   int wg = 16;              // walkers per work item
   int bpc = 0;              // resident blocks per CU requested (0: occupancy limit)
-  int occ[2][3] = {{1, 1, 1}, {1, 1, 1}};   // occupancy limit per precision (FP64, FP32) and bins per lane
+  int occ[3][3] = {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}};   // occupancy limit per variant (FP64, FP32, Kepler) and bins per lane
   bool f32 = false;         // single-precision log-likelihood and response kernels
+  bool kep = false;         // heliocentric detectors on exact Kepler ellipses
+  double* kep_tab = nullptr;  // [n_det][KV_STRIDE] orbit series (Kepler detectors)
   int tile = 256;
   int grad_method = PES_GRAD_ADJOINT;
   int schedule = PES_SCHED_QUEUE;
@@ -76,6 +78,7 @@ struct pes_ctx {
   int64_t cap = 0;
   double* wtab = nullptr;
   float* wtab32 = nullptr;    // FP32 copy of wtab (single-precision kernels)
+  double* wkep = nullptr;     // [cap][n_det][KW_STRIDE] projected orbit series (Kepler contexts)
   int* ntiles = nullptr;
   int* perm = nullptr;
   int* gstart = nullptr;
@@ -110,6 +113,9 @@ int fail_hip(pes_ctx* c, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return fail_hip((ctx), e_, #call); \
   } while (0)
 
+// Kernel variant of the log-likelihood: 0 FP64, 1 FP32, 2 FP64 on exact Kepler orbits.
+int occ_var(const pes_ctx* c) { return c->kep ? 2 : (c->f32 ? 1 : 0); }
+
 bool mode_ok(int l, int m) {
   return (l == 2 && (m == 2 || m == 1)) || (l == 3 && (m == 3 || m == 2)) || (l == 4 && m == 4);
 }
@@ -117,6 +123,7 @@ bool mode_ok(int l, int m) {
 void free_workspace(pes_ctx* c) {
   (void)hipFree(c->wtab);
   (void)hipFree(c->wtab32);
+  (void)hipFree(c->wkep);
   (void)hipFree(c->ntiles);
   (void)hipFree(c->perm);
   (void)hipFree(c->gstart);
@@ -124,6 +131,7 @@ void free_workspace(pes_ctx* c) {
   (void)hipFree(c->partial);
   c->wtab = nullptr;
   c->wtab32 = nullptr;
+  c->wkep = nullptr;
   c->ntiles = c->perm = c->gstart = c->counters = nullptr;
   c->partial = nullptr;
   c->cap = 0;
@@ -136,6 +144,7 @@ int ensure_workspace(pes_ctx* c, int64_t B) {
   const int64_t ng = (cap + 1) / 1 + 1;  // groups <= walkers
   if (hipMalloc(&c->wtab, sizeof(double) * cap * W_STRIDE) != hipSuccess ||
       hipMalloc(&c->wtab32, sizeof(float) * cap * W_STRIDE) != hipSuccess ||
+      (c->kep && hipMalloc(&c->wkep, sizeof(double) * cap * c->cfg.n_det * KW_STRIDE) != hipSuccess) ||
       hipMalloc(&c->ntiles, sizeof(int) * cap) != hipSuccess ||
       hipMalloc(&c->perm, sizeof(int) * cap) != hipSuccess ||
       hipMalloc(&c->gstart, sizeof(int) * (ng + 1)) != hipSuccess ||
@@ -219,6 +228,74 @@ void fill_geometry(const pes_detector& d, DetParams& p) {
   }
 }
 
+// Fourier series (harmonics 0..kKepH of the revolution phase alpha) of the
+// orbit vectors of a heliocentric detector on exact Kepler ellipses:
+// semi-major axis 1 AU, eccentricity e = L / (2 sqrt3 AU), inclination
+// sin i = sqrt3 e, longitude of perihelion b_n = 2 pi n / 3, ascending node
+// b_n + pi/2, mean anomaly alpha - b_n (the ellipses whose first-order
+// expansion in e is the triangle of fill_geometry).  Sampled at 64 phases in
+// long double (Kepler's equation by Newton's method) and transformed
+// exactly; the series converge as e^k, so harmonic 7 and up are below 1e-13 s.
+void kepler_table(const pes_detector& d, double* out) {
+  constexpr int NS = 64;
+  const long double PI = 3.14159265358979323846264338327950288L;
+  const long double R = (long double)kAU / (long double)kC;
+  const long double e = (long double)d.arm_m / (2.0L * sqrtl(3.0L) * (long double)kAU);
+  const long double si = sqrtl(3.0L) * e, ci = sqrtl(1.0L - si * si), sq = sqrtl(1.0L - e * e);
+  // samples: 15 vector components (Delta_0, Delta_1, x_0 - c, x_1 - c, c) and 3 inverse lengths
+  long double v[NS][18];
+  for (int j = 0; j < NS; ++j) {
+    const long double al = 2.0L * PI * j / NS;
+    long double x[3][3];
+    for (int n = 0; n < 3; ++n) {
+      const long double b = 2.0L * PI * n / 3.0L;
+      const long double M = al - b;
+      long double E = M + e * sinl(M);
+      for (int it = 0; it < 12; ++it) E -= (E - e * sinl(E) - M) / (1.0L - e * cosl(E));
+      const long double xo = R * (cosl(E) - e), yo = R * sq * sinl(E);
+      const long double u = yo, w = -xo;                 // argument of perihelion -pi/2
+      const long double Om = b + 0.5L * PI;
+      x[n][0] = u * cosl(Om) - w * ci * sinl(Om);
+      x[n][1] = u * sinl(Om) + w * ci * cosl(Om);
+      x[n][2] = w * si;
+    }
+    long double c[3], d0[3], d1[3], d2[3];
+    for (int k = 0; k < 3; ++k) {
+      c[k] = (x[0][k] + x[1][k] + x[2][k]) / 3.0L;
+      d0[k] = x[2][k] - x[1][k];
+      d1[k] = x[0][k] - x[2][k];
+      d2[k] = x[1][k] - x[0][k];
+    }
+    for (int k = 0; k < 3; ++k) {
+      v[j][k] = d0[k];
+      v[j][3 + k] = d1[k];
+      v[j][6 + k] = x[0][k] - c[k];
+      v[j][9 + k] = x[1][k] - c[k];
+      v[j][12 + k] = c[k];
+    }
+    const long double* dd[3] = {d0, d1, d2};
+    for (int t = 0; t < 3; ++t)
+      v[j][15 + t] = 1.0L / sqrtl(dd[t][0] * dd[t][0] + dd[t][1] * dd[t][1] + dd[t][2] * dd[t][2]);
+  }
+  for (int i = 0; i < KV_STRIDE; ++i) out[i] = 0.0;
+  for (int q = 0; q < 18; ++q) {
+    double* o = out + q * kKepT;   // 15 vector components, then the 3 inverse lengths (KV_INVL)
+    long double a0 = 0.0L;
+    for (int j = 0; j < NS; ++j) a0 += v[j][q];
+    o[0] = (double)(a0 / NS);
+    for (int h = 1; h <= kKepH; ++h) {
+      long double ac = 0.0L, as = 0.0L;
+      for (int j = 0; j < NS; ++j) {
+        const long double al = 2.0L * PI * j / NS;
+        ac += v[j][q] * cosl(h * al);
+        as += v[j][q] * sinl(h * al);
+      }
+      o[2 * h - 1] = (double)(2.0L * ac / NS);
+      o[2 * h] = (double)(2.0L * as / NS);
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -280,13 +357,23 @@ int pes_create(const pes_config* cfg, pes_ctx** out) {
   for (int i = 0; i < cfg->n_det; ++i) {
     const pes_detector& d = cfg->det[i];
     if (d.kind < 0 || d.kind > 2 || (d.tdi_gen != 15 && d.tdi_gen != 20) || !(d.arm_m > 0) ||
-        !(d.oms_asd >= 0) || !(d.acc_asd >= 0) || (d.kind == PES_TIANQIN && !(d.tq_period_s > 0)))
+        !(d.oms_asd >= 0) || !(d.acc_asd >= 0) || (d.kind == PES_TIANQIN && !(d.tq_period_s > 0)) ||
+        (d.orbit != PES_ORBIT_FIRST_ORDER && d.orbit != PES_ORBIT_KEPLER) ||
+        (d.kind == PES_TIANQIN && d.orbit != PES_ORBIT_FIRST_ORDER))
       return PES_EINVAL;
   }
+  // every heliocentric detector of a context takes the same orbit model
+  bool any_kep = false, any_first = false;
+  for (int i = 0; i < cfg->n_det; ++i) {
+    if (cfg->det[i].kind == PES_TIANQIN) continue;
+    (cfg->det[i].orbit == PES_ORBIT_KEPLER ? any_kep : any_first) = true;
+  }
+  if (any_kep && any_first) return PES_EINVAL;
   pes_ctx* c = new (std::nothrow) pes_ctx();
   if (!c) return PES_ENOMEM;
   c->cfg = *cfg;
   c->N = cfg->n_bins;
+  c->kep = any_kep;
   if (hipGetDevice(&c->device) != hipSuccess ||
       hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
       c->n_cu < 1) {
@@ -310,8 +397,9 @@ int pes_create(const pes_config* cfg, pes_ctx** out) {
   c->tile = 256 * c->bpl;
   c->ntmax = (int)((c->N + c->tile - 1) / c->tile);
   c->ntmax_alloc = (int)((c->N + 255) / 256);
-  for (int p = 0; p < 2; ++p)
-    for (int bpl = 1; bpl <= 2; ++bpl) c->occ[p][bpl] = std::max(1, loglike_blocks_per_cu(bpl, c->long_sinc, p == 1));
+  for (int p = 0; p < 3; ++p)
+    for (int bpl = 1; bpl <= 2; ++bpl)
+      c->occ[p][bpl] = std::max(1, loglike_blocks_per_cu(bpl, c->long_sinc, p == 1, p == 2));
   const int64_t nb = (c->N + 255) / 256;
   if (hipMalloc(&c->bins, sizeof(double) * B_NFIELDS * c->N) != hipSuccess ||
       hipMalloc(&c->tabs, sizeof(double) * T_NFIELDS * c->N * cfg->n_det) != hipSuccess ||
@@ -319,6 +407,16 @@ int pes_create(const pes_config* cfg, pes_ctx** out) {
       hipMalloc(&c->dd, sizeof(double)) != hipSuccess) {
     pes_destroy(c);
     return PES_ENOMEM;
+  }
+  if (c->kep) {
+    double host[kMaxDet * KV_STRIDE] = {0};
+    for (int i = 0; i < cfg->n_det; ++i)
+      if (cfg->det[i].kind != PES_TIANQIN) kepler_table(cfg->det[i], host + i * KV_STRIDE);
+    if (hipMalloc(&c->kep_tab, sizeof(double) * kMaxDet * KV_STRIDE) != hipSuccess ||
+        hipMemcpy(c->kep_tab, host, sizeof(host), hipMemcpyHostToDevice) != hipSuccess) {
+      pes_destroy(c);
+      return PES_ENOMEM;
+    }
   }
   hipError_t e = launch_bin_tables(c->bins, c->tabs, c->N, cfg->f0, cfg->df, cfg->n_det, c->dt, 0);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -340,6 +438,7 @@ int pes_destroy(pes_ctx* c) {
   (void)hipFree(c->tabs);
   (void)hipFree(c->dd_part);
   (void)hipFree(c->dd);
+  (void)hipFree(c->kep_tab);
   delete c;
   return PES_OK;
 }
@@ -400,7 +499,7 @@ int pes_get_tuning(pes_ctx* c, int* bins_per_lane, int* walkers_per_group, int* 
   if (!c || !bins_per_lane || !walkers_per_group || !blocks_per_cu) return PES_EINVAL;
   *bins_per_lane = c->bpl;
   *walkers_per_group = c->wg;
-  *blocks_per_cu = c->bpc > 0 ? std::min(c->bpc, c->occ[c->f32][c->bpl]) : c->occ[c->f32][c->bpl];
+  *blocks_per_cu = c->bpc > 0 ? std::min(c->bpc, c->occ[occ_var(c)][c->bpl]) : c->occ[occ_var(c)][c->bpl];
   return PES_OK;
 }
 
@@ -448,7 +547,7 @@ int pes_autotune(pes_ctx* c, const double* theta, int64_t B, double* logl, doubl
   for (int ib = 0; ib < 2 && st == PES_OK; ++ib)
     for (int iw = 0; iw < 4 && st == PES_OK; ++iw)
       for (int half = 0; half < 2 && st == PES_OK; ++half) {
-        const int occ = c->occ[c->f32][bpls[ib]];
+        const int occ = c->occ[occ_var(c)][bpls[ib]];
         const int bpc = half ? std::max(1, occ / 2) : 0;
         if (half && bpc == occ) continue;
         pes_set_tuning(c, bpls[ib], wgs[iw], bpc);
@@ -477,7 +576,7 @@ int pes_autotune(pes_ctx* c, const double* theta, int64_t B, double* logl, doubl
 int pes_reserve(pes_ctx* c, int64_t max_walkers) {
   if (!c || max_walkers < 0) return PES_EINVAL;
   const int st = ensure_workspace(c, max_walkers);
-  if (st != PES_OK || max_walkers == 0) return st;
+  if (st != PES_OK || max_walkers == 0 || c->kep) return st;   // no derivatives on exact Kepler orbits
   return ensure_jac(c, std::min<int64_t>(max_walkers, kMaxDerivBatch));
 }
 
@@ -511,6 +610,10 @@ int pes_noise(pes_ctx* c, uint64_t seed, double* out, void* stream) {
 int pes_probe(pes_ctx* c, const double* theta, int64_t B, int stage, double* out, void* stream) {
   if (!c || (B > 0 && (!theta || !out)) || B < 0 || B > 65535 || stage < PES_PROBE_MODE || stage > PES_PROBE_LINKS)
     return PES_EINVAL;
+  if (c->kep) {
+    snprintf(c->err, sizeof(c->err), "stage probes evaluate the first-order orbit only");
+    return PES_EINVAL;
+  }
   if (B == 0) return PES_OK;
   int st = ensure_workspace(c, B);
   if (st != PES_OK) return st;
@@ -521,6 +624,8 @@ int pes_probe(pes_ctx* c, const double* theta, int64_t B, int stage, double* out
   ra.tabs = c->tabs;
   ra.wtab = c->wtab;
   ra.wtab32 = nullptr;
+  ra.wkep = nullptr;
+  ra.kep = nullptr;
   ra.out = out;
   ra.N = c->N;
   ra.n_modes = c->cfg.n_modes;
@@ -539,18 +644,21 @@ int pes_response(pes_ctx* c, const double* theta, int64_t B, double* out, void* 
   hipStream_t s = (hipStream_t)stream;
   PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, setup_args(c), s));
   if (c->f32) PES_HIP(c, launch_table32(c->wtab, B, c->wtab32, s));
+  if (c->kep) PES_HIP(c, launch_kepler_proj(theta, B, c->kep_tab, setup_args(c), c->wkep, s));
   ResponseArgs ra;
   ra.bins = c->bins;
   ra.tabs = c->tabs;
   ra.wtab = c->wtab;
   ra.wtab32 = c->f32 ? c->wtab32 : nullptr;
+  ra.wkep = c->kep ? c->wkep : nullptr;
+  ra.kep = c->kep_tab;
   ra.out = out;
   ra.N = c->N;
   ra.n_modes = c->cfg.n_modes;
   ra.plan = c->plan;
   ra.n_det = c->cfg.n_det;
   ra.dt = c->dt;
-  PES_HIP(c, launch_response(ra, B, c->long_sinc, c->f32, s));
+  PES_HIP(c, launch_response(ra, B, c->long_sinc, c->f32, c->kep, s));
   return PES_OK;
 }
 
@@ -562,6 +670,7 @@ namespace {
 struct LoglikeWork {
   double* wtab;
   float* wtab32;
+  double* wkep;
   int* ntiles;
   int* perm;
   int* gstart;
@@ -593,12 +702,15 @@ int run_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, const 
   sa.full_tiles = grid_mode ? 1 : 0;
   PES_HIP(c, launch_setup(theta, B, ws.wtab, ws.ntiles, sa, s));
   if (c->f32) PES_HIP(c, launch_table32(ws.wtab, B, ws.wtab32, s));
+  if (c->kep) PES_HIP(c, launch_kepler_proj(theta, B, c->kep_tab, sa, ws.wkep, s));
   PES_HIP(c, launch_plan(ws.ntiles, (int)B, c->wg, c->ntmax, !grid_mode, ws.perm, ws.gstart, ws.counters, s));
   LoglikeArgs a;
   a.bins = c->bins;
   a.tabs = c->tabs;
   a.wtab = ws.wtab;
   a.wtab32 = ws.wtab32;
+  a.wkep = ws.wkep;
+  a.kep = c->kep_tab;
   a.ntiles = ws.ntiles;
   a.perm = ws.perm;
   a.gstart = ws.gstart;
@@ -613,14 +725,14 @@ int run_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, const 
   a.plan = c->plan;
   a.n_det = c->cfg.n_det;
   a.dt = c->dt;
-  const int bpc = c->bpc > 0 ? std::min(c->bpc, c->occ[c->f32][c->bpl]) : c->occ[c->f32][c->bpl];
+  const int bpc = c->bpc > 0 ? std::min(c->bpc, c->occ[occ_var(c)][c->bpl]) : c->occ[occ_var(c)][c->bpl];
   // persistent grid: the resident blocks, but never more than the items can be
   const int grid = grid_mode ? (int)(n_groups * c->ntmax)
                              : (int)std::min<int64_t>((int64_t)c->n_cu * bpc, n_groups * c->ntmax);
   a.grid_mode = grid_mode ? 1 : 0;
   const bool rec = c->timing && c->n_ev < kMaxEv;
   if (rec) PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev], s));
-  PES_HIP(c, launch_loglike(a, c->bpl, c->long_sinc, c->f32, grid, s));
+  PES_HIP(c, launch_loglike(a, c->bpl, c->long_sinc, c->f32, c->kep, grid, s));
   if (rec) {
     PES_HIP(c, hipEventRecord(c->ev[2 * c->n_ev + 1], s));
     ++c->n_ev;
@@ -641,14 +753,14 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
   if (st != PES_OK) return st;
   st = ensure_workspace(c, B);
   if (st != PES_OK) return st;
-  const LoglikeWork ws{c->wtab, c->wtab32, c->ntiles, c->perm, c->gstart, c->counters, c->partial};
+  const LoglikeWork ws{c->wtab, c->wtab32, c->wkep, c->ntiles, c->perm, c->gstart, c->counters, c->partial};
   return run_loglike(c, theta, B, logl, ws, (hipStream_t)stream);
 }
 
 // The log-likelihood workspace of B walkers carved out of one buffer (each
 // part 256-byte aligned); returns the bytes it takes.  base may be null to
 // size it only.
-static int64_t carve_loglike_work(char* base, int64_t B, int ntmax, LoglikeWork* ws) {
+static int64_t carve_loglike_work(char* base, int64_t B, int ntmax, int n_kep, LoglikeWork* ws) {
   int64_t off = 0;
   auto take = [&](int64_t bytes) {
     char* p = base ? base + off : nullptr;
@@ -657,14 +769,15 @@ static int64_t carve_loglike_work(char* base, int64_t B, int ntmax, LoglikeWork*
   };
   char* wtab = take(sizeof(double) * B * W_STRIDE);
   char* wtab32 = take(sizeof(float) * B * W_STRIDE);
+  char* wkep = n_kep > 0 ? take(sizeof(double) * B * n_kep * KW_STRIDE) : nullptr;
   char* ntiles = take(sizeof(int) * B);
   char* perm = take(sizeof(int) * B);
   char* gstart = take(sizeof(int) * (B + 3));
   char* counters = take(sizeof(int) * 4);
   char* partial = take(sizeof(double) * 2 * B * (int64_t)ntmax);
   if (ws)
-    *ws = LoglikeWork{(double*)wtab,  (float*)wtab32,   (int*)ntiles,   (int*)perm,
-                      (int*)gstart,   (int*)counters,   (double*)partial};
+    *ws = LoglikeWork{(double*)wtab,  (float*)wtab32, (double*)wkep,   (int*)ntiles,
+                      (int*)perm,     (int*)gstart,   (int*)counters,  (double*)partial};
   return off;
 }
 
@@ -678,14 +791,15 @@ int pes_loglike_noalloc(pes_ctx* c, const double* theta, int64_t B, double* logl
     snprintf(c->err, sizeof(c->err), "the device scratch array has no address on device %d", c->device);
     return PES_EHIP;
   }
-  const int64_t need = carve_loglike_work(nullptr, B, c->ntmax, nullptr);
+  const int n_kep = c->kep ? c->cfg.n_det : 0;
+  const int64_t need = carve_loglike_work(nullptr, B, c->ntmax, n_kep, nullptr);
   if (need > kScratchBytes) {
     snprintf(c->err, sizeof(c->err), "%lld walkers x %d tiles need %lld bytes of scratch; it holds %lld",
              (long long)B, c->ntmax, (long long)need, (long long)kScratchBytes);
     return PES_ESHAPE;
   }
   LoglikeWork ws;
-  carve_loglike_work((char*)c->scratch, B, c->ntmax, &ws);
+  carve_loglike_work((char*)c->scratch, B, c->ntmax, n_kep, &ws);
   return run_loglike(c, theta, B, logl, ws, (hipStream_t)stream);
 }
 
@@ -705,6 +819,10 @@ static JacArgs jac_args(const pes_ctx* c, int64_t B, int tile) {
 
 int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* grad, void* stream) {
   if (!c || B < 0 || B > kMaxDerivBatch || (B > 0 && (!theta || !grad))) return PES_EINVAL;
+  if (c->kep) {
+    snprintf(c->err, sizeof(c->err), "derivatives use the first-order orbit only");
+    return PES_EINVAL;
+  }
   if (!c->has_data) return PES_ESTATE;
   if (B == 0) return PES_OK;
   int st = ensure_jac(c, B);
@@ -718,6 +836,10 @@ int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* g
 
 int pes_set_precision(pes_ctx* c, int bits) {
   if (!c || (bits != 32 && bits != 64)) return PES_EINVAL;
+  if (c->kep && bits == 32) {
+    snprintf(c->err, sizeof(c->err), "exact Kepler orbits are evaluated in FP64 only");
+    return PES_EINVAL;
+  }
   c->f32 = bits == 32;
   return PES_OK;
 }
@@ -736,6 +858,10 @@ int pes_set_grad_method(pes_ctx* c, int method) {
 
 int pes_fisher(pes_ctx* c, const double* theta, int64_t B, double* F, void* stream) {
   if (!c || B < 0 || B > kMaxDerivBatch || (B > 0 && (!theta || !F))) return PES_EINVAL;
+  if (c->kep) {
+    snprintf(c->err, sizeof(c->err), "derivatives use the first-order orbit only");
+    return PES_EINVAL;
+  }
   if (B == 0) return PES_OK;
   int st = ensure_jac(c, B);
   if (st != PES_OK) return st;

@@ -142,11 +142,16 @@ struct NoProbe {
 // Tab: accessor of this walker's constant table (wavefront-uniform); det: the
 // detector block.  S = double (values) or Dual<1> (value and one tangent).
 // GEO selects the geocentric orbit.  a = pi f L, (zr, zi) = e^{-2 pi i f L}.
-template <bool GEO, bool LONG_SINC, int CLS, class S, class Tab, class Probe = NoProbe>
+// KEP: heliocentric detector on exact Kepler ellipses (S = double only); kw:
+// the walker's projected orbit series for this detector [KW_STRIDE], kinv: the
+// detector's inverse-arm-length series [3][kKepT].
+template <bool GEO, bool LONG_SINC, int CLS, class S, class Tab, class Probe = NoProbe, bool KEP = false>
 __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const ModePlan& plan,
                                                     double inv_year, double inv_ptq, const BinRegs& b,
                                                     double a, double zr, double zi,
-                                                    const Probe& probe = Probe()) {
+                                                    const Probe& probe = Probe(),
+                                                    const double* __restrict__ kw = nullptr,
+                                                    const double* __restrict__ kinv = nullptr) {
   S yFr0 = 0.0, yFi0 = 0.0, yBr0 = 0.0, yBi0 = 0.0;
   S yFr1 = 0.0, yFi1 = 0.0, yBr1 = 0.0, yBi1 = 0.0;
   S yFr2 = 0.0, yFi2 = 0.0, yBr2 = 0.0, yBi2 = 0.0;
@@ -219,21 +224,66 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
     // spacecraft geometry at t_f
     S sa, ca;
     sincos_cycles(tau * inv_year + wd(D_AO), sa, ca);
-    S ua, ub;
-    if (GEO) {
-      sincos_cycles(tau * inv_ptq + wd(D_PO), ub, ua);
+    S kn0, kn1, kn2, np0, np1, np2, nq0, nq1, nq2, kd0, kd1, kR;
+    if constexpr (KEP) {
+      // exact Kepler ellipses: every projection is a series in the harmonics
+      // of alpha; the link directions are the separations over their lengths
+      S hc[kKepH + 1], hs[kKepH + 1];
+      hc[0] = 1.0;
+      hs[0] = 0.0;
+      hc[1] = ca;
+      hs[1] = sa;
+      const S c2a = 2.0 * ca;
+#pragma unroll
+      for (int k = 2; k <= kKepH; ++k) {
+        hc[k] = fma(c2a, hc[k - 1], -hc[k - 2]);
+        hs[k] = fma(c2a, hs[k - 1], -hs[k - 2]);
+      }
+      auto series = [&](const double* __restrict__ c) __attribute__((always_inline)) {
+        S r = c[0];
+#pragma unroll
+        for (int k = 1; k <= kKepH; ++k) r = fma(c[2 * k - 1], hc[k], fma(c[2 * k], hs[k], r));
+        return r;
+      };
+      const S iL0 = series(kinv), iL1 = series(kinv + kKepT), iL2 = series(kinv + 2 * kKepT);
+      const S KD0 = series(kw + KW_KD0), KD1 = series(kw + KW_KD1);
+      const S PD0 = series(kw + KW_PD0), PD1 = series(kw + KW_PD1);
+      const S QD0 = series(kw + KW_QD0), QD1 = series(kw + KW_QD1);
+      kn0 = KD0 * iL0;
+      kn1 = KD1 * iL1;
+      kn2 = -(KD0 + KD1) * iL2;
+      np0 = PD0 * iL0;
+      np1 = PD1 * iL1;
+      np2 = -(PD0 + PD1) * iL2;
+      nq0 = QD0 * iL0;
+      nq1 = QD1 * iL1;
+      nq2 = -(QD0 + QD1) * iL2;
+      kd0 = series(kw + KW_KX0);
+      kd1 = series(kw + KW_KX1);
+      kR = series(kw + KW_KC);
     } else {
-      ua = fma(-2.0 * sa, sa, 1.0);
-      ub = 2.0 * sa * ca;
-    }
+      S ua, ub;
+      if (GEO) {
+        sincos_cycles(tau * inv_ptq + wd(D_PO), ub, ua);
+      } else {
+        ua = fma(-2.0 * sa, sa, 1.0);
+        ub = 2.0 * sa * ca;
+      }
 #define PES_LIN(off) (fma(wd((off) + 3), sa, fma(wd((off) + 2), ca, fma(wd((off) + 1), ub, wd((off)) * ua))) + wd((off) + 4))
-    const S kn0 = PES_LIN(D_KN), kn1 = PES_LIN(D_KN + 5);
-    const S np0 = PES_LIN(D_NP), np1 = PES_LIN(D_NP + 5);
-    const S nq0 = PES_LIN(D_NQ), nq1 = PES_LIN(D_NQ + 5);
-    const S kd0 = PES_LIN(D_KD), kd1 = PES_LIN(D_KD + 5);
+      kn0 = PES_LIN(D_KN);
+      kn1 = PES_LIN(D_KN + 5);
+      np0 = PES_LIN(D_NP);
+      np1 = PES_LIN(D_NP + 5);
+      nq0 = PES_LIN(D_NQ);
+      nq1 = PES_LIN(D_NQ + 5);
+      kd0 = PES_LIN(D_KD);
+      kd1 = PES_LIN(D_KD + 5);
 #undef PES_LIN
-    const S kn2 = -(kn0 + kn1), np2 = -(np0 + np1), nq2 = -(nq0 + nq1);
-    const S kR = fma(wd(D_KR), ca, wd(D_KR + 1) * sa);
+      kn2 = -(kn0 + kn1);
+      np2 = -(np0 + np1);
+      nq2 = -(nq0 + nq1);
+      kR = fma(wd(D_KR), ca, wd(D_KR + 1) * sa);
+    }
     {
       const S knv[3] = {kn0, kn1, kn2}, npv[3] = {np0, np1, np2}, nqv[3] = {nq0, nq1, nq2}, kdv[2] = {kd0, kd1};
       probe.geom(j, knv, npv, nqv, kdv, kR);
@@ -313,23 +363,27 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
   return c;
 }
 
-template <bool GEO, bool LONG_SINC, int CLS = 1>
+template <bool GEO, bool LONG_SINC, int CLS = 1, bool KEP = false>
 __device__ __forceinline__ Chan eval_channels(const double* __restrict__ wt, int det, const ModePlan& plan,
                                               double inv_year, double inv_ptq, const BinRegs& b,
-                                              double a, double zr, double zi) {
-  const ChanT<double> c = eval_channels_t<GEO, LONG_SINC, CLS, double>(ValTab{wt}, det, plan, inv_year,
-                                                                  inv_ptq, b, a, zr, zi);
+                                              double a, double zr, double zi,
+                                              const double* __restrict__ kw = nullptr,
+                                              const double* __restrict__ kinv = nullptr) {
+  const ChanT<double> c = eval_channels_t<GEO, LONG_SINC, CLS, double, ValTab, NoProbe, KEP>(
+      ValTab{wt}, det, plan, inv_year, inv_ptq, b, a, zr, zi, NoProbe(), kw, kinv);
   return Chan{c.ar, c.ai, c.er, c.ei, c.tr, c.ti};
 }
 
 // eval_channels with the fit class chosen at run time (a wave-uniform branch).
-template <bool GEO, bool LONG_SINC>
+template <bool GEO, bool LONG_SINC, bool KEP = false>
 __device__ __forceinline__ Chan eval_channels_cls(int cls, const double* __restrict__ wt, int det,
                                                   const ModePlan& plan,
                                                   double inv_year, double inv_ptq, const BinRegs& b, double a,
-                                                  double zr, double zi) {
-  if (cls == 0) return eval_channels<GEO, LONG_SINC, 0>(wt, det, plan, inv_year, inv_ptq, b, a, zr, zi);
-  return eval_channels<GEO, LONG_SINC, 1>(wt, det, plan, inv_year, inv_ptq, b, a, zr, zi);
+                                                  double zr, double zi, const double* __restrict__ kw = nullptr,
+                                                  const double* __restrict__ kinv = nullptr) {
+  if (cls == 0)
+    return eval_channels<GEO, LONG_SINC, 0, KEP>(wt, det, plan, inv_year, inv_ptq, b, a, zr, zi, kw, kinv);
+  return eval_channels<GEO, LONG_SINC, 1, KEP>(wt, det, plan, inv_year, inv_ptq, b, a, zr, zi, kw, kinv);
 }
 
 }  // namespace pes

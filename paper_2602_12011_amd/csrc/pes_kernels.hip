@@ -206,6 +206,23 @@ __host__ __device__ inline int argu_quarters(int l, int m) {
   return 0;
 }
 
+// Sky basis: source direction (lam, beta), k = -nhat, polarization axes p, q
+// rotated by psi.
+template <class T>
+__device__ void sky_basis(const T& lam, const T& beta, const T& psi, T kv[3], T pv[3], T qv[3]) {
+  const T cl = cos(lam), sl = sin(lam), cb = cos(beta), sb = sin(beta);
+  const T cps = cos(psi), sps = sin(psi);
+  kv[0] = -(cb * cl);
+  kv[1] = -(cb * sl);
+  kv[2] = -sb;
+  const T uu[3] = {-sl, cl, T(0.0)};
+  const T vv[3] = {-(sb * cl), -(sb * sl), cb};
+  for (int i = 0; i < 3; ++i) {
+    pv[i] = cps * uu[i] + sps * vv[i];
+    qv[i] = sps * (-1.0 * uu[i]) + cps * vv[i];
+  }
+}
+
 // Writes the W_STRIDE entries of a physical theta's table through `put`;
 // returns the highest mode cutoff [Hz].
 template <class T, class Out>
@@ -317,17 +334,8 @@ __device__ double setup_walker(const T* th, const SetupArgs& sa, const Out& put,
   }
   if (all || part == 0) put(W_FMAX, T(fmx));
   if (!(all || part > sa.n_modes)) return fmx;
-  // sky basis: source direction (lam, beta), k = -nhat, axes p, q rotated by psi
-  const T cl = cos(lam), sl = sin(lam), cb = cos(beta), sb = sin(beta);
-  const T cps = cos(psi), sps = sin(psi);
-  const T kv[3] = {-(cb * cl), -(cb * sl), -sb};
-  const T uu[3] = {-sl, cl, T(0.0)};
-  const T vv[3] = {-(sb * cl), -(sb * sl), cb};
-  T pv[3], qv[3];
-  for (int i = 0; i < 3; ++i) {
-    pv[i] = cps * uu[i] + sps * vv[i];
-    qv[i] = sps * (-1.0 * uu[i]) + cps * vv[i];
-  }
+  T kv[3], pv[3], qv[3];
+  sky_basis(lam, beta, psi, kv, pv, qv);
   for (int d = 0; d < sa.n_det; ++d) {
     if (!(all || part == 1 + sa.n_modes + d)) continue;
     const DetParams& P = sa.dt.p[d];
@@ -385,6 +393,44 @@ __global__ void setup_kernel(const double* __restrict__ theta, int64_t B, double
   }
   const double fmx = setup_walker<double>(th, sa, ValOut{w}, part);
   if (part == 0) ntiles[b] = active_tiles(fmx, sa, sa.tile);
+}
+
+// Exact Kepler orbits: each walker's projections of the detectors' orbit
+// series onto its sky basis, one thread per (walker, detector).  Rows of a
+// geocentric detector, and of an unphysical walker, are left zero (the
+// evaluation never reads them).
+__global__ void kepler_proj_kernel(const double* __restrict__ theta, int64_t B, const double* __restrict__ kep,
+                                   SetupArgs sa, double* __restrict__ wkep) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * sa.n_det) return;
+  const int64_t b = i / sa.n_det;
+  const int d = (int)(i - b * sa.n_det);
+  double* __restrict__ out = wkep + i * KW_STRIDE;
+  const double* th = theta + b * 11;
+  if (sa.dt.p[d].kind == 2 || !theta_valid(th)) {
+    for (int j = 0; j < KW_STRIDE; ++j) out[j] = 0.0;
+    return;
+  }
+  double kv[3], pv[3], qv[3];
+  sky_basis(th[7], th[8], th[9], kv, pv, qv);
+  const double* __restrict__ v = kep + d * KV_STRIDE;
+  for (int j = 0; j < kKepT; ++j) {
+    double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int x = 0; x < 3; ++x) {
+      const double d0 = v[KV_D0 + x * kKepT + j], d1 = v[KV_D1 + x * kKepT + j];
+      c[0] = fma(kv[x], d0, c[0]);
+      c[1] = fma(kv[x], d1, c[1]);
+      c[2] = fma(pv[x], d0, c[2]);
+      c[3] = fma(pv[x], d1, c[3]);
+      c[4] = fma(qv[x], d0, c[4]);
+      c[5] = fma(qv[x], d1, c[5]);
+      c[6] = fma(kv[x], v[KV_X0 + x * kKepT + j], c[6]);
+      c[7] = fma(kv[x], v[KV_X1 + x * kKepT + j], c[7]);
+      c[8] = fma(kv[x], v[KV_C + x * kKepT + j], c[8]);
+    }
+    for (int f = 0; f < 9; ++f) out[f * kKepT + j] = c[f];
+  }
+  for (int j = 9 * kKepT; j < KW_STRIDE; ++j) out[j] = 0.0;
 }
 
 // Values and theta-derivatives of the walker table, wtan[b][i][k] = d w_i / d theta_k:
@@ -546,7 +592,7 @@ __global__ void __launch_bounds__(1024) plan_kernel(const int* __restrict__ ntil
 // ticket.  Lanes own bins; the walkers of the group are processed in turn,
 // each lane evaluating its bins, then a wavefront reduction and one LDS slot
 // per (walker, wave).  partial[w][tile] = (<d|h>, <h|h>) of that tile.
-template <int BPL, bool LS, bool F32>
+template <int BPL, bool LS, bool F32, bool KEP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     loglike_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                    const double* __restrict__ wtab, const int* __restrict__ ntiles,
@@ -632,10 +678,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
                     : eval_channels_f32_cls<false, LS>(cls[q], wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br[q],
                                                        (float)aa[q], (float)zr[q], (float)zi[q]);
             c = Chan{cf.ar, cf.ai, cf.er, cf.ei, cf.tr, cf.ti};
+          } else if (P.kind == 2) {
+            c = eval_channels_cls<true, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q],
+                                            zi[q]);
+          } else if constexpr (KEP) {
+            const double* __restrict__ kw = A.wkep + ((int64_t)w * A.n_det + det) * KW_STRIDE;
+            const double* __restrict__ kinv = A.kep + det * KV_STRIDE + KV_INVL;
+            c = eval_channels_cls<false, LS, true>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q],
+                                                   zr[q], zi[q], kw, kinv);
           } else {
-            c = (P.kind == 2)
-                    ? eval_channels_cls<true, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q])
-                    : eval_channels_cls<false, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q], zi[q]);
+            c = eval_channels_cls<false, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q],
+                                             zi[q]);
           }
           dh = fma(dar[q], c.ar, dh);
           dh = fma(dai[q], c.ai, dh);
@@ -720,7 +773,7 @@ __global__ void __launch_bounds__(kFinW * kFinP)
 
 // ---------------------------------------------------------------- response
 // out[b][det][c][k] = n_c G(f_k) C''_c for one walker per blockIdx.y.
-template <bool LS, bool F32>
+template <bool LS, bool F32, bool KEP>
 __global__ void response_kernel(ResponseArgs A) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t b = blockIdx.y;
@@ -746,11 +799,17 @@ __global__ void response_kernel(ResponseArgs A) {
             (P.kind == 2) ? eval_channels_f32<true, LS, 1>(wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi)
                           : eval_channels_f32<false, LS, 1>(wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi);
         c = Chan{cf.ar, cf.ai, cf.er, cf.ei, cf.tr, cf.ti};
+      } else if (P.kind == 2) {
+        c = eval_channels<true, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k], tb[T_ZR * N + k],
+                                    tb[T_ZI * N + k]);
+      } else if constexpr (KEP) {
+        const double* __restrict__ kw = A.wkep + (b * A.n_det + det) * KW_STRIDE;
+        const double* __restrict__ kinv = A.kep + det * KV_STRIDE + KV_INVL;
+        c = eval_channels<false, LS, 1, true>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
+                                              tb[T_ZR * N + k], tb[T_ZI * N + k], kw, kinv);
       } else {
-        c = (P.kind == 2) ? eval_channels<true, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
-                                                tb[T_ZR * N + k], tb[T_ZI * N + k])
-                          : eval_channels<false, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k],
-                                                 tb[T_ZR * N + k], tb[T_ZI * N + k]);
+        c = eval_channels<false, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k], tb[T_ZR * N + k],
+                                     tb[T_ZI * N + k]);
       }
     }
     const double Gr = tb[T_GR * N + k], Gi = tb[T_GI * N + k];
@@ -894,26 +953,39 @@ hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, bool sorted,
   return hipGetLastError();
 }
 
-template <int BPL, bool LS, bool F32>
+template <int BPL, bool LS, bool F32, bool KEP>
 static void launch_ll(const LoglikeArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((loglike_kernel<BPL, LS, F32>), dim3(grid), dim3(256), 0, s, a.bins, a.tabs, a.wtab,
+  hipLaunchKernelGGL((loglike_kernel<BPL, LS, F32, KEP>), dim3(grid), dim3(256), 0, s, a.bins, a.tabs, a.wtab,
                      a.ntiles, a.perm, a.gstart, a.counters, a.partial, a);
 }
 
-template <bool F32>
+template <bool F32, bool KEP>
 static void launch_ll_f(const LoglikeArgs& a, int bpl, bool long_sinc, int grid, hipStream_t s) {
   if (bpl == 2)
-    long_sinc ? launch_ll<2, true, F32>(a, grid, s) : launch_ll<2, false, F32>(a, grid, s);
+    long_sinc ? launch_ll<2, true, F32, KEP>(a, grid, s) : launch_ll<2, false, F32, KEP>(a, grid, s);
   else
-    long_sinc ? launch_ll<1, true, F32>(a, grid, s) : launch_ll<1, false, F32>(a, grid, s);
+    long_sinc ? launch_ll<1, true, F32, KEP>(a, grid, s) : launch_ll<1, false, F32, KEP>(a, grid, s);
 }
 
-hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, bool f32, int grid, hipStream_t s) {
-  if (f32 && !a.wtab32) return hipErrorInvalidValue;   // the FP32 kernels read the FP32 walker tables
+// Variants: FP64, FP32, and FP64 on exact Kepler orbits (not combined with FP32).
+hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, bool f32, bool kep, int grid,
+                          hipStream_t s) {
+  if (f32 && !a.wtab32) return hipErrorInvalidValue;       // the FP32 kernels read the FP32 walker tables
+  if (kep && (f32 || !a.wkep || !a.kep)) return hipErrorInvalidValue;   // and the Kepler ones the orbit series
   if (f32)
-    launch_ll_f<true>(a, bpl, long_sinc, grid, s);
+    launch_ll_f<true, false>(a, bpl, long_sinc, grid, s);
+  else if (kep)
+    launch_ll_f<false, true>(a, bpl, long_sinc, grid, s);
   else
-    launch_ll_f<false>(a, bpl, long_sinc, grid, s);
+    launch_ll_f<false, false>(a, bpl, long_sinc, grid, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_kepler_proj(const double* theta, int64_t B, const double* kep, const SetupArgs& sa,
+                              double* wkep, hipStream_t s) {
+  if (!kep || !wkep) return hipErrorInvalidValue;
+  const int64_t n = B * sa.n_det;
+  hipLaunchKernelGGL(kepler_proj_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, theta, B, kep, sa, wkep);
   return hipGetLastError();
 }
 
@@ -940,39 +1012,41 @@ hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, int st
   return hipGetLastError();
 }
 
-hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, bool f32, hipStream_t s) {
+template <bool LS, bool F32, bool KEP>
+static void launch_resp(const ResponseArgs& a, dim3 grid, int bs, hipStream_t s) {
+  hipLaunchKernelGGL((response_kernel<LS, F32, KEP>), grid, dim3(bs), 0, s, a);
+}
+
+hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, bool f32, bool kep, hipStream_t s) {
   if (f32 && !a.wtab32) return hipErrorInvalidValue;   // the FP32 kernel reads the FP32 walker tables
+  if (kep && (f32 || !a.wkep || !a.kep)) return hipErrorInvalidValue;
   const int bs = 256;
   const dim3 grid((unsigned)((a.N + bs - 1) / bs), (unsigned)B);
-  if (f32) {
-    if (long_sinc)
-      hipLaunchKernelGGL((response_kernel<true, true>), grid, dim3(bs), 0, s, a);
-    else
-      hipLaunchKernelGGL((response_kernel<false, true>), grid, dim3(bs), 0, s, a);
-  } else {
-    if (long_sinc)
-      hipLaunchKernelGGL((response_kernel<true, false>), grid, dim3(bs), 0, s, a);
-    else
-      hipLaunchKernelGGL((response_kernel<false, false>), grid, dim3(bs), 0, s, a);
-  }
+  if (f32)
+    long_sinc ? launch_resp<true, true, false>(a, grid, bs, s) : launch_resp<false, true, false>(a, grid, bs, s);
+  else if (kep)
+    long_sinc ? launch_resp<true, false, true>(a, grid, bs, s) : launch_resp<false, false, true>(a, grid, bs, s);
+  else
+    long_sinc ? launch_resp<true, false, false>(a, grid, bs, s) : launch_resp<false, false, false>(a, grid, bs, s);
   return hipGetLastError();
 }
 
-template <bool F32>
+template <bool F32, bool KEP>
 static int blocks_per_cu(int bpl, bool long_sinc) {
   int nb = 0;
   hipError_t e;
   if (bpl == 2)
-    e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2, true, F32>, 256, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2, false, F32>, 256, 0);
+    e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2, true, F32, KEP>, 256, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<2, false, F32, KEP>, 256, 0);
   else
-    e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, true, F32>, 256, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, false, F32>, 256, 0);
+    e = long_sinc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, true, F32, KEP>, 256, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loglike_kernel<1, false, F32, KEP>, 256, 0);
   return e == hipSuccess ? nb : 1;
 }
 
-int loglike_blocks_per_cu(int bpl, bool long_sinc, bool f32) {
-  return f32 ? blocks_per_cu<true>(bpl, long_sinc) : blocks_per_cu<false>(bpl, long_sinc);
+int loglike_blocks_per_cu(int bpl, bool long_sinc, bool f32, bool kep) {
+  if (f32) return blocks_per_cu<true, false>(bpl, long_sinc);
+  return kep ? blocks_per_cu<false, true>(bpl, long_sinc) : blocks_per_cu<false, false>(bpl, long_sinc);
 }
 
 }  // namespace pes

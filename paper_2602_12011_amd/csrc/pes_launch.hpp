@@ -28,6 +28,8 @@ struct LoglikeArgs {
   const double* tabs;
   const double* wtab;
   const float* wtab32;   // FP32 copy of the walker tables (single-precision kernels only)
+  const double* wkep;    // [B][n_det][KW_STRIDE] projected orbit series (exact Kepler orbits only)
+  const double* kep;     // [n_det][KV_STRIDE] orbit series of the detectors (exact Kepler orbits only)
   const int* ntiles;
   const int* perm;
   const int* gstart;
@@ -45,6 +47,8 @@ struct ResponseArgs {
   const double* tabs;
   const double* wtab;
   const float* wtab32;   // FP32 copy of the walker tables (single-precision kernels only)
+  const double* wkep;    // [B][n_det][KW_STRIDE] projected orbit series (exact Kepler orbits only)
+  const double* kep;     // [n_det][KV_STRIDE] orbit series of the detectors (exact Kepler orbits only)
   double* out;
   int64_t N;
   int n_modes, n_det;
@@ -77,12 +81,15 @@ hipError_t launch_setup_tan(const double* theta, int64_t B, double* wtab, double
                             const SetupArgs& sa, hipStream_t s);
 hipError_t launch_plan(const int* ntiles, int B, int wg, int ntmax, bool sorted, int* perm, int* gstart,
                        int* counters, hipStream_t s);
-hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, bool f32, int grid, hipStream_t s);
+hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, bool f32, bool kep, int grid,
+                          hipStream_t s);
+hipError_t launch_kepler_proj(const double* theta, int64_t B, const double* kep, const SetupArgs& sa,
+                              double* wkep, hipStream_t s);
 hipError_t launch_table32(const double* wtab, int64_t B, float* wtab32, hipStream_t s);
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
                            int64_t B, double* logl, hipStream_t s);
 hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, int stage, hipStream_t s);
-hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, bool f32, hipStream_t s);
-int loglike_blocks_per_cu(int bpl, bool long_sinc, bool f32);
+hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, bool f32, bool kep, hipStream_t s);
+int loglike_blocks_per_cu(int bpl, bool long_sinc, bool f32, bool kep);
 
 }  // namespace pes

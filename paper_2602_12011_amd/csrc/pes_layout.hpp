@@ -67,6 +67,29 @@ enum : int {
   D_AO = 0, D_PO = 1, D_KN = 2, D_NP = 12, D_NQ = 22, D_KD = 32, D_KR = 42
 };
 
+// ---- exact Keplerian heliocentric orbits (detector option).  Every
+// orbit-dependent vector is a periodic function of the revolution phase alpha,
+// kept as a Fourier series to harmonic kKepH (the Kepler ellipses' series
+// converge as e^k; e ~ 5e-3): term 0 the constant, 2k - 1 the cos(k alpha)
+// and 2k the sin(k alpha) coefficient.
+constexpr int kKepH = 6;
+constexpr int kKepT = 2 * kKepH + 1;   // 13 terms
+// Per detector (host-computed, walker-independent), light-seconds: the arm
+// vectors Delta_0 = x_2 - x_1, Delta_1 = x_0 - x_2, the offsets x_0 - c,
+// x_1 - c from the centroid c, and c, each [3 components][kKepT]; then the
+// inverse arm lengths 1/|Delta_t| (Delta_2 = x_1 - x_0) [3][kKepT].
+enum : int {
+  KV_D0 = 0, KV_D1 = 3 * kKepT, KV_X0 = 6 * kKepT, KV_X1 = 9 * kKepT, KV_C = 12 * kKepT,
+  KV_INVL = 15 * kKepT, KV_STRIDE = 240   // >= 18 kKepT (234)
+};
+// Per walker and detector (setup): the series of the projections
+//   k.Delta_0, k.Delta_1, p.Delta_0, p.Delta_1, q.Delta_0, q.Delta_1,
+//   k.(x_0 - c), k.(x_1 - c), k.c   (9 x kKepT)
+enum : int {
+  KW_KD0 = 0, KW_KD1 = kKepT, KW_PD0 = 2 * kKepT, KW_PD1 = 3 * kKepT, KW_QD0 = 4 * kKepT,
+  KW_QD1 = 5 * kKepT, KW_KX0 = 6 * kKepT, KW_KX1 = 7 * kKepT, KW_KC = 8 * kKepT, KW_STRIDE = 120   // >= 117
+};
+
 // ---- per-bin tables (structure of arrays, n_bins doubles per field).
 enum : int { B_F = 0, B_F13, B_FM13, B_FM76, B_LNF, B_NFIELDS };
 // Per detector and bin: delay factor z = e^{-2 pi i f L}; the TDI- and

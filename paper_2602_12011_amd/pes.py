@@ -26,7 +26,10 @@ class Detector(C.Structure):
     _fields_ = [("kind", C.c_int), ("tdi_gen", C.c_int), ("arm_m", C.c_double),
                 ("phase0", C.c_double), ("tq_period_s", C.c_double),
                 ("tq_lon", C.c_double), ("tq_lat", C.c_double),
-                ("oms_asd", C.c_double), ("acc_asd", C.c_double)]
+                ("oms_asd", C.c_double), ("acc_asd", C.c_double), ("orbit", C.c_int)]
+
+
+ORBIT = {"first_order": 0, "kepler": 1}
 
 
 class Config(C.Structure):
@@ -140,7 +143,8 @@ def make_config(cfg):
         c.det[i] = Detector(KIND[d["kind"]], int(d.get("tdi_gen", 20)), float(d["arm_m"]),
                             float(d.get("phase0", 0.0)), float(d.get("tq_period_s", 0.0)),
                             float(d.get("tq_lon", 0.0)), float(d.get("tq_lat", 0.0)),
-                            float(d["oms_asd"]), float(d["acc_asd"]))
+                            float(d["oms_asd"]), float(d["acc_asd"]),
+                            ORBIT[d.get("orbit", "first_order")])
     c.n_bins = int(cfg["n_bins"])
     c.f0 = float(cfg["f0"])
     c.df = float(cfg["df"])
