@@ -395,9 +395,12 @@ int pes_set_schedule(pes_ctx* ctx, int schedule);
  * dev [B] receives the results) for every tuning candidate (bins per lane 1
  * or 2, walkers per item 8, 16, 32 or 64, blocks per CU at the occupancy
  * limit or half of it): the mean of two calls after a warm-up, then the three
- * fastest again as the least of three single calls.  Keeps the fastest and
- * returns its time per call [ms] in *best_ms; on an error the previous tuning
- * stays.  Synchronizes the stream; the results do not depend on the tuning. */
+ * fastest again as the least of three single calls.  Keeps the fastest, or
+ * among those finalists within 1% of it the one with the most walkers per item
+ * (each item reads its bin tile's tables once, so it moves the fewest bytes),
+ * and returns its time per call [ms] in *best_ms; on an error the previous
+ * tuning stays.  Synchronizes the stream; the results do not depend on the
+ * tuning. */
 int pes_autotune(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double* best_ms,
                  void* stream);
 

@@ -568,8 +568,14 @@ int pes_autotune(pes_ctx* c, const double* theta, int64_t B, double* logl, doubl
     return st != PES_OK ? st : PES_EHIP;
   }
   std::sort(cand, cand + std::min(nc, 3), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
-  pes_set_tuning(c, cand[0].bpl, cand[0].wg, cand[0].bpc);
-  *best_ms = cand[0].ms;
+  // among the finalists within 1% of the fastest, the one with the most
+  // walkers per item: each item reads its tile's bin tables once, so that
+  // choice moves the fewest bytes for the same time
+  int pick = 0;
+  for (int k = 1; k < std::min(nc, 3); ++k)
+    if (cand[k].ms <= 1.01 * cand[0].ms && cand[k].wg > cand[pick].wg) pick = k;
+  pes_set_tuning(c, cand[pick].bpl, cand[pick].wg, cand[pick].bpc);
+  *best_ms = cand[pick].ms;
   return PES_OK;
 }
 
