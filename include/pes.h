@@ -194,7 +194,10 @@ int pes_grad(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double*
 /* Gradient method of pes_grad:
  *   PES_GRAD_ADJOINT (default): hand-written reverse sweep per bin with the
  *     forward values recomputed (no per-bin storage); adjoints of the walker
- *     table contracted with its theta-derivatives.
+ *     table's mode entries contracted with their theta-derivatives, those of
+ *     the sky projections reduced through the orthonormal sky basis (this
+ *     needs spacecraft offsets that sum to zero, as both orbit models here
+ *     have; pes_grad returns PES_EINVAL otherwise).
  *   PES_GRAD_FORWARD: forward-mode tangents, one (bin, parameter direction)
  *     pair per lane (the evaluation of pes_fisher); the cross-check.
  * PES_EINVAL for another value. */

@@ -8,12 +8,17 @@
 // back through A/E/T and the TDI combinations to the six complex links
 // (adj_links), then, for every active mode, through the link transfer
 // functions, the projections, the orbit at t_f, amplitude, phase and t_f to
-// the entries of the walker table (adj_unit).  Each table entry's adjoint is
+// the entries of the walker table (adj_unit).  Each mode entry's adjoint is
 // contracted at once with its theta-derivatives (the tangent table of the
-// setup), so only 11 accumulators live across bins.  The forward values of a
-// unit are recomputed from the table, nothing is stored per bin.
+// setup), so only a few accumulators live across bins.  The sky angles enter
+// only through the unit vectors k, p, q, whose projections onto the arms are
+// the detector entries; their adjoints collapse into three sums per lane
+// (adj_unit), contracted with the derivatives of the sky basis once per block.
+// The forward values of a unit are recomputed from the table, nothing is
+// stored per bin.
 #pragma once
 #include "pes_eval.hpp"
+#include "pes_launch.hpp"
 
 namespace pes {
 
@@ -21,6 +26,13 @@ namespace pes {
 // modify it): recomputations from it are not merged with earlier ones.
 __device__ __forceinline__ double opaque(double x) {
   asm volatile("" : "+v"(x));
+  return x;
+}
+// The same for a wave-uniform int: table offsets rebuilt from it after such a
+// point make the compiler load the entries again (scalar cache hits) instead
+// of keeping the earlier loads in scalar registers across the whole unit.
+__device__ __forceinline__ int opaque_u(int x) {
+  asm volatile("" : "+s"(x));
   return x;
 }
 
@@ -44,7 +56,6 @@ using DepMQChi = Deps<0, 1, 2, 3>;
 using DepMQD = Deps<0, 1, 4>;
 using DepIota = Deps<5>;
 using DepSky = Deps<7, 8>;
-using DepSkyPsi = Deps<7, 8, 9>;
 using DepTc = Deps<10>;
 
 // Compact tangent layout: per table entry only the derivatives with respect
@@ -88,6 +99,7 @@ constexpr int kTanDet0 = kTanMode0 + kMaxModes * kModeSlots;
 constexpr int kTanRot0 = kTanDet0 + kMaxDet * kDetSlots;
 constexpr int kTanSlots = kTanRot0 + kMaxModes * R_STRIDE;
 static_assert(kModeSlots == 49 && kDetSlots == 106, "compact tangent layout");
+static_assert(kTanSlots == kTanCompactSlots, "compact tangent table size");
 template <int F> struct ModeOff { static constexpr int value = kTanLayout.mode[F]; };
 template <int F> struct DetOff { static constexpr int value = kTanLayout.det[F]; };
 
@@ -194,16 +206,17 @@ __device__ __forceinline__ void adj_arm(const double* yb, double a, double pEr, 
 
 // Adjoint of the unit of mode j (and, when PAIR, of mode jm riding on it, as
 // in eval_channels_t) of (walker, bin, detector) given the link adjoints yb
-// (12 values: arm-major Fr, Fi, Br, Bi); accumulates d l / d theta into g.
+// (12 values: arm-major Fr, Fi, Br, Bi); accumulates d l / d theta into
+// g[0..10] and the three sky sums into g[11..13] (see the sky part below).
 // wt: the walker's table; tn: its tangents in the compact layout; ftc = f t_c
-// mod 1.
+// mod 1; L3 = L / 3 of the detector.
 template <bool GEO, bool LS, bool PAIR>
 __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const double* __restrict__ tn, int det,
-                                         int j, int jm, double inv_year, double inv_ptq, const BinRegs& b,
-                                         double a, double ftc, const double* yb, double* g) {
-  const int M0 = W_MODE0 + j * W_MODE_STRIDE;
-  const int D0 = W_DET0 + det * W_DET_STRIDE;
-  const int N0 = W_MODE0 + jm * W_MODE_STRIDE, R0 = W_ROT0 + R_STRIDE * jm;
+                                         int j, int jm, double inv_year, double inv_ptq, double L3,
+                                         const BinRegs& b, double a, double ftc, const double* yb, double* g) {
+  int M0 = W_MODE0 + opaque_u(j) * W_MODE_STRIDE;
+  int D0 = W_DET0 + opaque_u(det) * W_DET_STRIDE;
+  int N0 = W_MODE0 + opaque_u(jm) * W_MODE_STRIDE, R0 = W_ROT0 + R_STRIDE * opaque_u(jm);
 #define wm(i) wt[M0 + (i)]
 #define wd(i) wt[D0 + (i)]
 #define wn(i) wt[N0 + (i)]
@@ -303,6 +316,14 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   }
   const double c2 = fma(c0, c1, -(s0 * s1)), s2 = -fma(s0, c1, c0 * s1);
 
+  // table entries are loaded again below (see opaque_u)
+  det = opaque_u(det);
+  j = opaque_u(j);
+  jm = opaque_u(jm);
+  M0 = W_MODE0 + j * W_MODE_STRIDE;
+  N0 = W_MODE0 + jm * W_MODE_STRIDE;
+  R0 = W_ROT0 + R_STRIDE * jm;
+  D0 = W_DET0 + det * W_DET_STRIDE;
   // ---- reverse: arms
   double pEbr = 0.0, pEbi = 0.0, cEbr = 0.0, cEbi = 0.0;
   double cb0, sb0, knb0, npb0, nqb0, cb1, sb1, knb1, npb1, nqb1, cb2, sb2, knb2, npb2, nqb2;
@@ -342,26 +363,42 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   double uab = 0.0, ubb = 0.0, cab = kRb * wd(D_KR), sab = kRb * wd(D_KR + 1);
   DepSky::add(g, kRb * ca, td(D_KR));
   DepSky::add(g, kRb * sa, td(D_KR + 1));
-#define PES_LIN_ADJ(off, pb, DEP)              \
+#define PES_LIN_ADJ(off, pb)                   \
   {                                            \
     uab = fma(pb, wd((off)), uab);             \
     ubb = fma(pb, wd((off) + 1), ubb);         \
     cab = fma(pb, wd((off) + 2), cab);         \
     sab = fma(pb, wd((off) + 3), sab);         \
-    DEP::add(g, (pb) * ua, td((off)));         \
-    DEP::add(g, (pb) * ub, td((off) + 1));     \
-    DEP::add(g, (pb) * ca, td((off) + 2));     \
-    DEP::add(g, (pb) * sa, td((off) + 3));     \
-    DEP::add(g, (pb), td((off) + 4));          \
   }
-  PES_LIN_ADJ(D_KN, knb0, DepSky)
-  PES_LIN_ADJ(D_KN + 5, knb1, DepSky)
-  PES_LIN_ADJ(D_NP, npb0, DepSkyPsi)
-  PES_LIN_ADJ(D_NP + 5, npb1, DepSkyPsi)
-  PES_LIN_ADJ(D_NQ, nqb0, DepSkyPsi)
-  PES_LIN_ADJ(D_NQ + 5, nqb1, DepSkyPsi)
-  PES_LIN_ADJ(D_KD, kdb0, DepSky)
-  PES_LIN_ADJ(D_KD + 5, kdb1, DepSky)
+  PES_LIN_ADJ(D_KN, knb0)
+  PES_LIN_ADJ(D_KN + 5, knb1)
+  PES_LIN_ADJ(D_NP, npb0)
+  PES_LIN_ADJ(D_NP + 5, npb1)
+  PES_LIN_ADJ(D_NQ, nqb0)
+  PES_LIN_ADJ(D_NQ + 5, nqb1)
+  PES_LIN_ADJ(D_KD, kdb0)
+  PES_LIN_ADJ(D_KD + 5, kdb1)
+  // ---- sky part.  The projections are kn_t = k.n_t, np_t = p.n_t,
+  // nq_t = q.n_t, kd_t = k.Delta_t of the unit vectors k, p, q onto the arm
+  // directions n_t and spacecraft offsets Delta_t at t_f, whose coefficients
+  // alone depend on (lambda, beta, psi).  So d l / d theta_J gets
+  //   K.dk_J + P.dp_J + Q.dq_J,  K = sum_t knb_t n_t + kdb_t Delta_t,
+  //   P = sum_t npb_t n_t,  Q = sum_t nqb_t n_t.
+  // The offsets of a centred triangle are Delta_0 = L (n_0 + 2 n_1) / 3 and
+  // Delta_1 = -L (2 n_0 + n_1) / 3, so K = sum_t kap_t n_t.  Writing
+  // n_t = kn_t k + np_t p + nq_t q in the orthonormal triad and using
+  // k.dk = p.dp = q.dq = 0, k.dp = -p.dk, k.dq = -q.dk, p.dq = -q.dp:
+  //   d l / d theta_J += (p.dk_J) S_a + (q.dk_J) S_b + (q.dp_J) S_c,
+  //   S_a = sum_t kap_t np_t - npb_t kn_t,  S_b = sum_t kap_t nq_t - nqb_t kn_t,
+  //   S_c = sum_t npb_t nq_t - nqb_t np_t,
+  // three sums per lane, contracted once per block by the kernel.
+  {
+    const double kap0 = fma(L3, fma(-2.0, kdb1, kdb0), knb0);
+    const double kap1 = fma(L3, fma(2.0, kdb0, -kdb1), knb1);
+    g[kNParams] = fma(kap0, np0, fma(-npb0, kn0, fma(kap1, np1, fma(-npb1, kn1, g[kNParams]))));
+    g[kNParams + 1] = fma(kap0, nq0, fma(-nqb0, kn0, fma(kap1, nq1, fma(-nqb1, kn1, g[kNParams + 1]))));
+    g[kNParams + 2] = fma(npb0, nq0, fma(-nqb0, np0, fma(npb1, nq1, fma(-nqb1, np1, g[kNParams + 2]))));
+  }
 #undef PES_LIN_ADJ
   // ---- orbit at t_f
   double taub = 0.0;

@@ -179,7 +179,7 @@ int ensure_jac(pes_ctx* c, int64_t B) {
   const int64_t need = std::max(ng * cap * (kNParams + 2), nf * cap * kNParams * kNParams);
   if (B <= c->jcap && need <= c->jpart_n) return PES_OK;
   free_jac(c);
-  if (hipMalloc(&c->wtan, sizeof(double) * cap * W_STRIDE * kNParams) != hipSuccess ||
+  if (hipMalloc(&c->wtan, sizeof(double) * cap * (W_STRIDE * kNParams + kTanCompactSlots)) != hipSuccess ||
       hipMalloc(&c->jpart, sizeof(double) * need) != hipSuccess) {
     free_jac(c);
     snprintf(c->err, sizeof(c->err), "derivative workspace for %lld walkers failed", (long long)cap);
@@ -820,7 +820,19 @@ static JacArgs jac_args(const pes_ctx* c, int64_t B, int tile) {
   A.f0 = c->cfg.f0;
   A.df = c->cfg.df;
   A.dt = c->dt;
+  A.theta = nullptr;
   return A;
+}
+
+// The reverse sweep contracts the sky derivatives through the identity
+// Delta_0 = L (n_0 + 2 n_1) / 3, Delta_1 = -L (2 n_0 + n_1) / 3 of a
+// constellation whose spacecraft offsets sum to zero (both orbit models of
+// fill_geometry are such triangles); this checks it for a detector.
+static bool centred_triangle(const DetParams& p) {
+  for (int cc = 0; cc < 3; ++cc)
+    for (int i = 0; i < 5; ++i)
+      if (std::fabs(p.G[0][cc][i] + p.G[1][cc][i] + p.G[2][cc][i]) > 1e-12 * p.L) return false;
+  return true;
 }
 
 int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* grad, void* stream) {
@@ -831,11 +843,19 @@ int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* g
   }
   if (!c->has_data) return PES_ESTATE;
   if (B == 0) return PES_OK;
+  if (c->grad_method == PES_GRAD_ADJOINT)
+    for (int d = 0; d < c->cfg.n_det; ++d)
+      if (!centred_triangle(c->dt.p[d])) {
+        snprintf(c->err, sizeof(c->err), "detector %d: spacecraft offsets do not sum to zero", d);
+        return PES_EINVAL;
+      }
   int st = ensure_jac(c, B);
   if (st != PES_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   PES_HIP(c, launch_setup_tan(theta, B, c->wtab, c->wtan, c->ntiles, setup_args(c), s));
-  PES_HIP(c, launch_grad(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, c->dd, jac_args(c, B, kGradTile),
+  JacArgs A = jac_args(c, B, kGradTile);
+  A.theta = theta;
+  PES_HIP(c, launch_grad(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, c->dd, A,
                          c->long_sinc, c->grad_method == PES_GRAD_ADJOINT, logl, grad, s));
   return PES_OK;
 }

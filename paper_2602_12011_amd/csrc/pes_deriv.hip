@@ -267,17 +267,17 @@ __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const d
   const double ftc = frac_prod(br.f, wt[W_TC]);
 #pragma unroll 1
   for (int u = 0; u < A.plan.n_pairs; ++u)
-    adj_unit<GEO, LS, true>(wt, wtn, det, A.plan.lead[u], A.plan.member[u], P.inv_year, P.inv_ptq, br, a, ftc, ybs, g);
+    adj_unit<GEO, LS, true>(wt, wtn, det, A.plan.lead[u], A.plan.member[u], P.inv_year, P.inv_ptq, P.L * (1.0 / 3.0), br, a, ftc, ybs, g);
 #pragma unroll 1
   for (int u = A.plan.n_pairs; u < A.plan.n_units; ++u)
-    adj_unit<GEO, LS, false>(wt, wtn, det, A.plan.lead[u], 0, P.inv_year, P.inv_ptq, br, a, ftc, ybs, g);
+    adj_unit<GEO, LS, false>(wt, wtn, det, A.plan.lead[u], 0, P.inv_year, P.inv_ptq, P.L * (1.0 / 3.0), br, a, ftc, ybs, g);
 }
 
-// The walker's tangents are staged in LDS in the compact layout (4.5 KiB):
-// the contraction reads ~150 of them per mode unit as wave-uniform LDS
-// broadcasts, which keeps them out of the scalar registers and their spills
-// (the walker table itself stays on scalar loads: staging it too moves the
-// pressure into vector registers).
+// The walker's tangents are staged in LDS in the compact layout (4.6 KiB,
+// written once per walker by compact_tan_kernel): the contraction reads the
+// mode entries' ones as wave-uniform LDS broadcasts, which keeps them out of
+// the scalar registers and their spills (the walker table itself stays on
+// scalar loads: staging it too moves the pressure into vector registers).
 // Two waves per SIMD: the reverse sweep fits 254 registers (a couple of
 // spilled values); one wave per SIMD leaves its long dependency chains exposed.
 template <bool LS>
@@ -296,14 +296,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
   if (k0 >= nact) return;
   const int lane = threadIdx.x;
   {
-    compact_tangents(wtan + (int64_t)b * W_STRIDE * kNParams, tan_s, lane, 64);
+    const double* __restrict__ src = wtan + (int64_t)b * kTanSlots;
+    for (int i = lane; i < kTanSlots; i += 64) tan_s[i] = src[i];
     __syncthreads();
   }
   const double* wtn = tan_s;
   const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
-  double g[kNParams];
+  double g[kNParams + 3];
 #pragma unroll
-  for (int i = 0; i < kNParams; ++i) g[i] = 0.0;
+  for (int i = 0; i < kNParams + 3; ++i) g[i] = 0.0;
   double dh = 0.0, hh = 0.0;
   for (int64_t s0 = k0; s0 < kend; s0 += 64) {
     const int64_t k = s0 + lane;
@@ -316,6 +317,20 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
         adj_det<LS, false>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, yb_s + 12 * lane);
     }
   }
+  {
+    // the sky sums: g_J += (p.dk_J) S_a + (q.dk_J) S_b + (q.dp_J) S_c for
+    // J = (lambda, beta, psi).  With the basis of sky_basis (k = -(cos b cos l,
+    // cos b sin l, sin b), u = (-sin l, cos l, 0), v = (-sin b cos l,
+    // -sin b sin l, cos b), p = cos psi u + sin psi v, q = -sin psi u + cos psi v):
+    // dk/dl = -cos b u, dk/db = -v, dp/dl = cos psi (cos b k + sin b v) - sin psi sin b u,
+    // dp/db = sin psi k, dp/dpsi = q; hence p.dk = (-cos b cos psi, -sin psi, 0),
+    // q.dk = (cos b sin psi, -cos psi, 0), q.dp = (sin b, 0, 1).
+    const double* th = A.theta + (int64_t)b * kNParams;
+    const double sb = sin(th[8]), cb = cos(th[8]), sps = sin(th[9]), cps = cos(th[9]);
+    g[7] = fma(-cb * cps, g[kNParams], fma(cb * sps, g[kNParams + 1], fma(sb, g[kNParams + 2], g[7])));
+    g[8] = fma(-sps, g[kNParams], fma(-cps, g[kNParams + 1], g[8]));
+    g[9] += g[kNParams + 2];
+  }
   double red[kNParams + 2];
 #pragma unroll
   for (int i = 0; i < kNParams; ++i) red[i] = wave_sum_dpp(g[i]);
@@ -326,6 +341,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
 #pragma unroll
     for (int i = 0; i < kNParams + 2; ++i) p[i] = red[i];
   }
+}
+
+// The compact tangent table of each walker (one block of 64 per walker).
+__global__ void __launch_bounds__(64) compact_tan_kernel(const double* __restrict__ wtan, double* __restrict__ wtanc) {
+  const int b = blockIdx.x;
+  compact_tangents(wtan + (int64_t)b * W_STRIDE * kNParams, wtanc + (int64_t)b * kTanSlots, threadIdx.x, 64);
 }
 
 // Per walker, tiles summed in order.  logl = <d|h> - <h|h>/2 - <d|d>/2.
@@ -375,10 +396,14 @@ hipError_t launch_grad(const double* bins, const double* tabs, const double* wta
                        double* logl, double* grad, hipStream_t s) {
   const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
   if (adjoint) {
+    if (!A.theta) return hipErrorInvalidValue;
+    // the compact tables follow the full ones of the batch in the same buffer
+    double* wtanc = const_cast<double*>(wtan) + (int64_t)A.B * W_STRIDE * kNParams;
+    hipLaunchKernelGGL(compact_tan_kernel, dim3((unsigned)A.B), dim3(64), 0, s, wtan, wtanc);
     if (long_sinc)
-      hipLaunchKernelGGL((adj_kernel<true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+      hipLaunchKernelGGL((adj_kernel<true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtanc, partial, A);
     else
-      hipLaunchKernelGGL((adj_kernel<false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtan, partial, A);
+      hipLaunchKernelGGL((adj_kernel<false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtanc, partial, A);
   } else if (long_sinc) {
     hipLaunchKernelGGL((forward_grad_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   } else {

@@ -56,6 +56,9 @@ struct ResponseArgs {
   DetTable dt;
 };
 
+// Doubles per walker of the compact tangent table of the reverse sweep.
+constexpr int kTanCompactSlots = 584;
+
 struct JacArgs {
   int64_t N;
   int B, n_modes, n_det;
@@ -63,6 +66,7 @@ struct JacArgs {
   int tile;           // bins per block (a multiple of 64)
   double f0, df;
   DetTable dt;
+  const double* theta;   // [B][11] (the reverse sweep's sky contraction)
 };
 
 hipError_t launch_grad(const double* bins, const double* tabs, const double* wtab, const double* wtan,
