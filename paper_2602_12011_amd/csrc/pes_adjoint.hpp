@@ -28,13 +28,6 @@ __device__ __forceinline__ double opaque(double x) {
   asm volatile("" : "+v"(x));
   return x;
 }
-// The same for a wave-uniform int: table offsets rebuilt from it after such a
-// point make the compiler load the entries again (scalar cache hits) instead
-// of keeping the earlier loads in scalar registers across the whole unit.
-__device__ __forceinline__ int opaque_u(int x) {
-  asm volatile("" : "+s"(x));
-  return x;
-}
 
 // g[J...] += cbar * d(entry)/d(theta_J) for the parameters J the entry depends
 // on (the setup makes every other derivative exactly zero).  tan_row holds

@@ -202,11 +202,13 @@ __device__ __forceinline__ void fisher_dense_body(const double* __restrict__ bin
     partial[((int64_t)t * A.B + b) * (kNParams * kNParams) + row * kNParams + col] = sum;
 }
 
-// Two waves per SIMD: the dense Fisher body needs about 200 registers (held
-// to 168 for a third wave it spills 30 of them, and measures the same); the
-// gradient variant holds the residual as well and runs two without spilling.
+// Three waves per SIMD for the dense Fisher body: with the detector entries
+// loaded per geometry section (opaque_u in eval_channels_t) it fits 168
+// registers with two spilled values (before that, 200; the third wave is
+// worth 7% here); 3 blocks of 50 KiB of LDS per CU.  The gradient variant
+// holds the residual as well and runs two without spilling.
 template <bool LS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     forward_fisher_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                           const double* __restrict__ wtab, const double* __restrict__ wtan,
                           double* __restrict__ partial, JacArgs A) {

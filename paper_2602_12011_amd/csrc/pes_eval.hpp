@@ -119,6 +119,14 @@ struct BinRegs {
   double f, f13, fm13, fm76, lnf;
 };
 
+// A wave-uniform int the compiler must treat as unknown: table offsets built
+// from it inside a loop are not hoisted out of it (the entries are loaded again
+// from the scalar cache instead of held in scalar registers across the loop).
+__device__ __forceinline__ int opaque_u(int x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
 struct Chan {
   double ar, ai, er, ei, tr, ti;
 };
@@ -159,7 +167,6 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
   const S ftc = frac_prod(b.f, T(W_TC));
   const double half_f = 0.5 * b.f;
   const double pi_f = kPi * b.f;
-  const int D0 = W_DET0 + det * W_DET_STRIDE;
 
   // One evaluation unit: mode j and, when PAIR, the mode jm with the same m
   // added as a complex amplitude on j's phase factor.
@@ -221,7 +228,10 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
       aC2 = fma(am, T(R0 + R_KCR), aC2);
       aCi = am * T(R0 + R_KCI);
     }
-    // spacecraft geometry at t_f
+    // spacecraft geometry at t_f.  In the tangent kernels the detector entries
+    // are loaded from here on (opaque_u), which keeps their scalar registers
+    // free through the waveform part; the value kernels keep the default.
+    const int D0 = W_DET0 + (std::is_same<S, double>::value ? det : opaque_u(det)) * W_DET_STRIDE;
     S sa, ca;
     sincos_cycles(tau * inv_year + wd(D_AO), sa, ca);
     S kn0, kn1, kn2, np0, np1, np2, nq0, nq1, nq2, kd0, kd1, kR;
