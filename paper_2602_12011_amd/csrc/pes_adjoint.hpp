@@ -41,12 +41,6 @@ struct Deps {
 };
 // theta = (M, q, chi1, chi2, D_L, iota, phi_c, lambda, beta, psi, t_c)
 using DepM = Deps<0>;
-using DepQ = Deps<1>;
-using DepQPhi = Deps<1, 6>;
-using DepQChi = Deps<1, 2, 3>;
-using DepMQ = Deps<0, 1>;
-using DepMQChi = Deps<0, 1, 2, 3>;
-using DepMQD = Deps<0, 1, 4>;
 using DepIota = Deps<5>;
 using DepSky = Deps<7, 8>;
 using DepTc = Deps<10>;
@@ -412,7 +406,6 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   const double ampb = fma(aPb, wm(M_KP), aCb * wm(M_KC));   // aCb: adjoint of 2 aC
   double xb = ampb * amp0 * dtap;
   const double qa = ampb * tap * b.fm76;
-  DepMQD::add(g, qa, tm(M_AM0));
   double qn = 0.0;
   if (PAIR) {
     DepIota::add(g, aPb * amn, tr(R_KPR));
@@ -422,7 +415,6 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
     const double amnb = fma(aPb, wr(R_KPR), fma(aPib, wr(R_KPI), fma(aCb, wr(R_KCR), aCib * wr(R_KCI))));
     xb = fma(amnb * amn0, dtap, xb);
     qn = amnb * tap * b.fm76;
-    DepMQD::add(g, qn, tnm(M_AM0));
   }
   DepM::add(g, xb * b.f, tm(M_FCI));
   // recompute the waveform powers (from opaque copies of the bin values, so
@@ -432,23 +424,35 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   const double lnv = opaque(b.lnf) * (1.0 / 3.0) + wm(M_LNCM);
   const double w2 = w * w, w3 = w2 * w, w4 = w2 * w2, w5 = w4 * w, w6 = w4 * w2, w8 = w4 * w4;
   const double v2 = v * v, lv = lnv * v, lw2 = lnv * w2;
-  DepMQD::add(g, qa * v, tm(M_AM1));
-  DepMQD::add(g, qa * v2, tm(M_AM2));
-  double vb = qa * fma(2.0 * wm(M_AM2), v, wm(M_AM1));
-  if (PAIR) {
-    DepMQD::add(g, qn * v, tnm(M_AM1));
-    DepMQD::add(g, qn * v2, tnm(M_AM2));
-    vb = fma(qn, fma(2.0 * wn(M_AM2), v, wn(M_AM1)), vb);
+  // The contractions below group each parameter's terms first (sum over the
+  // entries of basis value x tangent) and scale by the common adjoint once.
+  // amplitude: A = AM0 + AM1 v + AM2 v^2 on (M, q, D_L)
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int J = r == 2 ? 4 : r;
+    double d = fma(v2, tm(M_AM2)[r], fma(v, tm(M_AM1)[r], tm(M_AM0)[r]));
+    if (PAIR) d = fma(qn, fma(v2, tnm(M_AM2)[r], fma(v, tnm(M_AM1)[r], tnm(M_AM0)[r])), qa * d);
+    else d = qa * d;
+    g[J] += d;
   }
+  double vb = qa * fma(2.0 * wm(M_AM2), v, wm(M_AM1));
+  if (PAIR) vb = fma(qn, fma(2.0 * wn(M_AM2), v, wn(M_AM1)), vb);
   // ---- t_f - t_c
-  DepMQ::add(g, taub * w, tm(M_T7));
-  DepMQ::add(g, taub * w2, tm(M_T6));
-  DepMQ::add(g, taub * lw2, tm(M_T6L));
-  DepMQ::add(g, taub * w3, tm(M_T5));
-  DepMQChi::add(g, taub * w4, tm(M_T4));
-  DepMQChi::add(g, taub * w5, tm(M_T3));
-  DepMQ::add(g, taub * w6, tm(M_T2));
-  DepMQ::add(g, taub * w8, tm(M_T0));
+  // t_f series on (M, q) for every entry, (chi1, chi2) for T4 and T3
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    double d = w * tm(M_T7)[r];
+    d = fma(w2, tm(M_T6)[r], d);
+    d = fma(lw2, tm(M_T6L)[r], d);
+    d = fma(w3, tm(M_T5)[r], d);
+    d = fma(w4, tm(M_T4)[r], d);
+    d = fma(w5, tm(M_T3)[r], d);
+    d = fma(w6, tm(M_T2)[r], d);
+    d = fma(w8, tm(M_T0)[r], d);
+    g[r] = fma(taub, d, g[r]);
+  }
+#pragma unroll
+  for (int r = 2; r < 4; ++r) g[r] = fma(taub, fma(w4, tm(M_T4)[r], w5 * tm(M_T3)[r]), g[r]);
   // d tau / d w
   double dtw = 8.0 * wm(M_T0) * w;
   dtw = fma(dtw, w, 6.0 * wm(M_T2));
@@ -462,15 +466,20 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   // ---- phase
   const double phb = Phib;
   DepTc::add(g, phb * b.f, tn);
-  DepQPhi::add(g, phb, tm(M_C0));
-  DepQ::add(g, phb * w5, tm(M_A0));
-  DepQ::add(g, phb * w3, tm(M_A2));
-  DepQChi::add(g, phb * w2, tm(M_A3));
-  DepQChi::add(g, phb * w, tm(M_A4));
-  DepQ::add(g, phb * lnv, tm(M_B5));
-  DepQ::add(g, phb * v, tm(M_A6));
-  DepQ::add(g, phb * lv, tm(M_B6));
-  DepQ::add(g, phb * v2, tm(M_A7));
+  {   // phase series on q for every entry, (chi1, chi2) for A3 and A4, phi_c for C0
+    double d = fma(w5, tm(M_A0)[0], tm(M_C0)[0]);
+    d = fma(w3, tm(M_A2)[0], d);
+    d = fma(w2, tm(M_A3)[0], d);
+    d = fma(w, tm(M_A4)[0], d);
+    d = fma(lnv, tm(M_B5)[0], d);
+    d = fma(v, tm(M_A6)[0], d);
+    d = fma(lv, tm(M_B6)[0], d);
+    d = fma(v2, tm(M_A7)[0], d);
+    g[1] = fma(phb, d, g[1]);
+#pragma unroll
+    for (int r = 1; r < 3; ++r) g[r + 1] = fma(phb, fma(w2, tm(M_A3)[r], w * tm(M_A4)[r]), g[r + 1]);
+    g[6] = fma(phb, tm(M_C0)[1], g[6]);
+  }
   const double dpw = fma(fma(5.0 * wm(M_A0), w2, 3.0 * wm(M_A2)), w2, fma(2.0 * wm(M_A3), w, wm(M_A4)));
   wb = fma(phb, dpw, wb);
   lnvb = fma(phb, fma(wm(M_B6), v, wm(M_B5)), lnvb);

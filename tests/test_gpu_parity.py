@@ -43,7 +43,7 @@ def _check_loglike(orc, cfg, d, L_gpu, th, what):
     L_or = orc.loglike(cfg, d, th)
     sigma = 0.5 * orc.inner(cfg, d, d)
     both_inf = np.isneginf(L_or) & np.isneginf(L_gpu)
-    err = np.where(both_inf, 0.0, np.abs(L_gpu - L_or))
+    err = np.abs(np.where(both_inf, 0.0, L_gpu) - np.where(both_inf, 0.0, L_or))
     bound = RTOL_L * np.maximum(np.abs(np.where(both_inf, 0.0, L_or)), sigma)
     worst = np.argmax(err / bound)
     assert np.all(err <= bound), (
