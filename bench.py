@@ -452,7 +452,8 @@ def kepler_leg(torch, pes, steps):
     """The headline workload with the heliocentric detector on exact Kepler
     ellipses (arms flexing at order e^2 AU) instead of the first-order
     triangle: evals/s at the autotuned tuning and the cost relative to the
-    first-order orbit in the same run."""
+    first-order orbit in the same run; then the derivatives on both orbits
+    (Fisher matrices at 256 points, forward-mode gradients at 1024 walkers)."""
     out = {}
     for orbit in ("first_order", "kepler"):
         cfg = W.config("cfg1")
@@ -468,13 +469,20 @@ def kepler_leg(torch, pes, steps):
         _, tuning = ctx.autotune(theta)
         out[orbit] = dict(ms_per_call=round(_time_ms(torch, lambda: ctx.loglike(theta, o), steps), 3),
                           tuning=tuning)
+        thf = theta[:256].contiguous()
+        thg = theta[:1024].contiguous()
+        ctx.set_grad_method("forward")
+        out[orbit]["fisher_ms"] = round(_time_ms(torch, lambda: ctx.fisher(thf), 2), 3)
+        out[orbit]["grad_forward_ms"] = round(_time_ms(torch, lambda: ctx.grad(thg), 1), 3)
         ctx.close()
     k, f = out["kepler"], out["first_order"]
     return dict(workload="LISA-like on exact Kepler ellipses, 5 modes, 2^20 bins (df=1/yr), 4096 walkers, "
-                         "noise-free injection",
+                         "noise-free injection; Fisher at 256 and forward-mode gradients at 1024 of them",
                 ms_per_call=k["ms_per_call"], evals_per_s=round(4096 / (k["ms_per_call"] * 1e-3), 1),
                 tuning=k["tuning"], first_order_ms_per_call_same_run=f["ms_per_call"],
-                cost_over_first_order=round(k["ms_per_call"] / f["ms_per_call"], 3))
+                cost_over_first_order=round(k["ms_per_call"] / f["ms_per_call"], 3),
+                fisher_ms=k["fisher_ms"], fisher_first_order_ms=f["fisher_ms"],
+                grad_forward_ms=k["grad_forward_ms"], grad_forward_first_order_ms=f["grad_forward_ms"])
 
 
 EXTRINSIC = (7, 8, 9, 10)   # lambda, beta, psi, t_c

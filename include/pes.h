@@ -70,9 +70,9 @@ typedef struct {
                           heliocentric detector of a context takes the same); TianQin: 0.
                           With PES_ORBIT_KEPLER the link directions are the unit separations
                           of the spacecraft at t_f, the transfer function and the TDI factor
-                          keep the nominal L; such a context evaluates log L and the response
-                          in FP64 (pes_grad, pes_fisher, pes_probe and pes_set_precision(32)
-                          return PES_EINVAL). */
+                          keep the nominal L; such a context evaluates in FP64 (pes_probe
+                          and pes_set_precision(32) return PES_EINVAL), its derivatives in
+                          forward mode. */
 } pes_detector;
 
 typedef struct {
@@ -188,7 +188,8 @@ int pes_set_precision(pes_ctx* ctx, int bits);
  * response in reverse mode): logl (dev) [B] (may be NULL), grad (dev) [B][11]
  * in the units of theta.  Requires pes_set_data.  Unphysical samples:
  * logl = -inf, grad = 0.  B <= 65535.  The method is chosen per context by
- * pes_set_grad_method; both give the same values up to rounding. */
+ * pes_set_grad_method; both give the same values up to rounding.  Contexts on
+ * exact Kepler orbits always use the forward-mode evaluation. */
 int pes_grad(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double* grad, void* stream);
 
 /* Gradient method of pes_grad:
@@ -196,8 +197,9 @@ int pes_grad(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double*
  *     forward values recomputed (no per-bin storage); adjoints of the walker
  *     table's mode entries contracted with their theta-derivatives, those of
  *     the sky projections reduced through the orthonormal sky basis (this
- *     needs spacecraft offsets that sum to zero, as both orbit models here
- *     have; pes_grad returns PES_EINVAL otherwise).
+ *     needs spacecraft offsets that sum to zero, as the first-order orbits
+ *     have; pes_grad returns PES_EINVAL otherwise, and contexts on exact
+ *     Kepler orbits take the forward-mode path whatever this setting).
  *   PES_GRAD_FORWARD: forward-mode tangents, one (bin, parameter direction)
  *     pair per lane (the evaluation of pes_fisher); the cross-check.
  * PES_EINVAL for another value. */
@@ -208,7 +210,8 @@ int pes_set_grad_method(pes_ctx* ctx, int method);
  * eq_inner_product) from the forward-mode Jacobian of the A/E/T response, the
  * J^T W J contraction on FP64 matrix cores: F (dev) [B][11][11], symmetric,
  * in the units of theta.  Independent of the data.  Unphysical samples: NaN.
- * B <= 65535. */
+ * B <= 65535.  On exact Kepler orbits the projected orbit series carry their
+ * sky-angle derivatives into the tangents. */
 int pes_fisher(pes_ctx* ctx, const double* theta, int64_t B, double* F, void* stream);
 
 /* ---- Sampler.  Bayes' theorem splits the posterior into prior and

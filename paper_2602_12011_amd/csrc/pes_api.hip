@@ -79,6 +79,7 @@ struct pes_ctx {
   double* wtab = nullptr;
   float* wtab32 = nullptr;    // FP32 copy of wtab (single-precision kernels)
   double* wkep = nullptr;     // [cap][n_det][KW_STRIDE] projected orbit series (Kepler contexts)
+  double* wkept = nullptr;    // [jcap][n_det][3][KW_STRIDE] their sky-angle derivatives (Kepler contexts)
   int* ntiles = nullptr;
   int* perm = nullptr;
   int* gstart = nullptr;
@@ -166,7 +167,8 @@ constexpr int kFisherTile = 1024;
 void free_jac(pes_ctx* c) {
   (void)hipFree(c->wtan);
   (void)hipFree(c->jpart);
-  c->wtan = c->jpart = nullptr;
+  (void)hipFree(c->wkept);
+  c->wtan = c->jpart = c->wkept = nullptr;
   c->jcap = 0;
   c->jpart_n = 0;
 }
@@ -180,7 +182,8 @@ int ensure_jac(pes_ctx* c, int64_t B) {
   if (B <= c->jcap && need <= c->jpart_n) return PES_OK;
   free_jac(c);
   if (hipMalloc(&c->wtan, sizeof(double) * cap * (W_STRIDE * kNParams + kTanCompactSlots)) != hipSuccess ||
-      hipMalloc(&c->jpart, sizeof(double) * need) != hipSuccess) {
+      hipMalloc(&c->jpart, sizeof(double) * need) != hipSuccess ||
+      (c->kep && hipMalloc(&c->wkept, sizeof(double) * cap * c->cfg.n_det * 3 * KW_STRIDE) != hipSuccess)) {
     free_jac(c);
     snprintf(c->err, sizeof(c->err), "derivative workspace for %lld walkers failed", (long long)cap);
     return PES_ENOMEM;
@@ -582,7 +585,7 @@ int pes_autotune(pes_ctx* c, const double* theta, int64_t B, double* logl, doubl
 int pes_reserve(pes_ctx* c, int64_t max_walkers) {
   if (!c || max_walkers < 0) return PES_EINVAL;
   const int st = ensure_workspace(c, max_walkers);
-  if (st != PES_OK || max_walkers == 0 || c->kep) return st;   // no derivatives on exact Kepler orbits
+  if (st != PES_OK || max_walkers == 0) return st;
   return ensure_jac(c, std::min<int64_t>(max_walkers, kMaxDerivBatch));
 }
 
@@ -821,7 +824,20 @@ static JacArgs jac_args(const pes_ctx* c, int64_t B, int tile) {
   A.df = c->cfg.df;
   A.dt = c->dt;
   A.theta = nullptr;
+  A.kep = A.wkep = A.wkept = nullptr;
   return A;
+}
+
+// Kepler contexts: the walkers' projected orbit series and their sky-angle
+// derivatives for the tangent kernels.
+static int kepler_jac_setup(pes_ctx* c, const double* theta, int64_t B, JacArgs& A, hipStream_t s) {
+  if (!c->kep) return PES_OK;
+  PES_HIP(c, launch_kepler_proj(theta, B, c->kep_tab, setup_args(c), c->wkep, s));
+  PES_HIP(c, launch_kepler_proj_tan(theta, B, c->kep_tab, setup_args(c), c->wkept, s));
+  A.kep = c->kep_tab;
+  A.wkep = c->wkep;
+  A.wkept = c->wkept;
+  return PES_OK;
 }
 
 // The reverse sweep contracts the sky derivatives through the identity
@@ -837,13 +853,12 @@ static bool centred_triangle(const DetParams& p) {
 
 int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* grad, void* stream) {
   if (!c || B < 0 || B > kMaxDerivBatch || (B > 0 && (!theta || !grad))) return PES_EINVAL;
-  if (c->kep) {
-    snprintf(c->err, sizeof(c->err), "derivatives use the first-order orbit only");
-    return PES_EINVAL;
-  }
   if (!c->has_data) return PES_ESTATE;
   if (B == 0) return PES_OK;
-  if (c->grad_method == PES_GRAD_ADJOINT)
+  // exact Kepler orbits: the forward-mode evaluation (the reverse sweep's sky
+  // contraction assumes a rigid triangle)
+  const bool adjoint = c->grad_method == PES_GRAD_ADJOINT && !c->kep;
+  if (adjoint)
     for (int d = 0; d < c->cfg.n_det; ++d)
       if (!centred_triangle(c->dt.p[d])) {
         snprintf(c->err, sizeof(c->err), "detector %d: spacecraft offsets do not sum to zero", d);
@@ -855,8 +870,10 @@ int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* g
   PES_HIP(c, launch_setup_tan(theta, B, c->wtab, c->wtan, c->ntiles, setup_args(c), s));
   JacArgs A = jac_args(c, B, kGradTile);
   A.theta = theta;
-  PES_HIP(c, launch_grad(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, c->dd, A,
-                         c->long_sinc, c->grad_method == PES_GRAD_ADJOINT, logl, grad, s));
+  st = kepler_jac_setup(c, theta, B, A, s);
+  if (st != PES_OK) return st;
+  PES_HIP(c, launch_grad(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, c->dd, A, c->long_sinc, adjoint, logl,
+                         grad, s));
   return PES_OK;
 }
 
@@ -884,17 +901,15 @@ int pes_set_grad_method(pes_ctx* c, int method) {
 
 int pes_fisher(pes_ctx* c, const double* theta, int64_t B, double* F, void* stream) {
   if (!c || B < 0 || B > kMaxDerivBatch || (B > 0 && (!theta || !F))) return PES_EINVAL;
-  if (c->kep) {
-    snprintf(c->err, sizeof(c->err), "derivatives use the first-order orbit only");
-    return PES_EINVAL;
-  }
   if (B == 0) return PES_OK;
   int st = ensure_jac(c, B);
   if (st != PES_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   PES_HIP(c, launch_setup_tan(theta, B, c->wtab, c->wtan, c->ntiles, setup_args(c), s));
-  PES_HIP(c, launch_fisher(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, jac_args(c, B, kFisherTile),
-                           c->long_sinc, F, s));
+  JacArgs A = jac_args(c, B, kFisherTile);
+  st = kepler_jac_setup(c, theta, B, A, s);
+  if (st != PES_OK) return st;
+  PES_HIP(c, launch_fisher(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, A, c->long_sinc, F, s));
   return PES_OK;
 }
 

@@ -20,6 +20,35 @@ __device__ __forceinline__ int64_t active_bins(double fmx, double f0, double df,
   return (int64_t)nb;
 }
 
+// Exact Kepler orbits in the tangent kernels: the walker's projected series
+// derivatives in the three sky angles for every detector, staged in LDS
+// ([det][angle][KW_STRIDE], then one zero row for the other directions).
+constexpr int kKwtRows = kMaxDet * 3;
+__device__ __forceinline__ void stage_kw_tangents(const JacArgs& A, int b, double* kwt_s) {
+  const double* __restrict__ src = A.wkept + (int64_t)b * A.n_det * 3 * KW_STRIDE;
+  const int n = A.n_det * 3 * KW_STRIDE;
+  for (int i = threadIdx.x; i < (kKwtRows + 1) * KW_STRIDE; i += blockDim.x) kwt_s[i] = i < n ? src[i] : 0.0;
+}
+// This lane's accessor of a heliocentric detector's series (direction p).
+__device__ __forceinline__ KwLane kw_lane(const JacArgs& A, int b, int det, int p, const double* kwt_s) {
+  const int row = (p >= 7 && p <= 9) ? det * 3 + (p - 7) : kKwtRows;
+  return KwLane{A.wkep + ((int64_t)b * A.n_det + det) * KW_STRIDE, kwt_s + row * KW_STRIDE};
+}
+
+// Dual-number channels of one (bin, detector) for the lane's direction p.
+template <bool LS, bool KEP>
+__device__ __forceinline__ ChanT<Dual<1>> eval_tangent(const TanTabLane& T, const JacArgs& A, const DetParams& P,
+                                                       int b, int det, int p, const double* kwt_s,
+                                                       const BinRegs& br, double a, double zr, double zi) {
+  if (P.kind == 2)
+    return eval_channels_t<true, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi);
+  if constexpr (KEP)
+    return eval_channels_t<false, LS, 1, Dual<1>, TanTabLane, NoProbe, true, KwLane>(
+        T, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi, NoProbe(), kw_lane(A, b, det, p, kwt_s),
+        A.kep + det * KV_STRIDE + KV_INVL);
+  return eval_channels_t<false, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi);
+}
+
 // Forward-mode gradient (the cross-check of the reverse sweep), one (bin,
 // parameter) pair per lane: lane l of a wavefront carries the tangent
 // direction p = l % 16 (p < 11; the other five lanes contribute zeros) of bin
@@ -29,12 +58,13 @@ __device__ __forceinline__ int64_t active_bins(double fmx, double f0, double df,
 // is staged in LDS once per block (the lanes read different directions of the
 // same entry); the four wavefronts of a block take interleaved groups of the
 // block's bin tile.
-template <bool LS>
+template <bool LS, bool KEP>
 __device__ __forceinline__ void forward_grad_body(const double* __restrict__ bins, const double* __restrict__ tabs,
                                                   const double* __restrict__ wtab, const double* __restrict__ wtan,
                                                   double* __restrict__ partial, const JacArgs& A) {
   __shared__ double red[4][256];
   __shared__ double tan_s[W_STRIDE * kNParams];   // the walker's tangent table, 25 KiB
+  __shared__ double kwt_s[KEP ? (kKwtRows + 1) * KW_STRIDE : 1];
   const int t = blockIdx.x;
   const int b = blockIdx.y;
   const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
@@ -44,6 +74,7 @@ __device__ __forceinline__ void forward_grad_body(const double* __restrict__ bin
   const int64_t k0 = (int64_t)t * A.tile;
   if (k0 >= nact) return;
   for (int i = threadIdx.x; i < W_STRIDE * kNParams; i += 256) tan_s[i] = wtn[i];
+  if (KEP) stage_kw_tangents(A, b, kwt_s);
   __syncthreads();
   const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -68,11 +99,7 @@ __device__ __forceinline__ void forward_grad_body(const double* __restrict__ bin
       const double wT = in ? tb[T_WT * N + kk] : 0.0;
       const DetParams& P = A.dt.p[det];
       const TanTabLane T{wt, tan_s, pin ? p : 0};
-      const ChanT<Dual<1>> c = (P.kind == 2)
-                                   ? eval_channels_t<true, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year, P.inv_ptq,
-                                                                          br, a, zr, zi)
-                                   : eval_channels_t<false, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year,
-                                                                           P.inv_ptq, br, a, zr, zi);
+      const ChanT<Dual<1>> c = eval_tangent<LS, KEP>(T, A, P, b, det, pin ? p : 0, kwt_s, br, a, zr, zi);
       const double W[6] = {wA, wA, wA * (1.0 / 3.0), wA * (1.0 / 3.0), wT, wT};
       const double D[6] = {in ? tb[T_DAR * N + kk] : 0.0, in ? tb[T_DAI * N + kk] : 0.0,
                            in ? tb[T_DER * N + kk] : 0.0, in ? tb[T_DEI * N + kk] : 0.0,
@@ -117,12 +144,13 @@ __device__ __forceinline__ void forward_grad_body(const double* __restrict__ bin
 // round and one is partly written: twelve ring slots suffice.
 constexpr int kRing = 12;
 
-template <bool LS>
+template <bool LS, bool KEP>
 __device__ __forceinline__ void fisher_dense_body(const double* __restrict__ bins, const double* __restrict__ tabs,
                                                   const double* __restrict__ wtab, const double* __restrict__ wtan,
                                                   double* __restrict__ partial, const JacArgs& A) {
   __shared__ double tan_s[W_STRIDE * kNParams];             // the walker's tangent table, 25 KiB
   __shared__ double ring[4][kRing][6][kNParams];            // per wave; reused for the final sums
+  __shared__ double kwt_s[KEP ? (kKwtRows + 1) * KW_STRIDE : 1];
   const int t = blockIdx.x;
   const int b = blockIdx.y;
   const double* __restrict__ wt = wtab + (int64_t)b * W_STRIDE;
@@ -132,6 +160,7 @@ __device__ __forceinline__ void fisher_dense_body(const double* __restrict__ bin
   const int64_t k0 = (int64_t)t * A.tile;
   if (k0 >= nact) return;
   for (int i = threadIdx.x; i < W_STRIDE * kNParams; i += 256) tan_s[i] = wtn[i];
+  if (KEP) stage_kw_tangents(A, b, kwt_s);
   __syncthreads();
   const int64_t kend = k0 + A.tile < nact ? k0 + A.tile : nact;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -161,11 +190,7 @@ __device__ __forceinline__ void fisher_dense_body(const double* __restrict__ bin
         const double sA = in ? sqrt(tb[T_WA * N + kk]) : 0.0;
         const double sT = in ? sqrt(tb[T_WT * N + kk]) : 0.0;
         const TanTabLane T{wt, tan_s, p};
-        const ChanT<Dual<1>> c = (P.kind == 2)
-                                     ? eval_channels_t<true, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year, P.inv_ptq,
-                                                                            br, a, zr, zi)
-                                     : eval_channels_t<false, LS, 1, Dual<1>>(T, det, A.plan, P.inv_year,
-                                                                             P.inv_ptq, br, a, zr, zi);
+        const ChanT<Dual<1>> c = eval_tangent<LS, KEP>(T, A, P, b, det, p, kwt_s, br, a, zr, zi);
         const double sE = sA * 0.5773502691896258;   // W_E = W_A / 3
         const double v[6] = {sA * c.ar.d[0], sA * c.ai.d[0], sE * c.er.d[0],
                              sE * c.ei.d[0], sT * c.tr.d[0], sT * c.ti.d[0]};
@@ -212,14 +237,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     forward_fisher_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                           const double* __restrict__ wtab, const double* __restrict__ wtan,
                           double* __restrict__ partial, JacArgs A) {
-  fisher_dense_body<LS>(bins, tabs, wtab, wtan, partial, A);
+  fisher_dense_body<LS, false>(bins, tabs, wtab, wtan, partial, A);
 }
 template <bool LS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     forward_grad_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                         const double* __restrict__ wtab, const double* __restrict__ wtan,
                         double* __restrict__ partial, JacArgs A) {
-  forward_grad_body<LS>(bins, tabs, wtab, wtan, partial, A);
+  forward_grad_body<LS, false>(bins, tabs, wtab, wtan, partial, A);
+}
+// The same on exact Kepler orbits (9 KiB more LDS for the series derivatives:
+// two blocks per CU).
+template <bool LS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    forward_fisher_kep_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
+                              const double* __restrict__ wtab, const double* __restrict__ wtan,
+                              double* __restrict__ partial, JacArgs A) {
+  fisher_dense_body<LS, true>(bins, tabs, wtab, wtan, partial, A);
+}
+template <bool LS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    forward_grad_kep_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
+                            const double* __restrict__ wtab, const double* __restrict__ wtan,
+                            double* __restrict__ partial, JacArgs A) {
+  forward_grad_body<LS, true>(bins, tabs, wtab, wtan, partial, A);
 }
 
 // Reverse-mode gradient: for each (walker, bin, detector) one forward
@@ -397,6 +438,8 @@ hipError_t launch_grad(const double* bins, const double* tabs, const double* wta
                        double* partial, const double* dd, const JacArgs& A, bool long_sinc, bool adjoint,
                        double* logl, double* grad, hipStream_t s) {
   const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
+  const bool kep = A.wkep != nullptr;
+  if (kep && (adjoint || !A.kep || !A.wkept)) return hipErrorInvalidValue;
   if (adjoint) {
     if (!A.theta) return hipErrorInvalidValue;
     // the compact tables follow the full ones of the batch in the same buffer
@@ -406,6 +449,10 @@ hipError_t launch_grad(const double* bins, const double* tabs, const double* wta
       hipLaunchKernelGGL((adj_kernel<true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtanc, partial, A);
     else
       hipLaunchKernelGGL((adj_kernel<false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtanc, partial, A);
+  } else if (kep && long_sinc) {
+    hipLaunchKernelGGL((forward_grad_kep_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
+  } else if (kep) {
+    hipLaunchKernelGGL((forward_grad_kep_kernel<false>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   } else if (long_sinc) {
     hipLaunchKernelGGL((forward_grad_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   } else {
@@ -419,7 +466,13 @@ hipError_t launch_grad(const double* bins, const double* tabs, const double* wta
 hipError_t launch_fisher(const double* bins, const double* tabs, const double* wtab, const double* wtan,
                          double* partial, const JacArgs& A, bool long_sinc, double* F, hipStream_t s) {
   const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
-  if (long_sinc)
+  const bool kep = A.wkep != nullptr;
+  if (kep && (!A.kep || !A.wkept)) return hipErrorInvalidValue;
+  if (kep && long_sinc)
+    hipLaunchKernelGGL((forward_fisher_kep_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
+  else if (kep)
+    hipLaunchKernelGGL((forward_fisher_kep_kernel<false>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
+  else if (long_sinc)
     hipLaunchKernelGGL((forward_fisher_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   else
     hipLaunchKernelGGL((forward_fisher_kernel<false>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);

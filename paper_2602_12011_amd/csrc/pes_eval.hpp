@@ -29,6 +29,21 @@ struct TanTab {
   }
 };
 
+// The projected Kepler orbit series of a walker in the tangent kernels: the
+// values (wavefront-uniform) and this lane's tangent row (zeros unless its
+// direction is a sky angle).
+struct KwLane {
+  const double* __restrict__ v;
+  const double* __restrict__ t;
+};
+__device__ __forceinline__ double kw_at(const double* __restrict__ kw, int i) { return kw[i]; }
+__device__ __forceinline__ Dual<1> kw_at(const KwLane& kw, int i) {
+  Dual<1> r;
+  r.v = kw.v[i];
+  r.d[0] = kw.t[i];
+  return r;
+}
+
 // The same with a direction that may differ between lanes (the values stay
 // wavefront-uniform, the tangents are per-lane loads).
 struct TanTabLane {
@@ -150,15 +165,17 @@ struct NoProbe {
 // Tab: accessor of this walker's constant table (wavefront-uniform); det: the
 // detector block.  S = double (values) or Dual<1> (value and one tangent).
 // GEO selects the geocentric orbit.  a = pi f L, (zr, zi) = e^{-2 pi i f L}.
-// KEP: heliocentric detector on exact Kepler ellipses (S = double only); kw:
-// the walker's projected orbit series for this detector [KW_STRIDE], kinv: the
+// KEP: heliocentric detector on exact Kepler ellipses; kw: the walker's
+// projected orbit series for this detector [KW_STRIDE] (a KwLane for S =
+// Dual<1>), kinv: the
 // detector's inverse-arm-length series [3][kKepT].
-template <bool GEO, bool LONG_SINC, int CLS, class S, class Tab, class Probe = NoProbe, bool KEP = false>
+template <bool GEO, bool LONG_SINC, int CLS, class S, class Tab, class Probe = NoProbe, bool KEP = false,
+          class KWA = const double*>
 __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const ModePlan& plan,
                                                     double inv_year, double inv_ptq, const BinRegs& b,
                                                     double a, double zr, double zi,
                                                     const Probe& probe = Probe(),
-                                                    const double* __restrict__ kw = nullptr,
+                                                    KWA kw = KWA(),
                                                     const double* __restrict__ kinv = nullptr) {
   S yFr0 = 0.0, yFi0 = 0.0, yBr0 = 0.0, yBi0 = 0.0;
   S yFr1 = 0.0, yFi1 = 0.0, yBr1 = 0.0, yBi1 = 0.0;
@@ -255,10 +272,18 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
         for (int k = 1; k <= kKepH; ++k) r = fma(c[2 * k - 1], hc[k], fma(c[2 * k], hs[k], r));
         return r;
       };
+      // the same over the walker's series (coefficients with tangents in the tangent kernels)
+      auto series_w = [&](int off) __attribute__((always_inline)) {
+        S r = kw_at(kw, off);
+#pragma unroll
+        for (int k = 1; k <= kKepH; ++k)
+          r = fma(kw_at(kw, off + 2 * k - 1), hc[k], fma(kw_at(kw, off + 2 * k), hs[k], r));
+        return r;
+      };
       const S iL0 = series(kinv), iL1 = series(kinv + kKepT), iL2 = series(kinv + 2 * kKepT);
-      const S KD0 = series(kw + KW_KD0), KD1 = series(kw + KW_KD1);
-      const S PD0 = series(kw + KW_PD0), PD1 = series(kw + KW_PD1);
-      const S QD0 = series(kw + KW_QD0), QD1 = series(kw + KW_QD1);
+      const S KD0 = series_w(KW_KD0), KD1 = series_w(KW_KD1);
+      const S PD0 = series_w(KW_PD0), PD1 = series_w(KW_PD1);
+      const S QD0 = series_w(KW_QD0), QD1 = series_w(KW_QD1);
       kn0 = KD0 * iL0;
       kn1 = KD1 * iL1;
       kn2 = -(KD0 + KD1) * iL2;
@@ -268,9 +293,9 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
       nq0 = QD0 * iL0;
       nq1 = QD1 * iL1;
       nq2 = -(QD0 + QD1) * iL2;
-      kd0 = series(kw + KW_KX0);
-      kd1 = series(kw + KW_KX1);
-      kR = series(kw + KW_KC);
+      kd0 = series_w(KW_KX0);
+      kd1 = series_w(KW_KX1);
+      kR = series_w(KW_KC);
     } else {
       S ua, ub;
       if (GEO) {

@@ -433,6 +433,55 @@ __global__ void kepler_proj_kernel(const double* __restrict__ theta, int64_t B, 
   for (int j = 9 * kKepT; j < KW_STRIDE; ++j) out[j] = 0.0;
 }
 
+// Derivatives of the projected series in the sky angles: the series projected
+// on the derivatives of the sky basis, one thread per (walker, detector, angle
+// s = lambda, beta, psi).  wkept[b][d][s][KW_STRIDE]; zero rows as above.
+__global__ void kepler_proj_tan_kernel(const double* __restrict__ theta, int64_t B, const double* __restrict__ kep,
+                                       SetupArgs sa, double* __restrict__ wkept) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * sa.n_det * 3) return;
+  const int64_t b = i / (sa.n_det * 3);
+  const int r = (int)(i - b * sa.n_det * 3);
+  const int d = r / 3, sk = r - 3 * d;
+  double* __restrict__ out = wkept + i * KW_STRIDE;
+  const double* th = theta + b * 11;
+  if (sa.dt.p[d].kind == 2 || !theta_valid(th)) {
+    for (int j = 0; j < KW_STRIDE; ++j) out[j] = 0.0;
+    return;
+  }
+  Dual<1> ang[3];
+  for (int q = 0; q < 3; ++q) {
+    ang[q] = Dual<1>(th[7 + q]);
+    ang[q].d[0] = q == sk ? 1.0 : 0.0;
+  }
+  Dual<1> kd[3], pd[3], qd[3];
+  sky_basis(ang[0], ang[1], ang[2], kd, pd, qd);
+  double kv[3], pv[3], qv[3];
+  for (int x = 0; x < 3; ++x) {
+    kv[x] = kd[x].d[0];
+    pv[x] = pd[x].d[0];
+    qv[x] = qd[x].d[0];
+  }
+  const double* __restrict__ v = kep + d * KV_STRIDE;
+  for (int j = 0; j < kKepT; ++j) {
+    double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int x = 0; x < 3; ++x) {
+      const double d0 = v[KV_D0 + x * kKepT + j], d1 = v[KV_D1 + x * kKepT + j];
+      c[0] = fma(kv[x], d0, c[0]);
+      c[1] = fma(kv[x], d1, c[1]);
+      c[2] = fma(pv[x], d0, c[2]);
+      c[3] = fma(pv[x], d1, c[3]);
+      c[4] = fma(qv[x], d0, c[4]);
+      c[5] = fma(qv[x], d1, c[5]);
+      c[6] = fma(kv[x], v[KV_X0 + x * kKepT + j], c[6]);
+      c[7] = fma(kv[x], v[KV_X1 + x * kKepT + j], c[7]);
+      c[8] = fma(kv[x], v[KV_C + x * kKepT + j], c[8]);
+    }
+    for (int f = 0; f < 9; ++f) out[f * kKepT + j] = c[f];
+  }
+  for (int j = 9 * kKepT; j < KW_STRIDE; ++j) out[j] = 0.0;
+}
+
 // Values and theta-derivatives of the walker table, wtan[b][i][k] = d w_i / d theta_k:
 // one thread per (walker, direction k) carrying a single tangent.
 __global__ void setup_tan_kernel(const double* __restrict__ theta, int64_t B, double* __restrict__ wtab,
@@ -986,6 +1035,15 @@ hipError_t launch_kepler_proj(const double* theta, int64_t B, const double* kep,
   if (!kep || !wkep) return hipErrorInvalidValue;
   const int64_t n = B * sa.n_det;
   hipLaunchKernelGGL(kepler_proj_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, theta, B, kep, sa, wkep);
+  return hipGetLastError();
+}
+
+hipError_t launch_kepler_proj_tan(const double* theta, int64_t B, const double* kep, const SetupArgs& sa,
+                                  double* wkept, hipStream_t s) {
+  if (!kep || !wkept) return hipErrorInvalidValue;
+  const int64_t n = B * sa.n_det * 3;
+  hipLaunchKernelGGL(kepler_proj_tan_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, theta, B, kep, sa,
+                     wkept);
   return hipGetLastError();
 }
 

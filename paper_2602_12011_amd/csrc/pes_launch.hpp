@@ -67,6 +67,12 @@ struct JacArgs {
   double f0, df;
   DetTable dt;
   const double* theta;   // [B][11] (the reverse sweep's sky contraction)
+  // exact Kepler orbits (null otherwise): the detectors' series [kMaxDet][KV_STRIDE],
+  // the walkers' projected series [B][n_det][KW_STRIDE] and their derivatives
+  // in lambda, beta, psi [B][n_det][3][KW_STRIDE]
+  const double* kep;
+  const double* wkep;
+  const double* wkept;
 };
 
 hipError_t launch_grad(const double* bins, const double* tabs, const double* wtab, const double* wtan,
@@ -89,6 +95,8 @@ hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, bool f3
                           hipStream_t s);
 hipError_t launch_kepler_proj(const double* theta, int64_t B, const double* kep, const SetupArgs& sa,
                               double* wkep, hipStream_t s);
+hipError_t launch_kepler_proj_tan(const double* theta, int64_t B, const double* kep, const SetupArgs& sa,
+                                  double* wkept, hipStream_t s);
 hipError_t launch_table32(const double* wtab, int64_t B, float* wtab32, hipStream_t s);
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
                            int64_t B, double* logl, hipStream_t s);

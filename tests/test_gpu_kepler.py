@@ -4,7 +4,10 @@ to 1e-9 max(|L|, <d|d>/2) and A/E/T element by element to 1e-9 |h| + 1e-12
 max|h| (T also 1e-11 of the A/E magnitude), as for the first-order orbit, on
 LISA alone, on the three-detector network (TianQin stays geocentric), on the
 paper's 32703-bin grid (long sinc fits) and with TDI 1.5; both bin-per-lane
-kernel variants.  The calls that do not support these orbits refuse them."""
+kernel variants.  Gradients (forward mode, whichever method is set) and Fisher
+matrices against the oracle's dual numbers on the same orbits, at the
+tolerances of the first-order orbit's derivative tests.  The calls that do not
+support these orbits (stage probes, single precision) refuse them."""
 import numpy as np
 import pytest
 
@@ -125,16 +128,90 @@ def test_kepler_differs_from_first_order(orc, torch_dev, pes):
     assert np.abs(diff_gpu - diff_or).max() <= 1e-8 * scale
 
 
+DERIV_CASES = {
+    "lisa_hm": (lambda: _cfg("cfg1", n_bins=3000 + 17), W.THETA0),
+    "network": (lambda: _cfg("cfg2", n_bins=2000 + 9), W.THETA0),
+    "pe_grid": (lambda: _cfg("pehm"), W.THETA_PE),
+}
+
+
+def _walkers(case, inj, n, stream):
+    th = np.vstack([inj + 1e-5 * W.prior_widths(), W.draw_walkers(n - 1, stream=stream)])
+    if case == "pe_grid":
+        th[1:, 10] += W.THETA_PE[10] - W.THETA0[10]
+        th[1, 0] = 1.0e5                       # a light walker reaches the long-sinc bins
+    return th
+
+
+@pytest.mark.parametrize("method", ["adjoint", "forward"])
+@pytest.mark.parametrize("case", list(DERIV_CASES))
+def test_kepler_grad_matches_oracle(orc, torch_dev, pes, case, method):
+    torch = torch_dev
+    mk, inj = DERIV_CASES[case]
+    cfg = mk()
+    d = orc.response(cfg, inj)
+    th = _walkers(case, inj, 3 if case == "pe_grid" else 5, 73)
+    print(f"[kepler] grad {case} {method}: n_bins={cfg['n_bins']} dets={len(cfg['detectors'])}", flush=True)
+    ctx = pes.Context(cfg)
+    ctx.set_grad_method(method)
+    ctx.set_data(torch.from_numpy(np.ascontiguousarray(d)).to("cuda"))
+    tht = torch.from_numpy(th).to("cuda")
+    L, g = ctx.grad(tht)
+    L, g = L.cpu().numpy(), g.cpu().numpy()
+    L_ll = ctx.loglike(tht).cpu().numpy()
+    ctx.close()
+    L_or, g_or = orc.grad(cfg, d, th)
+    sigma = 0.5 * orc.inner(cfg, d, d)
+    assert np.all(np.abs(L - L_or) <= 1e-9 * np.maximum(np.abs(L_or), sigma))
+    assert np.all(np.abs(L - L_ll) <= 1e-10 * np.maximum(np.abs(L_ll), sigma))
+    s = W.prior_widths()
+    for b in range(th.shape[0]):
+        scale = np.abs(g_or[b] * s).max()
+        err = np.abs(g[b] - g_or[b]) * s
+        assert np.all(err <= 1e-6 * scale), (case, b, (err / scale).max())
+
+
+@pytest.mark.parametrize("case", list(DERIV_CASES))
+def test_kepler_fisher_matches_oracle(orc, torch_dev, pes, case):
+    torch = torch_dev
+    mk, inj = DERIV_CASES[case]
+    cfg = mk()
+    th = _walkers(case, inj, 3, 74)
+    print(f"[kepler] fisher {case}: n_bins={cfg['n_bins']}", flush=True)
+    ctx = pes.Context(cfg)
+    F = ctx.fisher(torch.from_numpy(th).to("cuda")).cpu().numpy()
+    ctx.close()
+    F_or = orc.fisher(cfg, th)
+    assert np.allclose(F, np.transpose(F, (0, 2, 1)), rtol=1e-12, atol=0)
+    for b in range(th.shape[0]):
+        dg = np.sqrt(np.outer(np.diag(F_or[b]), np.diag(F_or[b])))
+        err = np.abs(F[b] - F_or[b]) / dg
+        assert np.all(err <= 1e-6), (case, b, err.max(), np.unravel_index(err.argmax(), err.shape))
+
+
+def test_kepler_fisher_differs_from_first_order(orc, torch_dev, pes):
+    """The exact orbits change the Fisher matrix by the oracle's own amount."""
+    torch = torch_dev
+    kep = _cfg("cfg1", n_bins=3000)
+    first = W.config("cfg1", n_bins=3000)
+    th = torch.from_numpy(W.THETA0[None, :].copy()).to("cuda")
+    Fs = []
+    for cfg in (kep, first):
+        ctx = pes.Context(cfg)
+        Fs.append(ctx.fisher(th).cpu().numpy()[0])
+        ctx.close()
+    F_or = orc.fisher(kep, W.THETA0[None, :])[0] - orc.fisher(first, W.THETA0[None, :])[0]
+    dg = np.sqrt(np.outer(np.diag(Fs[1]), np.diag(Fs[1])))
+    assert np.abs(F_or / dg).max() > 1e-6
+    assert np.abs((Fs[0] - Fs[1] - F_or) / dg).max() <= 2e-6
+
+
 def test_kepler_refusals(torch_dev, pes):
     torch = torch_dev
     cfg = _cfg("cfg0")
     ctx = pes.Context(cfg)
     ctx.set_data(torch.zeros((1, 3, cfg["n_bins"], 2), dtype=torch.float64, device="cuda"))
     th = torch.from_numpy(W.draw_walkers(4, stream=3)).to("cuda")
-    with pytest.raises(pes.PesError):
-        ctx.grad(th)
-    with pytest.raises(pes.PesError):
-        ctx.fisher(th)
     with pytest.raises(pes.PesError):
         ctx.probe(th, "mode")
     with pytest.raises(pes.PesError):
