@@ -645,11 +645,13 @@ def ess_leg(torch, pes, B, n_pilot, n_collect, n_run, fit_steps, tau=1.1, fit_ba
         if use_flow:
             smp.set_flow(flow, 0.9)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        smp.step(n_run)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        print(f"[ess] {name}: {n_run} steps in {dt:.1f} s", file=sys.stderr, flush=True)
+        dt = 0.0
+        for k in range(0, n_run, 50):   # chunks of 50 steps, so long runs report progress
+            t0 = time.perf_counter()
+            smp.step(min(50, n_run - k))
+            torch.cuda.synchronize()
+            dt += time.perf_counter() - t0
+            print(f"[ess] {name}: {min(k + 50, n_run)}/{n_run} steps, {dt:.1f} s", file=sys.stderr, flush=True)
         acc = smp.state()[2].cpu().numpy().sum() / (B * n_run)
         chains[name] = smp.read_chain().cpu().numpy()
         smp.close()
