@@ -220,31 +220,38 @@ def derivative_leg(torch, pes, reps):
 
 
 def graph_leg(torch, pes, steps):
-    """Sampler steps/s at the small workload (1000 walkers, 4096 bins, (2,2)),
-    where launches dominate: eager steps against one captured-graph replay per step."""
-    cfg = W.config("cfg0")
-    dev = torch.device("cuda:0")
-    ctx = pes.Context(cfg)
-    th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
-    ctx.set_data(ctx.response(th0)[0].clone())
-    prior = _prior_spec()
-    B = cfg["walkers"]
-    rng = np.random.default_rng(11)
-    start = torch.from_numpy(W.THETA0 + 1e-6 * W.prior_widths() * rng.normal(size=(B, 11))).to(dev)
-    a = pes.Sampler(ctx, prior, B, 5)
-    b = pes.Sampler(ctx, prior, B, 5)
-    a.set_state(start)
-    b.set_state(start)
-    s = torch.cuda.Stream()
-    with torch.cuda.stream(s):
-        b.capture(s)
-        t_graph = _time_ms(torch, lambda: b.launch(1, s), steps)
-    t_eager = _time_ms(torch, lambda: a.step(1), steps)
-    a.close()
-    b.close()
-    ctx.close()
-    return dict(workload="1000 walkers, 4096 bins, (2,2) mode, LISA-like", eager_ms_per_step=round(t_eager, 4),
-                graph_ms_per_step=round(t_graph, 4), graph_speedup=round(t_eager / t_graph, 3))
+    """Sampler steps/s, eager steps against one captured-graph replay per
+    step: at the small workload (1000 walkers, 4096 bins, (2,2)), and at a
+    batch small enough for the launches to dominate (64 walkers, the first
+    512 of those bins)."""
+    def one(B, n_bins):
+        cfg = W.config("cfg0", n_bins=n_bins)
+        dev = torch.device("cuda:0")
+        ctx = pes.Context(cfg)
+        th0 = torch.from_numpy(W.THETA0[None, :].copy()).to(dev)
+        ctx.set_data(ctx.response(th0)[0].clone())
+        prior = _prior_spec()
+        rng = np.random.default_rng(11)
+        start = torch.from_numpy(W.THETA0 + 1e-6 * W.prior_widths() * rng.normal(size=(B, 11))).to(dev)
+        a = pes.Sampler(ctx, prior, B, 5)
+        b = pes.Sampler(ctx, prior, B, 5)
+        a.set_state(start)
+        b.set_state(start)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            b.capture(s)
+            t_graph = _time_ms(torch, lambda: b.launch(1, s), steps)
+        t_eager = _time_ms(torch, lambda: a.step(1), steps)
+        a.close()
+        b.close()
+        ctx.close()
+        return t_eager, t_graph
+    te, tg = one(1000, None)
+    te_s, tg_s = one(64, 512)
+    return dict(workload="1000 walkers, 4096 bins, (2,2) mode, LISA-like", eager_ms_per_step=round(te, 4),
+                graph_ms_per_step=round(tg, 4), graph_speedup=round(te / tg, 3),
+                small=dict(workload="64 walkers, 512 bins, (2,2) mode, LISA-like", eager_ms_per_step=round(te_s, 4),
+                           graph_ms_per_step=round(tg_s, 4), graph_speedup=round(te_s / tg_s, 3)))
 
 
 def schedule_utilisation(cfg, theta, tile, grid):
