@@ -164,6 +164,33 @@ def test_loglike_fp32(orc, torch_dev, pes, case):
     assert np.allclose(Ls[0], Ls[1], rtol=1e-12, atol=1e-9 * sigma)
 
 
+def test_fp32_full_size_sampled(orc, torch_dev, pes):
+    """The benchmark's FP32 launch (4096 walkers, 2^20 bins, five modes) on 8
+    walkers at evenly spaced ranks of the mass order, against the oracle with
+    the derived bound above."""
+    torch = torch_dev
+    cfg = _cfg("cfg1")
+    B = cfg["walkers"]
+    print(f"[fp32] full size: B={B} n_bins={cfg['n_bins']}", flush=True)
+    d = orc.response(cfg, W.THETA0)
+    th = W.draw_walkers(B, stream=1)
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(np.ascontiguousarray(d)).to("cuda"))
+    ctx.set_precision(32)
+    tht = torch.from_numpy(th).to("cuda")
+    ctx.autotune(tht)
+    L = ctx.loglike(tht).cpu().numpy()
+    ctx.close()
+    assert np.all(np.isfinite(L)) and np.all(L <= 0)
+    order = np.argsort(th[:, 0], kind="stable")
+    idx = np.unique(order[np.linspace(0, B - 1, 8).round().astype(int)])
+    L_or = orc.loglike(cfg, d, th[idx])
+    sigma = 0.5 * orc.inner(cfg, d, d)
+    bound = 2.0 * _loglike_bound(orc, cfg, d, th[idx]) + 1e-9 * np.maximum(np.abs(L_or), sigma)
+    err = np.abs(L[idx] - L_or)
+    assert np.all(err <= bound), float((err / bound).max())
+
+
 def test_precision_switch(torch_dev, pes):
     torch = torch_dev
     cfg = _cfg("cfg0")

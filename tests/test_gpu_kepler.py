@@ -128,6 +128,36 @@ def test_kepler_differs_from_first_order(orc, torch_dev, pes):
     assert np.abs(diff_gpu - diff_or).max() <= 1e-8 * scale
 
 
+def test_kepler_full_size_sampled(orc, torch_dev, pes):
+    """The benchmark's Kepler launch (4096 walkers, 2^20 bins, five modes) on a
+    sample of walkers the oracle evaluates one by one: 16 at evenly spaced
+    ranks of the mass order, both ends included; autotuned and at 24 walkers
+    per item with two bins per lane (a partial last group)."""
+    torch = torch_dev
+    cfg = _cfg("cfg1")
+    B = cfg["walkers"]
+    print(f"[kepler] full size: B={B} n_bins={cfg['n_bins']}", flush=True)
+    d = orc.response(cfg, W.THETA0)
+    th = W.draw_walkers(B, stream=1)
+    ctx = pes.Context(cfg)
+    ctx.set_data(torch.from_numpy(np.ascontiguousarray(d)).to("cuda"))
+    tht = torch.from_numpy(th).to("cuda")
+    ctx.autotune(tht)
+    L = ctx.loglike(tht).cpu().numpy()
+    ctx.set_tuning(2, 24, 0)
+    L24 = ctx.loglike(tht).cpu().numpy()
+    ctx.close()
+    assert np.all(np.isfinite(L)) and np.all(L <= 0)
+    order = np.argsort(th[:, 0], kind="stable")
+    idx = np.unique(order[np.linspace(0, B - 1, 16).round().astype(int)])
+    L_or = orc.loglike(cfg, d, th[idx])
+    sigma = 0.5 * orc.inner(cfg, d, d)
+    for got in (L[idx], L24[idx]):
+        err = np.abs(got - L_or)
+        assert np.all(err <= 1e-9 * np.maximum(np.abs(L_or), sigma)), float(
+            (err / (1e-9 * np.maximum(np.abs(L_or), sigma))).max())
+
+
 DERIV_CASES = {
     "lisa_hm": (lambda: _cfg("cfg1", n_bins=3000 + 17), W.THETA0),
     "network": (lambda: _cfg("cfg2", n_bins=2000 + 9), W.THETA0),
