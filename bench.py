@@ -460,7 +460,8 @@ def kepler_leg(torch, pes, steps):
     ellipses (arms flexing at order e^2 AU) instead of the first-order
     triangle: evals/s at the autotuned tuning and the cost relative to the
     first-order orbit in the same run; then the derivatives on both orbits
-    (Fisher matrices at 256 points, forward-mode gradients at 1024 walkers)."""
+    (Fisher matrices at 256 points, forward- and reverse-mode gradients at
+    1024 walkers)."""
     out = {}
     for orbit in ("first_order", "kepler"):
         cfg = W.config("cfg1")
@@ -481,15 +482,18 @@ def kepler_leg(torch, pes, steps):
         ctx.set_grad_method("forward")
         out[orbit]["fisher_ms"] = round(_time_ms(torch, lambda: ctx.fisher(thf), 2), 3)
         out[orbit]["grad_forward_ms"] = round(_time_ms(torch, lambda: ctx.grad(thg), 1), 3)
+        ctx.set_grad_method("adjoint")
+        out[orbit]["grad_adjoint_ms"] = round(_time_ms(torch, lambda: ctx.grad(thg), 3), 3)
         ctx.close()
     k, f = out["kepler"], out["first_order"]
     return dict(workload="LISA-like on exact Kepler ellipses, 5 modes, 2^20 bins (df=1/yr), 4096 walkers, "
-                         "noise-free injection; Fisher at 256 and forward-mode gradients at 1024 of them",
+                         "noise-free injection; Fisher at 256 and gradients at 1024 of them",
                 ms_per_call=k["ms_per_call"], evals_per_s=round(4096 / (k["ms_per_call"] * 1e-3), 1),
                 tuning=k["tuning"], first_order_ms_per_call_same_run=f["ms_per_call"],
                 cost_over_first_order=round(k["ms_per_call"] / f["ms_per_call"], 3),
                 fisher_ms=k["fisher_ms"], fisher_first_order_ms=f["fisher_ms"],
-                grad_forward_ms=k["grad_forward_ms"], grad_forward_first_order_ms=f["grad_forward_ms"])
+                grad_forward_ms=k["grad_forward_ms"], grad_forward_first_order_ms=f["grad_forward_ms"],
+                grad_adjoint_ms=k["grad_adjoint_ms"], grad_adjoint_first_order_ms=f["grad_adjoint_ms"])
 
 
 EXTRINSIC = (7, 8, 9, 10)   # lambda, beta, psi, t_c

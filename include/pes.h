@@ -71,8 +71,7 @@ typedef struct {
                           With PES_ORBIT_KEPLER the link directions are the unit separations
                           of the spacecraft at t_f, the transfer function and the TDI factor
                           keep the nominal L; such a context evaluates in FP64 (pes_probe
-                          and pes_set_precision(32) return PES_EINVAL), its derivatives in
-                          forward mode. */
+                          and pes_set_precision(32) return PES_EINVAL). */
 } pes_detector;
 
 typedef struct {
@@ -188,8 +187,7 @@ int pes_set_precision(pes_ctx* ctx, int bits);
  * response in reverse mode): logl (dev) [B] (may be NULL), grad (dev) [B][11]
  * in the units of theta.  Requires pes_set_data.  Unphysical samples:
  * logl = -inf, grad = 0.  B <= 65535.  The method is chosen per context by
- * pes_set_grad_method; both give the same values up to rounding.  Contexts on
- * exact Kepler orbits always use the forward-mode evaluation. */
+ * pes_set_grad_method; both give the same values up to rounding. */
 int pes_grad(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double* grad, void* stream);
 
 /* Gradient method of pes_grad:
@@ -197,9 +195,10 @@ int pes_grad(pes_ctx* ctx, const double* theta, int64_t B, double* logl, double*
  *     forward values recomputed (no per-bin storage); adjoints of the walker
  *     table's mode entries contracted with their theta-derivatives, those of
  *     the sky projections reduced through the orthonormal sky basis (this
- *     needs spacecraft offsets that sum to zero, as the first-order orbits
- *     have; pes_grad returns PES_EINVAL otherwise, and contexts on exact
- *     Kepler orbits take the forward-mode path whatever this setting).
+ *     needs, on the first-order orbit, spacecraft offsets that sum to zero,
+ *     as that orbit has; pes_grad returns PES_EINVAL otherwise; on exact
+ *     Kepler orbits the projections of the orbit series on all three sky
+ *     basis vectors carry it).
  *   PES_GRAD_FORWARD: forward-mode tangents, one (bin, parameter direction)
  *     pair per lane (the evaluation of pes_fisher); the cross-check.
  * PES_EINVAL for another value. */

@@ -191,16 +191,44 @@ __device__ __forceinline__ void adj_arm(const double* yb, double a, double pEr, 
   nqb = fma(-2.0 * nq, ppb, np * pcb);
 }
 
+// Harmonics cos k alpha, sin k alpha (k = 0..kKepH) of the orbit phase from
+// its cosine and sine (Chebyshev recurrence, as the response evaluates them).
+__device__ __forceinline__ void kep_harmonics(double ca, double sa, double (&hc)[kKepH + 1],
+                                              double (&hs)[kKepH + 1]) {
+  hc[0] = 1.0;
+  hs[0] = 0.0;
+  hc[1] = ca;
+  hs[1] = sa;
+  const double c2a = 2.0 * ca;
+#pragma unroll
+  for (int k = 2; k <= kKepH; ++k) {
+    hc[k] = fma(c2a, hc[k - 1], -hc[k - 2]);
+    hs[k] = fma(c2a, hs[k - 1], -hs[k - 2]);
+  }
+}
+__device__ __forceinline__ double kep_series(const double* __restrict__ cg, const double (&hc)[kKepH + 1],
+                                             const double (&hs)[kKepH + 1]) {
+  cdouble* c = as_const(cg);
+  double r = c[0];
+#pragma unroll
+  for (int k = 1; k <= kKepH; ++k) r = fma(c[2 * k - 1], hc[k], fma(c[2 * k], hs[k], r));
+  return r;
+}
+
 // Adjoint of the unit of mode j (and, when PAIR, of mode jm riding on it, as
 // in eval_channels_t) of (walker, bin, detector) given the link adjoints yb
 // (12 values: arm-major Fr, Fi, Br, Bi); accumulates d l / d theta into
 // g[0..10] and the three sky sums into g[11..13] (see the sky part below).
 // wt: the walker's table; tn: its tangents in the compact layout; ftc = f t_c
-// mod 1; L3 = L / 3 of the detector.
-template <bool GEO, bool LS, bool PAIR>
+// mod 1; L3 = L / 3 of the detector.  KEP: a heliocentric detector on exact
+// Kepler ellipses, kw its projected orbit series for this walker, kinv its
+// inverse-arm-length series (the geometry as the response evaluates it).
+template <bool GEO, bool LS, bool PAIR, bool KEP = false>
 __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const double* __restrict__ tn, int det,
                                          int j, int jm, double inv_year, double inv_ptq, double L3,
-                                         const BinRegs& b, double a, double ftc, const double* yb, double* g) {
+                                         const BinRegs& b, double a, double ftc, const double* yb, double* g,
+                                         const double* __restrict__ kw = nullptr,
+                                         const double* __restrict__ kinv = nullptr) {
   int M0 = W_MODE0 + opaque_u(j) * W_MODE_STRIDE;
   int D0 = W_DET0 + opaque_u(det) * W_DET_STRIDE;
   int N0 = W_MODE0 + opaque_u(jm) * W_MODE_STRIDE, R0 = W_ROT0 + R_STRIDE * opaque_u(jm);
@@ -262,22 +290,58 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
     aC2 = fma(amn, wr(R_KCR), aC2);
     aCi = amn * wr(R_KCI);
   }
-  double sa, ca, ua, ub;
+  double sa, ca, ua = 0.0, ub = 0.0;
   sincos_cycles(tau * inv_year + wd(D_AO), sa, ca);
-  if (GEO) {
-    sincos_cycles(tau * inv_ptq + wd(D_PO), ub, ua);
+  double kn0, kn1, kn2, np0, np1, np2, nq0, nq1, nq2, kd0, kd1, kR;
+  double KD0 = 0.0, KD1 = 0.0, PD0 = 0.0, PD1 = 0.0, QD0 = 0.0, QD1 = 0.0, iL0 = 0.0, iL1 = 0.0, iL2 = 0.0;
+  if constexpr (KEP) {
+    // separations Delta_t projected and over their lengths; offsets from the
+    // centroid and the centroid projected on k
+    double hc[kKepH + 1], hs[kKepH + 1];
+    kep_harmonics(ca, sa, hc, hs);
+    iL0 = kep_series(kinv, hc, hs);
+    iL1 = kep_series(kinv + kKepT, hc, hs);
+    iL2 = kep_series(kinv + 2 * kKepT, hc, hs);
+    KD0 = kep_series(kw + KW_KD0, hc, hs);
+    KD1 = kep_series(kw + KW_KD1, hc, hs);
+    PD0 = kep_series(kw + KW_PD0, hc, hs);
+    PD1 = kep_series(kw + KW_PD1, hc, hs);
+    QD0 = kep_series(kw + KW_QD0, hc, hs);
+    QD1 = kep_series(kw + KW_QD1, hc, hs);
+    kn0 = KD0 * iL0;
+    kn1 = KD1 * iL1;
+    kn2 = -(KD0 + KD1) * iL2;
+    np0 = PD0 * iL0;
+    np1 = PD1 * iL1;
+    np2 = -(PD0 + PD1) * iL2;
+    nq0 = QD0 * iL0;
+    nq1 = QD1 * iL1;
+    nq2 = -(QD0 + QD1) * iL2;
+    kd0 = kep_series(kw + KW_KX0, hc, hs);
+    kd1 = kep_series(kw + KW_KX1, hc, hs);
+    kR = kep_series(kw + KW_KC, hc, hs);
   } else {
-    ua = fma(-2.0 * sa, sa, 1.0);
-    ub = 2.0 * sa * ca;
-  }
+    if (GEO) {
+      sincos_cycles(tau * inv_ptq + wd(D_PO), ub, ua);
+    } else {
+      ua = fma(-2.0 * sa, sa, 1.0);
+      ub = 2.0 * sa * ca;
+    }
 #define PES_LIN(off) (fma(wd((off) + 3), sa, fma(wd((off) + 2), ca, fma(wd((off) + 1), ub, wd((off)) * ua))) + wd((off) + 4))
-  const double kn0 = PES_LIN(D_KN), kn1 = PES_LIN(D_KN + 5);
-  const double np0 = PES_LIN(D_NP), np1 = PES_LIN(D_NP + 5);
-  const double nq0 = PES_LIN(D_NQ), nq1 = PES_LIN(D_NQ + 5);
-  const double kd0 = PES_LIN(D_KD), kd1 = PES_LIN(D_KD + 5);
+    kn0 = PES_LIN(D_KN);
+    kn1 = PES_LIN(D_KN + 5);
+    np0 = PES_LIN(D_NP);
+    np1 = PES_LIN(D_NP + 5);
+    nq0 = PES_LIN(D_NQ);
+    nq1 = PES_LIN(D_NQ + 5);
+    kd0 = PES_LIN(D_KD);
+    kd1 = PES_LIN(D_KD + 5);
 #undef PES_LIN
-  const double kn2 = -(kn0 + kn1), np2 = -(np0 + np1), nq2 = -(nq0 + nq1);
-  const double kR = fma(wd(D_KR), ca, wd(D_KR + 1) * sa);
+    kn2 = -(kn0 + kn1);
+    np2 = -(np0 + np1);
+    nq2 = -(nq0 + nq1);
+    kR = fma(wd(D_KR), ca, wd(D_KR + 1) * sa);
+  }
   double sp, cp;
   sincos_cycles(fma(b.f, kR, phase), sp, cp);
   double pEr, pEi, cEr, cEi;
@@ -329,13 +393,16 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
     cpb = fma(pEbi, aPi, fma(cEbi, aCi, cpb));
     spb = fma(pEbr, aPi, fma(cEbr, aCi, spb));
   }
-  // the third arm follows from the other two
-  knb0 -= knb2;
-  knb1 -= knb2;
-  npb0 -= npb2;
-  npb1 -= npb2;
-  nqb0 -= nqb2;
-  nqb1 -= nqb2;
+  // the third arm follows from the other two (its phase always; its
+  // projections on the rigid triangle)
+  if (!KEP) {
+    knb0 -= knb2;
+    knb1 -= knb2;
+    npb0 -= npb2;
+    npb1 -= npb2;
+    nqb0 -= nqb2;
+    nqb1 -= nqb2;
+  }
   cb0 = fma(cb2, c1, fma(-sb2, s1, cb0));
   sb0 = fma(-cb2, s1, fma(-sb2, c1, sb0));
   cb1 = fma(cb2, c0, fma(-sb2, s0, cb1));
@@ -346,6 +413,52 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   // common phase (cycles): (sp, cp) = (sin, cos)(2 pi Phi), Phi = f kR + phase
   const double Phib = kTwoPi * fma(spb, cp, -(cpb * sp));
   const double kRb = b.f * Phib;
+  double taub = 0.0, alphab;
+  if constexpr (KEP) {
+    // ---- exact Kepler orbits: adjoints of the twelve series values
+    const double KDb0 = fma(knb0, iL0, -(knb2 * iL2)), KDb1 = fma(knb1, iL1, -(knb2 * iL2));
+    const double PDb0 = fma(npb0, iL0, -(npb2 * iL2)), PDb1 = fma(npb1, iL1, -(npb2 * iL2));
+    const double QDb0 = fma(nqb0, iL0, -(nqb2 * iL2)), QDb1 = fma(nqb1, iL1, -(nqb2 * iL2));
+    const double iLb0 = fma(knb0, KD0, fma(npb0, PD0, nqb0 * QD0));
+    const double iLb1 = fma(knb1, KD1, fma(npb1, PD1, nqb1 * QD1));
+    const double iLb2 = -fma(knb2, KD0 + KD1, fma(npb2, PD0 + PD1, nqb2 * (QD0 + QD1)));
+    double hc[kKepH + 1], hs[kKepH + 1];
+    kep_harmonics(ca, sa, hc, hs);
+    // sky part: every projected vector V (Delta_t, x_t - c, c) is
+    // (k.V) k + (p.V) p + (q.V) q, so with the triad identities of the
+    // first-order branch below the sky adjoints reduce to the same three sums
+    const double PX0 = kep_series(kw + KW_PX0, hc, hs), PX1 = kep_series(kw + KW_PX1, hc, hs);
+    const double QX0 = kep_series(kw + KW_QX0, hc, hs), QX1 = kep_series(kw + KW_QX1, hc, hs);
+    const double PC = kep_series(kw + KW_PC, hc, hs), QC = kep_series(kw + KW_QC, hc, hs);
+    g[kNParams] = fma(KDb0, PD0, fma(-PDb0, KD0, fma(KDb1, PD1, fma(-PDb1, KD1,
+                  fma(kdb0, PX0, fma(kdb1, PX1, fma(kRb, PC, g[kNParams])))))));
+    g[kNParams + 1] = fma(KDb0, QD0, fma(-QDb0, KD0, fma(KDb1, QD1, fma(-QDb1, KD1,
+                      fma(kdb0, QX0, fma(kdb1, QX1, fma(kRb, QC, g[kNParams + 1])))))));
+    g[kNParams + 2] = fma(PDb0, QD0, fma(-QDb0, PD0, fma(PDb1, QD1, fma(-QDb1, PD1, g[kNParams + 2]))));
+    // time part: d/d alpha of the series, c_{2k-1} cos k alpha + c_{2k} sin k alpha
+    // -> k (c_{2k} cos k alpha - c_{2k-1} sin k alpha), summed with the adjoints
+    // d/d alpha of one series at this alpha
+    auto dser = [&](const double* __restrict__ cg) __attribute__((always_inline)) {
+      cdouble* c = as_const(cg);
+      double r = c[2] * hc[1] - c[1] * hs[1];
+#pragma unroll
+      for (int k = 2; k <= kKepH; ++k) r = fma((double)k, fma(c[2 * k], hc[k], -(c[2 * k - 1] * hs[k])), r);
+      return r;
+    };
+    double dal = iLb0 * dser(kinv);
+    dal = fma(iLb1, dser(kinv + kKepT), dal);
+    dal = fma(iLb2, dser(kinv + 2 * kKepT), dal);
+    dal = fma(KDb0, dser(kw + KW_KD0), dal);
+    dal = fma(KDb1, dser(kw + KW_KD1), dal);
+    dal = fma(PDb0, dser(kw + KW_PD0), dal);
+    dal = fma(PDb1, dser(kw + KW_PD1), dal);
+    dal = fma(QDb0, dser(kw + KW_QD0), dal);
+    dal = fma(QDb1, dser(kw + KW_QD1), dal);
+    dal = fma(kdb0, dser(kw + KW_KX0), dal);
+    dal = fma(kdb1, dser(kw + KW_KX1), dal);
+    dal = fma(kRb, dser(kw + KW_KC), dal);
+    alphab = kTwoPi * dal;   // per cycle of the orbit phase
+  } else {
   // ---- projections: P = c0 ua + c1 ub + c2 ca + c3 sa + c4
   double uab = 0.0, ubb = 0.0, cab = kRb * wd(D_KR), sab = kRb * wd(D_KR + 1);
   DepSky::add(g, kRb * ca, td(D_KR));
@@ -388,7 +501,6 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
   }
 #undef PES_LIN_ADJ
   // ---- orbit at t_f
-  double taub = 0.0;
   if (GEO) {
     const double betab = kTwoPi * fma(ubb, ua, -(uab * ub));
     taub = betab * inv_ptq;
@@ -397,7 +509,8 @@ __device__ __forceinline__ void adj_unit(const double* __restrict__ wt, const do
     sab = fma(-4.0 * sa, uab, fma(2.0 * ca, ubb, sab));
     cab = fma(2.0 * sa, ubb, cab);
   }
-  const double alphab = kTwoPi * fma(sab, ca, -(cab * sa));
+  alphab = kTwoPi * fma(sab, ca, -(cab * sa));
+  }
   taub = fma(alphab, inv_year, taub);
   DepTc::add(g, alphab, td(D_AO));
   // ---- amplitude, polarization, taper

@@ -830,13 +830,14 @@ static JacArgs jac_args(const pes_ctx* c, int64_t B, int tile) {
 
 // Kepler contexts: the walkers' projected orbit series and their sky-angle
 // derivatives for the tangent kernels.
-static int kepler_jac_setup(pes_ctx* c, const double* theta, int64_t B, JacArgs& A, hipStream_t s) {
+static int kepler_jac_setup(pes_ctx* c, const double* theta, int64_t B, bool tangents, JacArgs& A,
+                            hipStream_t s) {
   if (!c->kep) return PES_OK;
   PES_HIP(c, launch_kepler_proj(theta, B, c->kep_tab, setup_args(c), c->wkep, s));
-  PES_HIP(c, launch_kepler_proj_tan(theta, B, c->kep_tab, setup_args(c), c->wkept, s));
+  if (tangents) PES_HIP(c, launch_kepler_proj_tan(theta, B, c->kep_tab, setup_args(c), c->wkept, s));
   A.kep = c->kep_tab;
   A.wkep = c->wkep;
-  A.wkept = c->wkept;
+  A.wkept = tangents ? c->wkept : nullptr;
   return PES_OK;
 }
 
@@ -855,10 +856,8 @@ int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* g
   if (!c || B < 0 || B > kMaxDerivBatch || (B > 0 && (!theta || !grad))) return PES_EINVAL;
   if (!c->has_data) return PES_ESTATE;
   if (B == 0) return PES_OK;
-  // exact Kepler orbits: the forward-mode evaluation (the reverse sweep's sky
-  // contraction assumes a rigid triangle)
-  const bool adjoint = c->grad_method == PES_GRAD_ADJOINT && !c->kep;
-  if (adjoint)
+  const bool adjoint = c->grad_method == PES_GRAD_ADJOINT;
+  if (adjoint && !c->kep)   // the first-order sky contraction needs the centred triangle
     for (int d = 0; d < c->cfg.n_det; ++d)
       if (!centred_triangle(c->dt.p[d])) {
         snprintf(c->err, sizeof(c->err), "detector %d: spacecraft offsets do not sum to zero", d);
@@ -870,7 +869,7 @@ int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* g
   PES_HIP(c, launch_setup_tan(theta, B, c->wtab, c->wtan, c->ntiles, setup_args(c), s));
   JacArgs A = jac_args(c, B, kGradTile);
   A.theta = theta;
-  st = kepler_jac_setup(c, theta, B, A, s);
+  st = kepler_jac_setup(c, theta, B, !adjoint, A, s);
   if (st != PES_OK) return st;
   PES_HIP(c, launch_grad(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, c->dd, A, c->long_sinc, adjoint, logl,
                          grad, s));
@@ -907,7 +906,7 @@ int pes_fisher(pes_ctx* c, const double* theta, int64_t B, double* F, void* stre
   hipStream_t s = (hipStream_t)stream;
   PES_HIP(c, launch_setup_tan(theta, B, c->wtab, c->wtan, c->ntiles, setup_args(c), s));
   JacArgs A = jac_args(c, B, kFisherTile);
-  st = kepler_jac_setup(c, theta, B, A, s);
+  st = kepler_jac_setup(c, theta, B, true, A, s);
   if (st != PES_OK) return st;
   PES_HIP(c, launch_fisher(c->bins, c->tabs, c->wtab, c->wtan, c->jpart, A, c->long_sinc, F, s));
   return PES_OK;

@@ -267,11 +267,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 // evaluation gives the channels and the weighted residual, adj_links turns it
 // into link adjoints, and adj_unit recomputes and back-propagates every active
 // mode, contracting table-entry adjoints with the setup's theta-derivatives.
-template <bool LS, bool GEO>
+template <bool LS, bool GEO, bool KEP = false>
 __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const double* __restrict__ tb,
                                         const double* __restrict__ wt, const double* __restrict__ wtn,
                                         const JacArgs& A, int det, int64_t k, bool in, double* g,
-                                        double& dh, double& hh, double* __restrict__ ybs) {
+                                        double& dh, double& hh, double* __restrict__ ybs,
+                                        const double* __restrict__ kw = nullptr,
+                                        const double* __restrict__ kinv = nullptr) {
   const int64_t N = A.N;
   const int64_t kk = in ? k : N - 1;
   BinRegs br;
@@ -291,7 +293,7 @@ __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const d
   D[4] = in ? tb[T_DTR * N + kk] : 0.0;
   D[5] = in ? tb[T_DTI * N + kk] : 0.0;
   const DetParams& P = A.dt.p[det];
-  const Chan c = eval_channels<GEO, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi);
+  const Chan c = eval_channels<GEO, LS, 1, KEP>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi, kw, kinv);
   dh = fma(D[0], c.ar, dh);
   dh = fma(D[1], c.ai, dh);
   dh = fma(D[2], c.er, dh);
@@ -308,12 +310,15 @@ __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const d
     for (int q = 0; q < 12; ++q) ybs[q] = yb[q / 4][q % 4];
   }
   const double ftc = frac_prod(br.f, wt[W_TC]);
+  const double L3 = P.L * (1.0 / 3.0);
 #pragma unroll 1
   for (int u = 0; u < A.plan.n_pairs; ++u)
-    adj_unit<GEO, LS, true>(wt, wtn, det, A.plan.lead[u], A.plan.member[u], P.inv_year, P.inv_ptq, P.L * (1.0 / 3.0), br, a, ftc, ybs, g);
+    adj_unit<GEO, LS, true, KEP>(wt, wtn, det, A.plan.lead[u], A.plan.member[u], P.inv_year, P.inv_ptq, L3, br, a,
+                                 ftc, ybs, g, kw, kinv);
 #pragma unroll 1
   for (int u = A.plan.n_pairs; u < A.plan.n_units; ++u)
-    adj_unit<GEO, LS, false>(wt, wtn, det, A.plan.lead[u], 0, P.inv_year, P.inv_ptq, P.L * (1.0 / 3.0), br, a, ftc, ybs, g);
+    adj_unit<GEO, LS, false, KEP>(wt, wtn, det, A.plan.lead[u], 0, P.inv_year, P.inv_ptq, L3, br, a, ftc, ybs, g,
+                                  kw, kinv);
 }
 
 // The walker's tangents are staged in LDS in the compact layout (4.6 KiB,
@@ -323,7 +328,7 @@ __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const d
 // scalar loads: staging it too moves the pressure into vector registers).
 // Two waves per SIMD: the reverse sweep fits 254 registers (a couple of
 // spilled values); one wave per SIMD leaves its long dependency chains exposed.
-template <bool LS>
+template <bool LS, bool KEP>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     adj_kernel(const double* __restrict__ bins, const double* __restrict__ tabs,
                const double* __restrict__ wtab, const double* __restrict__ wtan,
@@ -356,6 +361,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
       const double* __restrict__ tb = tabs + (int64_t)det * T_NFIELDS * A.N;
       if (A.dt.p[det].kind == 2)
         adj_det<LS, true>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, yb_s + 12 * lane);
+      else if (KEP)
+        adj_det<LS, false, true>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, yb_s + 12 * lane,
+                                 A.wkep + ((int64_t)b * A.n_det + det) * KW_STRIDE, A.kep + det * KV_STRIDE + KV_INVL);
       else
         adj_det<LS, false>(bins, tb, wt, wtn, A, det, k, in, g, dh, hh, yb_s + 12 * lane);
     }
@@ -439,16 +447,20 @@ hipError_t launch_grad(const double* bins, const double* tabs, const double* wta
                        double* logl, double* grad, hipStream_t s) {
   const dim3 grid((unsigned)((A.N + A.tile - 1) / A.tile), (unsigned)A.B);
   const bool kep = A.wkep != nullptr;
-  if (kep && (adjoint || !A.kep || !A.wkept)) return hipErrorInvalidValue;
+  if (kep && (!A.kep || (!adjoint && !A.wkept))) return hipErrorInvalidValue;
   if (adjoint) {
     if (!A.theta) return hipErrorInvalidValue;
     // the compact tables follow the full ones of the batch in the same buffer
     double* wtanc = const_cast<double*>(wtan) + (int64_t)A.B * W_STRIDE * kNParams;
     hipLaunchKernelGGL(compact_tan_kernel, dim3((unsigned)A.B), dim3(64), 0, s, wtan, wtanc);
-    if (long_sinc)
-      hipLaunchKernelGGL((adj_kernel<true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtanc, partial, A);
+    if (long_sinc && kep)
+      hipLaunchKernelGGL((adj_kernel<true, true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtanc, partial, A);
+    else if (long_sinc)
+      hipLaunchKernelGGL((adj_kernel<true, false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtanc, partial, A);
+    else if (kep)
+      hipLaunchKernelGGL((adj_kernel<false, true>), grid, dim3(64), 0, s, bins, tabs, wtab, wtanc, partial, A);
     else
-      hipLaunchKernelGGL((adj_kernel<false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtanc, partial, A);
+      hipLaunchKernelGGL((adj_kernel<false, false>), grid, dim3(64), 0, s, bins, tabs, wtab, wtanc, partial, A);
   } else if (kep && long_sinc) {
     hipLaunchKernelGGL((forward_grad_kep_kernel<true>), grid, dim3(256), 0, s, bins, tabs, wtab, wtan, partial, A);
   } else if (kep) {

@@ -29,6 +29,12 @@ struct TanTab {
   }
 };
 
+// Kepler orbit series coefficients are constant while a kernel runs and the
+// same for every lane: read through the constant address space, they come in
+// by scalar loads instead of occupying vector registers.
+typedef const __attribute__((address_space(4))) double cdouble;
+__device__ __forceinline__ cdouble* as_const(const double* p) { return (cdouble*)p; }
+
 // The projected Kepler orbit series of a walker in the tangent kernels: the
 // values (wavefront-uniform) and this lane's tangent row (zeros unless its
 // direction is a sky angle).
@@ -36,10 +42,10 @@ struct KwLane {
   const double* __restrict__ v;
   const double* __restrict__ t;
 };
-__device__ __forceinline__ double kw_at(const double* __restrict__ kw, int i) { return kw[i]; }
+__device__ __forceinline__ double kw_at(const double* __restrict__ kw, int i) { return as_const(kw)[i]; }
 __device__ __forceinline__ Dual<1> kw_at(const KwLane& kw, int i) {
   Dual<1> r;
-  r.v = kw.v[i];
+  r.v = as_const(kw.v)[i];
   r.d[0] = kw.t[i];
   return r;
 }
@@ -266,7 +272,8 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
         hc[k] = fma(c2a, hc[k - 1], -hc[k - 2]);
         hs[k] = fma(c2a, hs[k - 1], -hs[k - 2]);
       }
-      auto series = [&](const double* __restrict__ c) __attribute__((always_inline)) {
+      auto series = [&](const double* __restrict__ cg) __attribute__((always_inline)) {
+        cdouble* c = as_const(cg);
         S r = c[0];
 #pragma unroll
         for (int k = 1; k <= kKepH; ++k) r = fma(c[2 * k - 1], hc[k], fma(c[2 * k], hs[k], r));

@@ -415,22 +415,29 @@ __global__ void kepler_proj_kernel(const double* __restrict__ theta, int64_t B, 
   sky_basis(th[7], th[8], th[9], kv, pv, qv);
   const double* __restrict__ v = kep + d * KV_STRIDE;
   for (int j = 0; j < kKepT; ++j) {
-    double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double c[15] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int x = 0; x < 3; ++x) {
       const double d0 = v[KV_D0 + x * kKepT + j], d1 = v[KV_D1 + x * kKepT + j];
+      const double x0 = v[KV_X0 + x * kKepT + j], x1 = v[KV_X1 + x * kKepT + j], xc = v[KV_C + x * kKepT + j];
       c[0] = fma(kv[x], d0, c[0]);
       c[1] = fma(kv[x], d1, c[1]);
       c[2] = fma(pv[x], d0, c[2]);
       c[3] = fma(pv[x], d1, c[3]);
       c[4] = fma(qv[x], d0, c[4]);
       c[5] = fma(qv[x], d1, c[5]);
-      c[6] = fma(kv[x], v[KV_X0 + x * kKepT + j], c[6]);
-      c[7] = fma(kv[x], v[KV_X1 + x * kKepT + j], c[7]);
-      c[8] = fma(kv[x], v[KV_C + x * kKepT + j], c[8]);
+      c[6] = fma(kv[x], x0, c[6]);
+      c[7] = fma(kv[x], x1, c[7]);
+      c[8] = fma(kv[x], xc, c[8]);
+      c[9] = fma(pv[x], x0, c[9]);
+      c[10] = fma(pv[x], x1, c[10]);
+      c[11] = fma(qv[x], x0, c[11]);
+      c[12] = fma(qv[x], x1, c[12]);
+      c[13] = fma(pv[x], xc, c[13]);
+      c[14] = fma(qv[x], xc, c[14]);
     }
-    for (int f = 0; f < 9; ++f) out[f * kKepT + j] = c[f];
+    for (int f = 0; f < 15; ++f) out[f * kKepT + j] = c[f];
   }
-  for (int j = 9 * kKepT; j < KW_STRIDE; ++j) out[j] = 0.0;
+  for (int j = 15 * kKepT; j < KW_STRIDE; ++j) out[j] = 0.0;
 }
 
 // Derivatives of the projected series in the sky angles: the series projected
@@ -464,22 +471,29 @@ __global__ void kepler_proj_tan_kernel(const double* __restrict__ theta, int64_t
   }
   const double* __restrict__ v = kep + d * KV_STRIDE;
   for (int j = 0; j < kKepT; ++j) {
-    double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double c[15] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int x = 0; x < 3; ++x) {
       const double d0 = v[KV_D0 + x * kKepT + j], d1 = v[KV_D1 + x * kKepT + j];
+      const double x0 = v[KV_X0 + x * kKepT + j], x1 = v[KV_X1 + x * kKepT + j], xc = v[KV_C + x * kKepT + j];
       c[0] = fma(kv[x], d0, c[0]);
       c[1] = fma(kv[x], d1, c[1]);
       c[2] = fma(pv[x], d0, c[2]);
       c[3] = fma(pv[x], d1, c[3]);
       c[4] = fma(qv[x], d0, c[4]);
       c[5] = fma(qv[x], d1, c[5]);
-      c[6] = fma(kv[x], v[KV_X0 + x * kKepT + j], c[6]);
-      c[7] = fma(kv[x], v[KV_X1 + x * kKepT + j], c[7]);
-      c[8] = fma(kv[x], v[KV_C + x * kKepT + j], c[8]);
+      c[6] = fma(kv[x], x0, c[6]);
+      c[7] = fma(kv[x], x1, c[7]);
+      c[8] = fma(kv[x], xc, c[8]);
+      c[9] = fma(pv[x], x0, c[9]);
+      c[10] = fma(pv[x], x1, c[10]);
+      c[11] = fma(qv[x], x0, c[11]);
+      c[12] = fma(qv[x], x1, c[12]);
+      c[13] = fma(pv[x], xc, c[13]);
+      c[14] = fma(qv[x], xc, c[14]);
     }
-    for (int f = 0; f < 9; ++f) out[f * kKepT + j] = c[f];
+    for (int f = 0; f < 15; ++f) out[f * kKepT + j] = c[f];
   }
-  for (int j = 9 * kKepT; j < KW_STRIDE; ++j) out[j] = 0.0;
+  for (int j = 15 * kKepT; j < KW_STRIDE; ++j) out[j] = 0.0;
 }
 
 // Values and theta-derivatives of the walker table, wtan[b][i][k] = d w_i / d theta_k:

@@ -84,10 +84,14 @@ enum : int {
 };
 // Per walker and detector (setup): the series of the projections
 //   k.Delta_0, k.Delta_1, p.Delta_0, p.Delta_1, q.Delta_0, q.Delta_1,
-//   k.(x_0 - c), k.(x_1 - c), k.c   (9 x kKepT)
+//   k.(x_0 - c), k.(x_1 - c), k.c   (9 x kKepT, what the response evaluates),
+//   p.(x_0 - c), p.(x_1 - c), q.(x_0 - c), q.(x_1 - c), p.c, q.c
+//   (6 x kKepT, the reverse sweep's sky contraction)
 enum : int {
   KW_KD0 = 0, KW_KD1 = kKepT, KW_PD0 = 2 * kKepT, KW_PD1 = 3 * kKepT, KW_QD0 = 4 * kKepT,
-  KW_QD1 = 5 * kKepT, KW_KX0 = 6 * kKepT, KW_KX1 = 7 * kKepT, KW_KC = 8 * kKepT, KW_STRIDE = 120   // >= 117
+  KW_QD1 = 5 * kKepT, KW_KX0 = 6 * kKepT, KW_KX1 = 7 * kKepT, KW_KC = 8 * kKepT,
+  KW_PX0 = 9 * kKepT, KW_PX1 = 10 * kKepT, KW_QX0 = 11 * kKepT, KW_QX1 = 12 * kKepT, KW_PC = 13 * kKepT,
+  KW_QC = 14 * kKepT, KW_STRIDE = 200   // >= 15 kKepT (195)
 };
 
 // ---- per-bin tables (structure of arrays, n_bins doubles per field).
