@@ -293,7 +293,8 @@ __device__ __forceinline__ void adj_det(const double* __restrict__ bins, const d
   D[4] = in ? tb[T_DTR * N + kk] : 0.0;
   D[5] = in ? tb[T_DTI * N + kk] : 0.0;
   const DetParams& P = A.dt.p[det];
-  const Chan c = eval_channels<GEO, LS, 1, KEP>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi, kw, kinv);
+  const Chan c =
+      eval_channels<GEO, LS, 1, KEP, KwScalar>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi, KwScalar{kw}, kinv);
   dh = fma(D[0], c.ar, dh);
   dh = fma(D[1], c.ai, dh);
   dh = fma(D[2], c.er, dh);

@@ -31,9 +31,14 @@ struct TanTab {
 
 // Kepler orbit series coefficients are constant while a kernel runs and the
 // same for every lane: read through the constant address space, they come in
-// by scalar loads instead of occupying vector registers.
+// by scalar loads instead of occupying vector registers.  The derivative
+// kernels read them so (KwScalar, KwLane); the log-likelihood and response
+// kernels, whose scalar registers are the tighter ones, keep plain loads.
 typedef const __attribute__((address_space(4))) double cdouble;
 __device__ __forceinline__ cdouble* as_const(const double* p) { return (cdouble*)p; }
+struct KwScalar {
+  const double* __restrict__ p;
+};
 
 // The projected Kepler orbit series of a walker in the tangent kernels: the
 // values (wavefront-uniform) and this lane's tangent row (zeros unless its
@@ -42,7 +47,8 @@ struct KwLane {
   const double* __restrict__ v;
   const double* __restrict__ t;
 };
-__device__ __forceinline__ double kw_at(const double* __restrict__ kw, int i) { return as_const(kw)[i]; }
+__device__ __forceinline__ double kw_at(const double* __restrict__ kw, int i) { return kw[i]; }
+__device__ __forceinline__ double kw_at(const KwScalar& kw, int i) { return as_const(kw.p)[i]; }
 __device__ __forceinline__ Dual<1> kw_at(const KwLane& kw, int i) {
   Dual<1> r;
   r.v = as_const(kw.v)[i];
@@ -273,8 +279,16 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
         hs[k] = fma(c2a, hs[k - 1], -hs[k - 2]);
       }
       auto series = [&](const double* __restrict__ cg) __attribute__((always_inline)) {
+        S r;
+        if constexpr (std::is_same<KWA, const double*>::value) {
+          const double* __restrict__ c = cg;
+          r = c[0];
+#pragma unroll
+          for (int k = 1; k <= kKepH; ++k) r = fma(c[2 * k - 1], hc[k], fma(c[2 * k], hs[k], r));
+          return r;
+        }
         cdouble* c = as_const(cg);
-        S r = c[0];
+        r = c[0];
 #pragma unroll
         for (int k = 1; k <= kKepH; ++k) r = fma(c[2 * k - 1], hc[k], fma(c[2 * k], hs[k], r));
         return r;
@@ -405,13 +419,13 @@ __device__ __forceinline__ ChanT<S> eval_channels_t(const Tab& T, int det, const
   return c;
 }
 
-template <bool GEO, bool LONG_SINC, int CLS = 1, bool KEP = false>
+template <bool GEO, bool LONG_SINC, int CLS = 1, bool KEP = false, class KWA = const double*>
 __device__ __forceinline__ Chan eval_channels(const double* __restrict__ wt, int det, const ModePlan& plan,
                                               double inv_year, double inv_ptq, const BinRegs& b,
                                               double a, double zr, double zi,
-                                              const double* __restrict__ kw = nullptr,
+                                              KWA kw = KWA(),
                                               const double* __restrict__ kinv = nullptr) {
-  const ChanT<double> c = eval_channels_t<GEO, LONG_SINC, CLS, double, ValTab, NoProbe, KEP>(
+  const ChanT<double> c = eval_channels_t<GEO, LONG_SINC, CLS, double, ValTab, NoProbe, KEP, KWA>(
       ValTab{wt}, det, plan, inv_year, inv_ptq, b, a, zr, zi, NoProbe(), kw, kinv);
   return Chan{c.ar, c.ai, c.er, c.ei, c.tr, c.ti};
 }
