@@ -459,9 +459,10 @@ def kepler_leg(torch, pes, steps):
     """The headline workload with the heliocentric detector on exact Kepler
     ellipses (arms flexing at order e^2 AU) instead of the first-order
     triangle: evals/s at the autotuned tuning and the cost relative to the
-    first-order orbit in the same run; then the derivatives on both orbits
-    (Fisher matrices at 256 points, forward- and reverse-mode gradients at
-    1024 walkers)."""
+    first-order orbit in the same run, in FP64 and with the single-precision
+    kernels (and their deviation from FP64 relative to max(|L|, <d|d>/2));
+    then the derivatives on both orbits (Fisher matrices at 256 points,
+    forward- and reverse-mode gradients at 1024 walkers)."""
     out = {}
     for orbit in ("first_order", "kepler"):
         cfg = W.config("cfg1")
@@ -474,9 +475,20 @@ def kepler_leg(torch, pes, steps):
         ctx.set_data(ctx.response(th0)[0].clone())
         theta = torch.from_numpy(W.draw_walkers(B, stream=1)).to(dev)
         o = torch.empty(B, dtype=torch.float64, device=dev)
+        far = th0.clone()
+        far[0, 4] = 1e12
+        sigma = -float(ctx.loglike(far)[0])           # <d|d>/2
         _, tuning = ctx.autotune(theta)
         out[orbit] = dict(ms_per_call=round(_time_ms(torch, lambda: ctx.loglike(theta, o), steps), 3),
                           tuning=tuning)
+        L64 = o.cpu().numpy().copy()
+        ctx.set_precision(32)
+        _, tuning32 = ctx.autotune(theta)
+        out[orbit]["fp32_ms_per_call"] = round(_time_ms(torch, lambda: ctx.loglike(theta, o), steps), 3)
+        out[orbit]["fp32_tuning"] = tuning32
+        rel = np.abs(o.cpu().numpy() - L64) / np.maximum(np.abs(L64), sigma)
+        out[orbit]["fp32_max_rel_dev_from_fp64"] = float(f"{rel.max():.3e}")
+        ctx.set_precision(64)
         thf = theta[:256].contiguous()
         thg = theta[:1024].contiguous()
         ctx.set_grad_method("forward")
@@ -491,6 +503,10 @@ def kepler_leg(torch, pes, steps):
                 ms_per_call=k["ms_per_call"], evals_per_s=round(4096 / (k["ms_per_call"] * 1e-3), 1),
                 tuning=k["tuning"], first_order_ms_per_call_same_run=f["ms_per_call"],
                 cost_over_first_order=round(k["ms_per_call"] / f["ms_per_call"], 3),
+                fp32_ms_per_call=k["fp32_ms_per_call"], fp32_evals_per_s=round(4096 / (k["fp32_ms_per_call"] * 1e-3), 1),
+                fp32_tuning=k["fp32_tuning"], fp32_first_order_ms_per_call=f["fp32_ms_per_call"],
+                fp32_speedup_over_fp64=round(k["ms_per_call"] / k["fp32_ms_per_call"], 3),
+                fp32_max_rel_dev_from_fp64=k["fp32_max_rel_dev_from_fp64"],
                 fisher_ms=k["fisher_ms"], fisher_first_order_ms=f["fisher_ms"],
                 grad_forward_ms=k["grad_forward_ms"], grad_forward_first_order_ms=f["grad_forward_ms"],
                 grad_adjoint_ms=k["grad_adjoint_ms"], grad_adjoint_first_order_ms=f["grad_adjoint_ms"])

@@ -70,8 +70,8 @@ typedef struct {
                           heliocentric detector of a context takes the same); TianQin: 0.
                           With PES_ORBIT_KEPLER the link directions are the unit separations
                           of the spacecraft at t_f, the transfer function and the TDI factor
-                          keep the nominal L; such a context evaluates in FP64 (pes_probe
-                          and pes_set_precision(32) return PES_EINVAL). */
+                          keep the nominal L; pes_probe refuses such a context
+                          (PES_EINVAL). */
 } pes_detector;
 
 typedef struct {
@@ -179,8 +179,10 @@ int pes_loglike_noalloc(pes_ctx* ctx, const double* theta, int64_t B, double* lo
  * whole cycles before every sine and cosine, and the noise-weighted inner
  * products -- and evaluates the amplitudes, orbits, projections, link
  * transfer functions (eq. eq_fd_resp) and TDI combinations in FP32 with FP32
- * fits (the paper compares both precisions, Sec. 3.1, Fig. fig_cost).
- * Gradients and Fisher matrices stay FP64.  PES_EINVAL for other values. */
+ * fits (the paper compares both precisions, Sec. 3.1, Fig. fig_cost); on
+ * exact Kepler orbits the orbit series are evaluated in FP32 from FP32
+ * copies of their coefficients.  Gradients and Fisher matrices stay FP64.
+ * PES_EINVAL for other values. */
 int pes_set_precision(pes_ctx* ctx, int bits);
 
 /* Gradient of log L with respect to theta (Sec. 2.3 differentiates the

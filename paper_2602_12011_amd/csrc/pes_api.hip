@@ -64,10 +64,12 @@ struct pes_ctx {
   bool long_sinc = false;   // a detector's largest sinc argument exceeds the short fit
   int wg = 16;              // walkers per work item
   int bpc = 0;              // resident blocks per CU requested (0: occupancy limit)
-  int occ[3][3] = {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}};   // occupancy limit per variant (FP64, FP32, Kepler) and bins per lane
+  // occupancy limit per variant (FP64, FP32, Kepler FP64, Kepler FP32) and bins per lane
+  int occ[4][3] = {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}, {1, 1, 1}};
   bool f32 = false;         // single-precision log-likelihood and response kernels
   bool kep = false;         // heliocentric detectors on exact Kepler ellipses
   double* kep_tab = nullptr;  // [n_det][KV_STRIDE] orbit series (Kepler detectors)
+  float* kep_tab32 = nullptr; // its FP32 copy (single precision)
   int tile = 256;
   int grad_method = PES_GRAD_ADJOINT;
   int schedule = PES_SCHED_QUEUE;
@@ -79,6 +81,7 @@ struct pes_ctx {
   double* wtab = nullptr;
   float* wtab32 = nullptr;    // FP32 copy of wtab (single-precision kernels)
   double* wkep = nullptr;     // [cap][n_det][KW_STRIDE] projected orbit series (Kepler contexts)
+  float* wkep32 = nullptr;    // its FP32 copy (Kepler contexts, single precision)
   double* wkept = nullptr;    // [jcap][n_det][3][KW_STRIDE] their sky-angle derivatives (Kepler contexts)
   int* ntiles = nullptr;
   int* perm = nullptr;
@@ -114,8 +117,8 @@ int fail_hip(pes_ctx* c, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return fail_hip((ctx), e_, #call); \
   } while (0)
 
-// Kernel variant of the log-likelihood: 0 FP64, 1 FP32, 2 FP64 on exact Kepler orbits.
-int occ_var(const pes_ctx* c) { return c->kep ? 2 : (c->f32 ? 1 : 0); }
+// Kernel variant of the log-likelihood: 0 FP64, 1 FP32, 2 FP64 and 3 FP32 on exact Kepler orbits.
+int occ_var(const pes_ctx* c) { return (c->kep ? 2 : 0) + (c->f32 ? 1 : 0); }
 
 bool mode_ok(int l, int m) {
   return (l == 2 && (m == 2 || m == 1)) || (l == 3 && (m == 3 || m == 2)) || (l == 4 && m == 4);
@@ -125,6 +128,7 @@ void free_workspace(pes_ctx* c) {
   (void)hipFree(c->wtab);
   (void)hipFree(c->wtab32);
   (void)hipFree(c->wkep);
+  (void)hipFree(c->wkep32);
   (void)hipFree(c->ntiles);
   (void)hipFree(c->perm);
   (void)hipFree(c->gstart);
@@ -133,6 +137,7 @@ void free_workspace(pes_ctx* c) {
   c->wtab = nullptr;
   c->wtab32 = nullptr;
   c->wkep = nullptr;
+  c->wkep32 = nullptr;
   c->ntiles = c->perm = c->gstart = c->counters = nullptr;
   c->partial = nullptr;
   c->cap = 0;
@@ -146,6 +151,7 @@ int ensure_workspace(pes_ctx* c, int64_t B) {
   if (hipMalloc(&c->wtab, sizeof(double) * cap * W_STRIDE) != hipSuccess ||
       hipMalloc(&c->wtab32, sizeof(float) * cap * W_STRIDE) != hipSuccess ||
       (c->kep && hipMalloc(&c->wkep, sizeof(double) * cap * c->cfg.n_det * KW_STRIDE) != hipSuccess) ||
+      (c->kep && hipMalloc(&c->wkep32, sizeof(float) * cap * c->cfg.n_det * KW_STRIDE) != hipSuccess) ||
       hipMalloc(&c->ntiles, sizeof(int) * cap) != hipSuccess ||
       hipMalloc(&c->perm, sizeof(int) * cap) != hipSuccess ||
       hipMalloc(&c->gstart, sizeof(int) * (ng + 1)) != hipSuccess ||
@@ -400,9 +406,9 @@ int pes_create(const pes_config* cfg, pes_ctx** out) {
   c->tile = 256 * c->bpl;
   c->ntmax = (int)((c->N + c->tile - 1) / c->tile);
   c->ntmax_alloc = (int)((c->N + 255) / 256);
-  for (int p = 0; p < 3; ++p)
+  for (int p = 0; p < 4; ++p)
     for (int bpl = 1; bpl <= 2; ++bpl)
-      c->occ[p][bpl] = std::max(1, loglike_blocks_per_cu(bpl, c->long_sinc, p == 1, p == 2));
+      c->occ[p][bpl] = std::max(1, loglike_blocks_per_cu(bpl, c->long_sinc, (p & 1) != 0, p >= 2));
   const int64_t nb = (c->N + 255) / 256;
   if (hipMalloc(&c->bins, sizeof(double) * B_NFIELDS * c->N) != hipSuccess ||
       hipMalloc(&c->tabs, sizeof(double) * T_NFIELDS * c->N * cfg->n_det) != hipSuccess ||
@@ -415,8 +421,12 @@ int pes_create(const pes_config* cfg, pes_ctx** out) {
     double host[kMaxDet * KV_STRIDE] = {0};
     for (int i = 0; i < cfg->n_det; ++i)
       if (cfg->det[i].kind != PES_TIANQIN) kepler_table(cfg->det[i], host + i * KV_STRIDE);
+    float host32[kMaxDet * KV_STRIDE];
+    for (int i = 0; i < kMaxDet * KV_STRIDE; ++i) host32[i] = (float)host[i];
     if (hipMalloc(&c->kep_tab, sizeof(double) * kMaxDet * KV_STRIDE) != hipSuccess ||
-        hipMemcpy(c->kep_tab, host, sizeof(host), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(c->kep_tab, host, sizeof(host), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc(&c->kep_tab32, sizeof(float) * kMaxDet * KV_STRIDE) != hipSuccess ||
+        hipMemcpy(c->kep_tab32, host32, sizeof(host32), hipMemcpyHostToDevice) != hipSuccess) {
       pes_destroy(c);
       return PES_ENOMEM;
     }
@@ -442,6 +452,7 @@ int pes_destroy(pes_ctx* c) {
   (void)hipFree(c->dd_part);
   (void)hipFree(c->dd);
   (void)hipFree(c->kep_tab);
+  (void)hipFree(c->kep_tab32);
   delete c;
   return PES_OK;
 }
@@ -635,6 +646,8 @@ int pes_probe(pes_ctx* c, const double* theta, int64_t B, int stage, double* out
   ra.wtab32 = nullptr;
   ra.wkep = nullptr;
   ra.kep = nullptr;
+  ra.wkep32 = nullptr;
+  ra.kep32 = nullptr;
   ra.out = out;
   ra.N = c->N;
   ra.n_modes = c->cfg.n_modes;
@@ -654,6 +667,7 @@ int pes_response(pes_ctx* c, const double* theta, int64_t B, double* out, void* 
   PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, setup_args(c), s));
   if (c->f32) PES_HIP(c, launch_table32(c->wtab, B, c->wtab32, s));
   if (c->kep) PES_HIP(c, launch_kepler_proj(theta, B, c->kep_tab, setup_args(c), c->wkep, s));
+  if (c->kep && c->f32) PES_HIP(c, launch_copy_f32(c->wkep, B * c->cfg.n_det * KW_STRIDE, c->wkep32, s));
   ResponseArgs ra;
   ra.bins = c->bins;
   ra.tabs = c->tabs;
@@ -661,6 +675,8 @@ int pes_response(pes_ctx* c, const double* theta, int64_t B, double* out, void* 
   ra.wtab32 = c->f32 ? c->wtab32 : nullptr;
   ra.wkep = c->kep ? c->wkep : nullptr;
   ra.kep = c->kep_tab;
+  ra.wkep32 = c->kep && c->f32 ? c->wkep32 : nullptr;
+  ra.kep32 = c->kep_tab32;
   ra.out = out;
   ra.N = c->N;
   ra.n_modes = c->cfg.n_modes;
@@ -680,6 +696,7 @@ struct LoglikeWork {
   double* wtab;
   float* wtab32;
   double* wkep;
+  float* wkep32;
   int* ntiles;
   int* perm;
   int* gstart;
@@ -712,6 +729,7 @@ int run_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, const 
   PES_HIP(c, launch_setup(theta, B, ws.wtab, ws.ntiles, sa, s));
   if (c->f32) PES_HIP(c, launch_table32(ws.wtab, B, ws.wtab32, s));
   if (c->kep) PES_HIP(c, launch_kepler_proj(theta, B, c->kep_tab, sa, ws.wkep, s));
+  if (c->kep && c->f32) PES_HIP(c, launch_copy_f32(ws.wkep, B * c->cfg.n_det * KW_STRIDE, ws.wkep32, s));
   PES_HIP(c, launch_plan(ws.ntiles, (int)B, c->wg, c->ntmax, !grid_mode, ws.perm, ws.gstart, ws.counters, s));
   LoglikeArgs a;
   a.bins = c->bins;
@@ -720,6 +738,8 @@ int run_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, const 
   a.wtab32 = ws.wtab32;
   a.wkep = ws.wkep;
   a.kep = c->kep_tab;
+  a.wkep32 = c->kep && c->f32 ? ws.wkep32 : nullptr;
+  a.kep32 = c->kep_tab32;
   a.ntiles = ws.ntiles;
   a.perm = ws.perm;
   a.gstart = ws.gstart;
@@ -762,14 +782,15 @@ int pes_loglike(pes_ctx* c, const double* theta, int64_t B, double* logl, void* 
   if (st != PES_OK) return st;
   st = ensure_workspace(c, B);
   if (st != PES_OK) return st;
-  const LoglikeWork ws{c->wtab, c->wtab32, c->wkep, c->ntiles, c->perm, c->gstart, c->counters, c->partial};
+  const LoglikeWork ws{c->wtab,  c->wtab32, c->wkep,     c->wkep32, c->ntiles,
+                       c->perm,  c->gstart, c->counters, c->partial};
   return run_loglike(c, theta, B, logl, ws, (hipStream_t)stream);
 }
 
 // The log-likelihood workspace of B walkers carved out of one buffer (each
 // part 256-byte aligned); returns the bytes it takes.  base may be null to
 // size it only.
-static int64_t carve_loglike_work(char* base, int64_t B, int ntmax, int n_kep, LoglikeWork* ws) {
+static int64_t carve_loglike_work(char* base, int64_t B, int ntmax, int n_kep, bool f32, LoglikeWork* ws) {
   int64_t off = 0;
   auto take = [&](int64_t bytes) {
     char* p = base ? base + off : nullptr;
@@ -779,14 +800,15 @@ static int64_t carve_loglike_work(char* base, int64_t B, int ntmax, int n_kep, L
   char* wtab = take(sizeof(double) * B * W_STRIDE);
   char* wtab32 = take(sizeof(float) * B * W_STRIDE);
   char* wkep = n_kep > 0 ? take(sizeof(double) * B * n_kep * KW_STRIDE) : nullptr;
+  char* wkep32 = n_kep > 0 && f32 ? take(sizeof(float) * B * n_kep * KW_STRIDE) : nullptr;
   char* ntiles = take(sizeof(int) * B);
   char* perm = take(sizeof(int) * B);
   char* gstart = take(sizeof(int) * (B + 3));
   char* counters = take(sizeof(int) * 4);
   char* partial = take(sizeof(double) * 2 * B * (int64_t)ntmax);
   if (ws)
-    *ws = LoglikeWork{(double*)wtab,  (float*)wtab32, (double*)wkep,   (int*)ntiles,
-                      (int*)perm,     (int*)gstart,   (int*)counters,  (double*)partial};
+    *ws = LoglikeWork{(double*)wtab, (float*)wtab32, (double*)wkep,   (float*)wkep32,  (int*)ntiles,
+                      (int*)perm,    (int*)gstart,   (int*)counters,  (double*)partial};
   return off;
 }
 
@@ -801,14 +823,14 @@ int pes_loglike_noalloc(pes_ctx* c, const double* theta, int64_t B, double* logl
     return PES_EHIP;
   }
   const int n_kep = c->kep ? c->cfg.n_det : 0;
-  const int64_t need = carve_loglike_work(nullptr, B, c->ntmax, n_kep, nullptr);
+  const int64_t need = carve_loglike_work(nullptr, B, c->ntmax, n_kep, c->f32, nullptr);
   if (need > kScratchBytes) {
     snprintf(c->err, sizeof(c->err), "%lld walkers x %d tiles need %lld bytes of scratch; it holds %lld",
              (long long)B, c->ntmax, (long long)need, (long long)kScratchBytes);
     return PES_ESHAPE;
   }
   LoglikeWork ws;
-  carve_loglike_work((char*)c->scratch, B, c->ntmax, n_kep, &ws);
+  carve_loglike_work((char*)c->scratch, B, c->ntmax, n_kep, c->f32, &ws);
   return run_loglike(c, theta, B, logl, ws, (hipStream_t)stream);
 }
 
@@ -878,10 +900,6 @@ int pes_grad(pes_ctx* c, const double* theta, int64_t B, double* logl, double* g
 
 int pes_set_precision(pes_ctx* c, int bits) {
   if (!c || (bits != 32 && bits != 64)) return PES_EINVAL;
-  if (c->kep && bits == 32) {
-    snprintf(c->err, sizeof(c->err), "exact Kepler orbits are evaluated in FP64 only");
-    return PES_EINVAL;
-  }
   c->f32 = bits == 32;
   return PES_OK;
 }

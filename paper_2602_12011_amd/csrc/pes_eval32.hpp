@@ -4,10 +4,11 @@
 // mode's SPA phase (up to ~1e6 cycles) and t_f (up to ~3e7 s) from the same
 // series as the FP64 evaluation, f t_c, the cutoff test, and the exact
 // removal of whole cycles before every sine and cosine.  Everything after
-// that -- amplitude and taper, the orbit at t_f, the projections, the Roemer
-// delay, the polarization factors, the six links with their transfer
-// functions and the TDI combinations -- runs in FP32 with FP32 fits, on an
-// FP32 copy of the walker table.  The channels are returned in FP32; the
+// that -- amplitude and taper, the orbit at t_f, the projections (of the
+// first-order triangle or the series of the exact Kepler ellipses), the
+// Roemer delay, the polarization factors, the six links with their transfer
+// functions and the TDI combinations -- runs in FP32 with FP32 fits, on FP32
+// copies of the walker table and of the orbit series.  The channels are returned in FP32; the
 // caller forms the noise-weighted inner products in FP64.
 #pragma once
 #include "pes_eval.hpp"
@@ -35,12 +36,17 @@ __device__ __forceinline__ float sinc_fit_f(float b) {
 
 // wt: the walker's FP64 table (phase, t_f, cutoff, t_c); ws: its FP32 copy
 // (everything else).  b: the bin's FP64 powers; a = pi f L, (zr, zi) =
-// e^{-2 pi i f L} in FP32.
-template <bool GEO, bool LONG_SINC, int CLS>
+// e^{-2 pi i f L} in FP32.  KEP: a heliocentric detector on exact Kepler
+// ellipses, with FP32 copies of the walker's projected orbit series for this
+// detector (kw, [KW_STRIDE]) and of the detector's inverse-arm-length series
+// (kinv, [3][kKepT]).
+template <bool GEO, bool LONG_SINC, int CLS, bool KEP = false>
 __device__ __forceinline__ ChanT<float> eval_channels_f32(const double* __restrict__ wt,
                                                           const float* __restrict__ ws, int det,
                                                           const ModePlan& plan, double inv_year, double inv_ptq,
-                                                          const BinRegs& b, float a, float zr, float zi) {
+                                                          const BinRegs& b, float a, float zr, float zi,
+                                                          const float* __restrict__ kw = nullptr,
+                                                          const float* __restrict__ kinv = nullptr) {
   float yFr0 = 0.0f, yFi0 = 0.0f, yBr0 = 0.0f, yBi0 = 0.0f;
   float yFr1 = 0.0f, yFi1 = 0.0f, yBr1 = 0.0f, yBi1 = 0.0f;
   float yFr2 = 0.0f, yFi2 = 0.0f, yBr2 = 0.0f, yBi2 = 0.0f;
@@ -106,22 +112,68 @@ __device__ __forceinline__ ChanT<float> eval_channels_f32(const double* __restri
       aCi = am * ws[R0 + R_KCI];
     }
     // spacecraft geometry at t_f: the orbit phases reduced in FP64
-    float sa, ca, ua, ub;
+    float sa, ca;
     sincos_cycles_f(fma(tau, inv_year, wt[D0 + D_AO]), sa, ca);
-    if (GEO) {
-      sincos_cycles_f(fma(tau, inv_ptq, wt[D0 + D_PO]), ub, ua);
+    float kn0, kn1, kn2, np0, np1, np2, nq0, nq1, nq2, kd0, kd1, kR;
+    if constexpr (KEP) {
+      // exact Kepler ellipses: the same series as the FP64 evaluation, in FP32
+      // (harmonics cos k alpha, sin k alpha by the Chebyshev recurrence)
+      float hc[kKepH + 1], hs[kKepH + 1];
+      hc[0] = 1.0f;
+      hs[0] = 0.0f;
+      hc[1] = ca;
+      hs[1] = sa;
+      const float c2a = 2.0f * ca;
+#pragma unroll
+      for (int k = 2; k <= kKepH; ++k) {
+        hc[k] = fmaf(c2a, hc[k - 1], -hc[k - 2]);
+        hs[k] = fmaf(c2a, hs[k - 1], -hs[k - 2]);
+      }
+      auto series = [&](const float* __restrict__ c) __attribute__((always_inline)) {
+        float r = c[0];
+#pragma unroll
+        for (int k = 1; k <= kKepH; ++k) r = fmaf(c[2 * k - 1], hc[k], fmaf(c[2 * k], hs[k], r));
+        return r;
+      };
+      const float iL0 = series(kinv), iL1 = series(kinv + kKepT), iL2 = series(kinv + 2 * kKepT);
+      const float KD0 = series(kw + KW_KD0), KD1 = series(kw + KW_KD1);
+      const float PD0 = series(kw + KW_PD0), PD1 = series(kw + KW_PD1);
+      const float QD0 = series(kw + KW_QD0), QD1 = series(kw + KW_QD1);
+      kn0 = KD0 * iL0;
+      kn1 = KD1 * iL1;
+      kn2 = -(KD0 + KD1) * iL2;
+      np0 = PD0 * iL0;
+      np1 = PD1 * iL1;
+      np2 = -(PD0 + PD1) * iL2;
+      nq0 = QD0 * iL0;
+      nq1 = QD1 * iL1;
+      nq2 = -(QD0 + QD1) * iL2;
+      kd0 = series(kw + KW_KX0);
+      kd1 = series(kw + KW_KX1);
+      kR = series(kw + KW_KC);
     } else {
-      ua = fmaf(-2.0f * sa, sa, 1.0f);
-      ub = 2.0f * sa * ca;
-    }
+      float ua, ub;
+      if (GEO) {
+        sincos_cycles_f(fma(tau, inv_ptq, wt[D0 + D_PO]), ub, ua);
+      } else {
+        ua = fmaf(-2.0f * sa, sa, 1.0f);
+        ub = 2.0f * sa * ca;
+      }
 #define PES_LIN(off) (fmaf(sd((off) + 3), sa, fmaf(sd((off) + 2), ca, fmaf(sd((off) + 1), ub, sd((off)) * ua))) + sd((off) + 4))
-    const float kn0 = PES_LIN(D_KN), kn1 = PES_LIN(D_KN + 5);
-    const float np0 = PES_LIN(D_NP), np1 = PES_LIN(D_NP + 5);
-    const float nq0 = PES_LIN(D_NQ), nq1 = PES_LIN(D_NQ + 5);
-    const float kd0 = PES_LIN(D_KD), kd1 = PES_LIN(D_KD + 5);
+      kn0 = PES_LIN(D_KN);
+      kn1 = PES_LIN(D_KN + 5);
+      np0 = PES_LIN(D_NP);
+      np1 = PES_LIN(D_NP + 5);
+      nq0 = PES_LIN(D_NQ);
+      nq1 = PES_LIN(D_NQ + 5);
+      kd0 = PES_LIN(D_KD);
+      kd1 = PES_LIN(D_KD + 5);
 #undef PES_LIN
-    const float kn2 = -(kn0 + kn1), np2 = -(np0 + np1), nq2 = -(nq0 + nq1);
-    const float kR = fmaf(sd(D_KR), ca, sd(D_KR + 1) * sa);
+      kn2 = -(kn0 + kn1);
+      np2 = -(np0 + np1);
+      nq2 = -(nq0 + nq1);
+      kR = fmaf(sd(D_KR), ca, sd(D_KR + 1) * sa);
+    }
     // mode phase plus the Roemer delay, whole cycles removed in FP64
     float sp, cp;
     sincos_cycles_f(fma(b.f, (double)kR, phase), sp, cp);
@@ -188,13 +240,16 @@ __device__ __forceinline__ ChanT<float> eval_channels_f32(const double* __restri
   return c;
 }
 
-template <bool GEO, bool LONG_SINC>
+template <bool GEO, bool LONG_SINC, bool KEP = false>
 __device__ __forceinline__ ChanT<float> eval_channels_f32_cls(int cls, const double* __restrict__ wt,
                                                               const float* __restrict__ ws, int det,
                                                               const ModePlan& plan, double inv_year, double inv_ptq,
-                                                              const BinRegs& b, float a, float zr, float zi) {
-  if (cls == 0) return eval_channels_f32<GEO, LONG_SINC, 0>(wt, ws, det, plan, inv_year, inv_ptq, b, a, zr, zi);
-  return eval_channels_f32<GEO, LONG_SINC, 1>(wt, ws, det, plan, inv_year, inv_ptq, b, a, zr, zi);
+                                                              const BinRegs& b, float a, float zr, float zi,
+                                                              const float* __restrict__ kw = nullptr,
+                                                              const float* __restrict__ kinv = nullptr) {
+  if (cls == 0)
+    return eval_channels_f32<GEO, LONG_SINC, 0, KEP>(wt, ws, det, plan, inv_year, inv_ptq, b, a, zr, zi, kw, kinv);
+  return eval_channels_f32<GEO, LONG_SINC, 1, KEP>(wt, ws, det, plan, inv_year, inv_ptq, b, a, zr, zi, kw, kinv);
 }
 
 }  // namespace pes

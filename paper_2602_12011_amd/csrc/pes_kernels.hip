@@ -734,12 +734,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
           Chan c;
           if constexpr (F32) {
             const float* __restrict__ ws = A.wtab32 + (int64_t)w * W_STRIDE;
-            const ChanT<float> cf =
-                (P.kind == 2)
-                    ? eval_channels_f32_cls<true, LS>(cls[q], wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br[q],
-                                                      (float)aa[q], (float)zr[q], (float)zi[q])
-                    : eval_channels_f32_cls<false, LS>(cls[q], wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br[q],
-                                                       (float)aa[q], (float)zr[q], (float)zi[q]);
+            ChanT<float> cf;
+            if (P.kind == 2) {
+              cf = eval_channels_f32_cls<true, LS>(cls[q], wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br[q],
+                                                   (float)aa[q], (float)zr[q], (float)zi[q]);
+            } else if constexpr (KEP) {
+              const float* __restrict__ kw = A.wkep32 + ((int64_t)w * A.n_det + det) * KW_STRIDE;
+              const float* __restrict__ kinv = A.kep32 + det * KV_STRIDE + KV_INVL;
+              cf = eval_channels_f32_cls<false, LS, true>(cls[q], wt, ws, det, A.plan, P.inv_year, P.inv_ptq,
+                                                          br[q], (float)aa[q], (float)zr[q], (float)zi[q], kw, kinv);
+            } else {
+              cf = eval_channels_f32_cls<false, LS>(cls[q], wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br[q],
+                                                    (float)aa[q], (float)zr[q], (float)zi[q]);
+            }
             c = Chan{cf.ar, cf.ai, cf.er, cf.ei, cf.tr, cf.ti};
           } else if (P.kind == 2) {
             c = eval_channels_cls<true, LS>(cls[q], wt, det, A.plan, P.inv_year, P.inv_ptq, br[q], aa[q], zr[q],
@@ -858,9 +865,17 @@ __global__ void response_kernel(ResponseArgs A) {
       if constexpr (F32) {
         const float* __restrict__ ws = A.wtab32 + b * W_STRIDE;
         const float a = (float)tb[T_A * N + k], zr = (float)tb[T_ZR * N + k], zi = (float)tb[T_ZI * N + k];
-        const ChanT<float> cf =
-            (P.kind == 2) ? eval_channels_f32<true, LS, 1>(wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi)
-                          : eval_channels_f32<false, LS, 1>(wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi);
+        ChanT<float> cf;
+        if (P.kind == 2) {
+          cf = eval_channels_f32<true, LS, 1>(wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi);
+        } else if constexpr (KEP) {
+          const float* __restrict__ kw = A.wkep32 + (b * A.n_det + det) * KW_STRIDE;
+          const float* __restrict__ kinv = A.kep32 + det * KV_STRIDE + KV_INVL;
+          cf = eval_channels_f32<false, LS, 1, true>(wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi, kw,
+                                                     kinv);
+        } else {
+          cf = eval_channels_f32<false, LS, 1>(wt, ws, det, A.plan, P.inv_year, P.inv_ptq, br, a, zr, zi);
+        }
         c = Chan{cf.ar, cf.ai, cf.er, cf.ei, cf.tr, cf.ti};
       } else if (P.kind == 2) {
         c = eval_channels<true, LS>(wt, det, A.plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k], tb[T_ZR * N + k],
@@ -886,7 +901,8 @@ __global__ void response_kernel(ResponseArgs A) {
   }
 }
 
-// FP32 copy of the walker tables for the single-precision kernels.
+// FP32 copy of the walker tables (or of the orbit series) for the
+// single-precision kernels.
 __global__ void table32_kernel(const double* __restrict__ wtab, int64_t n, float* __restrict__ wtab32) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) wtab32[i] = (float)wtab[i];
@@ -1030,13 +1046,14 @@ static void launch_ll_f(const LoglikeArgs& a, int bpl, bool long_sinc, int grid,
     long_sinc ? launch_ll<1, true, F32, KEP>(a, grid, s) : launch_ll<1, false, F32, KEP>(a, grid, s);
 }
 
-// Variants: FP64, FP32, and FP64 on exact Kepler orbits (not combined with FP32).
+// Variants: FP64 or FP32, each on the first-order orbit or on exact Kepler orbits.
 hipError_t launch_loglike(const LoglikeArgs& a, int bpl, bool long_sinc, bool f32, bool kep, int grid,
                           hipStream_t s) {
   if (f32 && !a.wtab32) return hipErrorInvalidValue;       // the FP32 kernels read the FP32 walker tables
-  if (kep && (f32 || !a.wkep || !a.kep)) return hipErrorInvalidValue;   // and the Kepler ones the orbit series
+  if (kep && (!a.wkep || !a.kep)) return hipErrorInvalidValue;   // and the Kepler ones the orbit series
+  if (kep && f32 && (!a.wkep32 || !a.kep32)) return hipErrorInvalidValue;   // in FP32 their FP32 copies
   if (f32)
-    launch_ll_f<true, false>(a, bpl, long_sinc, grid, s);
+    kep ? launch_ll_f<true, true>(a, bpl, long_sinc, grid, s) : launch_ll_f<true, false>(a, bpl, long_sinc, grid, s);
   else if (kep)
     launch_ll_f<false, true>(a, bpl, long_sinc, grid, s);
   else
@@ -1061,10 +1078,15 @@ hipError_t launch_kepler_proj_tan(const double* theta, int64_t B, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_table32(const double* wtab, int64_t B, float* wtab32, hipStream_t s) {
-  const int64_t n = B * W_STRIDE;
-  hipLaunchKernelGGL(table32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, wtab, n, wtab32);
+hipError_t launch_copy_f32(const double* src, int64_t n, float* dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (!src || !dst) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(table32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, n, dst);
   return hipGetLastError();
+}
+
+hipError_t launch_table32(const double* wtab, int64_t B, float* wtab32, hipStream_t s) {
+  return launch_copy_f32(wtab, B * W_STRIDE, wtab32, s);
 }
 
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
@@ -1091,10 +1113,13 @@ static void launch_resp(const ResponseArgs& a, dim3 grid, int bs, hipStream_t s)
 
 hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, bool f32, bool kep, hipStream_t s) {
   if (f32 && !a.wtab32) return hipErrorInvalidValue;   // the FP32 kernel reads the FP32 walker tables
-  if (kep && (f32 || !a.wkep || !a.kep)) return hipErrorInvalidValue;
+  if (kep && (!a.wkep || !a.kep)) return hipErrorInvalidValue;
+  if (kep && f32 && (!a.wkep32 || !a.kep32)) return hipErrorInvalidValue;
   const int bs = 256;
   const dim3 grid((unsigned)((a.N + bs - 1) / bs), (unsigned)B);
-  if (f32)
+  if (f32 && kep)
+    long_sinc ? launch_resp<true, true, true>(a, grid, bs, s) : launch_resp<false, true, true>(a, grid, bs, s);
+  else if (f32)
     long_sinc ? launch_resp<true, true, false>(a, grid, bs, s) : launch_resp<false, true, false>(a, grid, bs, s);
   else if (kep)
     long_sinc ? launch_resp<true, false, true>(a, grid, bs, s) : launch_resp<false, false, true>(a, grid, bs, s);
@@ -1117,7 +1142,7 @@ static int blocks_per_cu(int bpl, bool long_sinc) {
 }
 
 int loglike_blocks_per_cu(int bpl, bool long_sinc, bool f32, bool kep) {
-  if (f32) return blocks_per_cu<true, false>(bpl, long_sinc);
+  if (f32) return kep ? blocks_per_cu<true, true>(bpl, long_sinc) : blocks_per_cu<true, false>(bpl, long_sinc);
   return kep ? blocks_per_cu<false, true>(bpl, long_sinc) : blocks_per_cu<false, false>(bpl, long_sinc);
 }
 

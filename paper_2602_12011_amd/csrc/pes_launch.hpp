@@ -40,6 +40,8 @@ struct LoglikeArgs {
   ModePlan plan;
   int grid_mode;   // 1: block i takes work item i (plain grid); 0: atomic ticket
   DetTable dt;
+  const float* wkep32;   // FP32 copies of wkep and kep (single precision on exact Kepler orbits only)
+  const float* kep32;
 };
 
 struct ResponseArgs {
@@ -54,6 +56,8 @@ struct ResponseArgs {
   int n_modes, n_det;
   ModePlan plan;
   DetTable dt;
+  const float* wkep32;   // FP32 copies of wkep and kep (single precision on exact Kepler orbits only)
+  const float* kep32;
 };
 
 // Doubles per walker of the compact tangent table of the reverse sweep.
@@ -98,6 +102,7 @@ hipError_t launch_kepler_proj(const double* theta, int64_t B, const double* kep,
 hipError_t launch_kepler_proj_tan(const double* theta, int64_t B, const double* kep, const SetupArgs& sa,
                                   double* wkept, hipStream_t s);
 hipError_t launch_table32(const double* wtab, int64_t B, float* wtab32, hipStream_t s);
+hipError_t launch_copy_f32(const double* src, int64_t n, float* dst, hipStream_t s);
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
                            int64_t B, double* logl, hipStream_t s);
 hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, int stage, hipStream_t s);

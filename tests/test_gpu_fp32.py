@@ -1,5 +1,8 @@
 """The single-precision response and log-likelihood (pes_set_precision(ctx, 32))
-against the FP64 oracle, with a tolerance derived from the FP32 arithmetic.
+against the FP64 oracle, with a tolerance derived from the FP32 arithmetic, on
+the first-order orbit and (kep_* cases) on exact Kepler ellipses, whose orbit
+series the FP32 kernels sum in FP32 (13 terms each; the Roemer delay from the
+centroid's series stays within the dR below, |k.c| <= (1 + e) AU/c).
 
 With u = 2^-24 the unit roundoff of FP32, a channel value at frequency f of a
 detector with arm L (light-seconds) carries a relative error of at most
@@ -49,10 +52,12 @@ def pes():
     return P
 
 
-def _cfg(name, n_bins=None, dets=None):
+def _cfg(name, n_bins=None, dets=None, kepler=False):
     c = W.config(name, n_bins=n_bins)
     if dets is not None:
         c["detectors"] = dets
+    if kepler:   # heliocentric detectors on exact Kepler ellipses (TianQin stays geocentric)
+        c["detectors"] = [d if d["kind"] == "tianqin" else dict(d, orbit="kepler") for d in c["detectors"]]
     return c
 
 
@@ -68,6 +73,9 @@ CASES = {
     "net_ragged": (lambda: _cfg("cfg2", n_bins=9000 + 5), 16, False),
     "tdi15_hm": (lambda: _cfg("cfg1", n_bins=4096 + 255, dets=[dict(W.LISA, tdi_gen=15)]), 12, False),
     "pe_long_sinc": (lambda: W.config("pehm"), 12, False),
+    "kep_hm_ragged": (lambda: _cfg("cfg1", n_bins=20000 + 37, kepler=True), 32, False),
+    "kep_net_ragged": (lambda: _cfg("cfg2", n_bins=9000 + 5, kepler=True), 16, False),
+    "kep_pe_long_sinc": (lambda: _cfg("pehm", kepler=True), 12, False),
 }
 
 
@@ -75,13 +83,14 @@ def _freqs(cfg):
     return cfg["f0"] + np.arange(cfg["n_bins"]) * cfg["df"]
 
 
-@pytest.mark.parametrize("case", ["cfg0_full", "hm_ragged", "net_ragged", "tdi15_hm", "pe_long_sinc"])
+@pytest.mark.parametrize("case", ["cfg0_full", "hm_ragged", "net_ragged", "tdi15_hm", "pe_long_sinc",
+                                  "kep_hm_ragged", "kep_net_ragged", "kep_pe_long_sinc"])
 def test_response_fp32(orc, torch_dev, pes, case):
     torch = torch_dev
     cfg = CASES[case][0]()
-    th = np.vstack([W.THETA_PE if case == "pe_long_sinc" else W.THETA0,
+    th = np.vstack([W.THETA_PE if case.endswith("pe_long_sinc") else W.THETA0,
                     W.draw_walkers(3, stream=21, flat=CASES[case][2])])
-    if case == "pe_long_sinc":
+    if case.endswith("pe_long_sinc"):
         th[1, 0] = 1.0e5            # a light walker reaches the long-sinc bins
     print(f"[fp32] response {case}: n_bins={cfg['n_bins']} dets={len(cfg['detectors'])}", flush=True)
     ctx = pes.Context(cfg)
@@ -132,7 +141,7 @@ def test_loglike_fp32(orc, torch_dev, pes, case):
     torch = torch_dev
     mk, B, flat = CASES[case]
     cfg = mk()
-    inj = W.THETA_PE if case == "pe_long_sinc" else W.THETA0
+    inj = W.THETA_PE if case.endswith("pe_long_sinc") else W.THETA0
     d = orc.response(cfg, inj)
     th = np.vstack([inj, W.draw_walkers(B - 1, stream=11, flat=flat)])
     print(f"[fp32] loglike {case}: n_bins={cfg['n_bins']} dets={len(cfg['detectors'])} B={B}", flush=True)
@@ -164,14 +173,16 @@ def test_loglike_fp32(orc, torch_dev, pes, case):
     assert np.allclose(Ls[0], Ls[1], rtol=1e-12, atol=1e-9 * sigma)
 
 
-def test_fp32_full_size_sampled(orc, torch_dev, pes):
-    """The benchmark's FP32 launch (4096 walkers, 2^20 bins, five modes) on 8
-    walkers at evenly spaced ranks of the mass order, against the oracle with
-    the derived bound above."""
+@pytest.mark.parametrize("kepler", [False, True])
+def test_fp32_full_size_sampled(orc, torch_dev, pes, kepler):
+    """The benchmark's FP32 launches (4096 walkers, 2^20 bins, five modes, on
+    the first-order orbit and on exact Kepler ellipses) on 8 walkers at evenly
+    spaced ranks of the mass order, against the oracle with the derived bound
+    above."""
     torch = torch_dev
-    cfg = _cfg("cfg1")
+    cfg = _cfg("cfg1", kepler=kepler)
     B = cfg["walkers"]
-    print(f"[fp32] full size: B={B} n_bins={cfg['n_bins']}", flush=True)
+    print(f"[fp32] full size: kepler={kepler} B={B} n_bins={cfg['n_bins']}", flush=True)
     d = orc.response(cfg, W.THETA0)
     th = W.draw_walkers(B, stream=1)
     ctx = pes.Context(cfg)
