@@ -65,7 +65,7 @@ def lib():
         L.or_inner.restype = C.c_double
         L.or_psd.argtypes = [C.POINTER(Detector), dp, C.c_int64, dp]
         L.or_orbit.argtypes = [C.POINTER(Detector), C.c_double, dp]
-        L.or_link_fd.argtypes = [C.c_double, C.c_double, dp, dp, dp, dp]
+        L.or_link_fd.argtypes = [C.c_double, C.c_double, dp, dp, dp, dp, C.c_int]
         L.or_tdi.argtypes = [C.c_double, C.c_double, C.c_int, dp, dp, dp]
         L.or_ylm.argtypes = [C.c_int, C.c_int, C.c_double]
         L.or_ylm.restype = C.c_double
@@ -181,13 +181,15 @@ def orbit(det, t):
     return x
 
 
-def link_fd(f, L_s, k, x, H):
+def link_fd(f, L_s, k, x, H, unit=False):
+    """The six links of a static geometry; unit: link directions are the unit
+    separations of the spacecraft (exact Kepler orbits) instead of (x_r - x_s)/L."""
     k = _f64(k)
     x = _f64(x)
     H = np.asarray(H, dtype=np.complex128)
     Hr = _f64(np.stack([H.real, H.imag], axis=-1))
     y = np.zeros((3, 3, 2))
-    _check(lib().or_link_fd(float(f), float(L_s), _p(k), _p(x), _p(Hr), _p(y)), "or_link_fd")
+    _check(lib().or_link_fd(float(f), float(L_s), _p(k), _p(x), _p(Hr), _p(y), int(bool(unit))), "or_link_fd")
     return y[..., 0] + 1j * y[..., 1]
 
 

@@ -736,14 +736,15 @@ int or_orbit(const or_detector* det, double t, double* x) {
 }
 
 int or_link_fd(double f, double L_s, const double* k, const double* x, const double* H,
-               double* y) {
+               double* y, int unit) {
+  if (unit != 0 && unit != 1) return -1;
   double kk[3] = {k[0], k[1], k[2]};
   double xx[3][3];
   std::memcpy(xx, x, sizeof(xx));
   Cx<double> HH[3][3], yy[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) HH[i][j] = Cx<double>(H[2 * (3 * i + j)], H[2 * (3 * i + j) + 1]);
-  add_links(f, L_s, kk, xx, HH, yy);
+  add_links(f, L_s, kk, xx, HH, yy, unit == 1);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) { y[2 * (3 * i + j)] = yy[i][j].re; y[2 * (3 * i + j) + 1] = yy[i][j].im; }
   return 0;

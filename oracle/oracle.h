@@ -78,9 +78,12 @@ int or_orbit(const or_detector* det, double t, double* x);
 /* Six single-link transfer functions for a static geometry.
    k[3]: propagation direction; x[3][3]: spacecraft positions [light-s];
    H[3][3] complex: Fourier-domain strain tensor at f; L_s: arm [s].
+   unit = 0: link directions (x_r - x_s) / L_s (the rigid triangle); unit = 1:
+   the unit separations (x_r - x_s) / |x_r - x_s| (exact Kepler orbits), the
+   transfer function keeping L_s.
    out y[3][3] complex, y[r][s] = link received at r, sent from s (diag 0). */
 int or_link_fd(double f, double L_s, const double* k, const double* x,
-               const double* H, double* y);
+               const double* H, double* y, int unit);
 
 /* TDI X, Y, Z and A, E, T from the six links y[3][3] (layout as above). */
 int or_tdi(double f, double L_s, int gen, const double* y, double* xyz, double* aet);

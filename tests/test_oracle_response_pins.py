@@ -91,6 +91,36 @@ def test_fd_links_and_tdi_match_time_domain_bruteforce(orc, gen, f0):
     assert np.abs(aet_td - aet_fd).max() <= 1e-11 * scale
 
 
+def test_unit_separation_links(orc):
+    """The link directions of exact Kepler orbits (unit = True: the unit
+    separations, the transfer function keeping the nominal L).  On a triangle of
+    side L they are the rigid triangle's (x_r - x_s) / L, so both options agree
+    for any wave; with the wave travelling along the triangle's normal, k.n = 0
+    and k.x_r = k.c for every spacecraft, so the unit-separation links do not
+    change when the triangle is scaled about its centroid (with (x_r - x_s) / L
+    they would scale as s^2)."""
+    rng = np.random.default_rng(5)
+    L, x, k, ep, ec, H, Hp, Hc = _frame(rng)
+    for f in (3e-3, 2.1e-2):
+        a, b = orc.link_fd(f, L, k, x, H), orc.link_fd(f, L, k, x, H, unit=True)
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+    c = x.mean(axis=0)
+    nrm = np.cross(x[1] - x[0], x[2] - x[0])
+    kn = nrm / np.linalg.norm(nrm)
+    p = np.cross(kn, rng.normal(size=3))
+    p /= np.linalg.norm(p)
+    q = np.cross(kn, p)
+    Hn = Hp * (np.outer(p, p) - np.outer(q, q)) + Hc * (np.outer(p, q) + np.outer(q, p))
+    for f in (3e-3, 2.1e-2):
+        ref = orc.link_fd(f, L, kn, x, Hn, unit=True)
+        for sc in (0.9, 1.03):
+            xs = c + sc * (x - c)
+            got = orc.link_fd(f, L, kn, xs, Hn, unit=True)
+            assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), (f, sc)
+            rigid = orc.link_fd(f, L, kn, xs, Hn)
+            assert np.allclose(rigid[0, 1], sc ** 2 * ref[0, 1], rtol=1e-12)
+
+
 def test_long_wavelength_limit_matches_antenna_pattern(orc):
     """fL << 1: X_1.5 -> 4 (2 pi f L)^2 (F+ h+ + Fx hx) e^{-2 pi i f k.x1}, with the
     60-degree Michelson pattern F = (b.e.b - a.e.a)/2 of the arms a, b leaving S/C 1."""
