@@ -70,8 +70,7 @@ typedef struct {
                           heliocentric detector of a context takes the same); TianQin: 0.
                           With PES_ORBIT_KEPLER the link directions are the unit separations
                           of the spacecraft at t_f, the transfer function and the TDI factor
-                          keep the nominal L; pes_probe refuses such a context
-                          (PES_EINVAL). */
+                          keep the nominal L. */
 } pes_detector;
 
 typedef struct {
@@ -133,7 +132,8 @@ int pes_noise(pes_ctx* ctx, uint64_t seed, double* out, void* stream);
  *   PES_PROBE_GEOM  [B][n_det][n_modes][n_bins][12]: at the mode's t_f, for
  *     arms t = 0, 1, 2 (arm t opposite spacecraft t): k.n_t, (n_t.p)^2 -
  *     (n_t.q)^2, (n_t.p)(n_t.q), then k.(x_0 - c), k.(x_1 - c) and k.c [light-s]
- *     (x_s spacecraft, c the constellation centre; eq. eq_fd_resp's geometry);
+ *     (x_s spacecraft, c the constellation centre; eq. eq_fd_resp's geometry;
+ *     n_t the unit separation on exact Kepler orbits);
  *   PES_PROBE_LINKS [B][n_det][n_bins][12]: per arm t (Re, Im) of the forward
  *     and backward link sums of eq. eq_fd_resp over modes, divided by the
  *     common factor -i pi f L e^{-i pi f L}: arm 0 carries y_32 / y_23, arm 1

@@ -630,22 +630,19 @@ int pes_noise(pes_ctx* c, uint64_t seed, double* out, void* stream) {
 int pes_probe(pes_ctx* c, const double* theta, int64_t B, int stage, double* out, void* stream) {
   if (!c || (B > 0 && (!theta || !out)) || B < 0 || B > 65535 || stage < PES_PROBE_MODE || stage > PES_PROBE_LINKS)
     return PES_EINVAL;
-  if (c->kep) {
-    snprintf(c->err, sizeof(c->err), "stage probes evaluate the first-order orbit only");
-    return PES_EINVAL;
-  }
   if (B == 0) return PES_OK;
   int st = ensure_workspace(c, B);
   if (st != PES_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   PES_HIP(c, launch_setup(theta, B, c->wtab, c->ntiles, setup_args(c), s));
+  if (c->kep) PES_HIP(c, launch_kepler_proj(theta, B, c->kep_tab, setup_args(c), c->wkep, s));
   ResponseArgs ra;   // the stage probes evaluate in FP64 whatever the precision setting
   ra.bins = c->bins;
   ra.tabs = c->tabs;
   ra.wtab = c->wtab;
   ra.wtab32 = nullptr;
-  ra.wkep = nullptr;
-  ra.kep = nullptr;
+  ra.wkep = c->kep ? c->wkep : nullptr;
+  ra.kep = c->kep ? c->kep_tab : nullptr;
   ra.wkep32 = nullptr;
   ra.kep32 = nullptr;
   ra.out = out;
@@ -654,7 +651,7 @@ int pes_probe(pes_ctx* c, const double* theta, int64_t B, int stage, double* out
   ra.n_det = c->cfg.n_det;
   ra.plan = c->plan;
   ra.dt = c->dt;
-  PES_HIP(c, launch_probe(ra, B, c->long_sinc, stage, s));
+  PES_HIP(c, launch_probe(ra, B, c->long_sinc, c->kep, stage, s));
   return PES_OK;
 }
 

@@ -910,7 +910,8 @@ __global__ void table32_kernel(const double* __restrict__ wtab, int64_t n, float
 
 // ---------------------------------------------------------------- stage probes
 // The evaluation of the response with hooks that write its stages out, one
-// thread per (walker, bin), every mode its own unit.  Test entry point only.
+// thread per (walker, bin), every mode its own unit; KEP: heliocentric
+// detectors on exact Kepler ellipses.  Test entry point only.
 struct ProbeWriter {
   int stage, det, n_modes, n_det;
   int64_t b, k, N;
@@ -942,7 +943,7 @@ struct ProbeWriter {
   }
 };
 
-template <bool LS>
+template <bool LS, bool KEP>
 __global__ void probe_kernel(ResponseArgs A, int64_t B, int stage) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = A.N;
@@ -984,6 +985,10 @@ __global__ void probe_kernel(ResponseArgs A, int64_t B, int stage) {
       eval_channels_t<true, LS, 1, double, ValTab, ProbeWriter>(ValTab{wt}, det, plan, P.inv_year, P.inv_ptq, br,
                                                                tb[T_A * N + k], tb[T_ZR * N + k],
                                                                tb[T_ZI * N + k], pw);
+    else if constexpr (KEP)
+      eval_channels_t<false, LS, 1, double, ValTab, ProbeWriter, true>(
+          ValTab{wt}, det, plan, P.inv_year, P.inv_ptq, br, tb[T_A * N + k], tb[T_ZR * N + k], tb[T_ZI * N + k],
+          pw, A.wkep + (b * A.n_det + det) * KW_STRIDE, A.kep + det * KV_STRIDE + KV_INVL);
     else
       eval_channels_t<false, LS, 1, double, ValTab, ProbeWriter>(ValTab{wt}, det, plan, P.inv_year, P.inv_ptq, br,
                                                                 tb[T_A * N + k], tb[T_ZR * N + k],
@@ -1096,13 +1101,19 @@ hipError_t launch_finalize(const double* partial, const int* ntiles, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, int stage, hipStream_t s) {
+template <bool LS, bool KEP>
+static void launch_pr(const ResponseArgs& a, int64_t B, int stage, dim3 grid, hipStream_t s) {
+  hipLaunchKernelGGL((probe_kernel<LS, KEP>), grid, dim3(64), 0, s, a, B, stage);
+}
+
+hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, bool kep, int stage, hipStream_t s) {
+  if (kep && (!a.wkep || !a.kep)) return hipErrorInvalidValue;
   const int64_t n = B * a.N;
   const dim3 grid((unsigned)((n + 63) / 64));
-  if (long_sinc)
-    hipLaunchKernelGGL(probe_kernel<true>, grid, dim3(64), 0, s, a, B, stage);
+  if (kep)
+    long_sinc ? launch_pr<true, true>(a, B, stage, grid, s) : launch_pr<false, true>(a, B, stage, grid, s);
   else
-    hipLaunchKernelGGL(probe_kernel<false>, grid, dim3(64), 0, s, a, B, stage);
+    long_sinc ? launch_pr<true, false>(a, B, stage, grid, s) : launch_pr<false, false>(a, B, stage, grid, s);
   return hipGetLastError();
 }
 

@@ -105,7 +105,7 @@ hipError_t launch_table32(const double* wtab, int64_t B, float* wtab32, hipStrea
 hipError_t launch_copy_f32(const double* src, int64_t n, float* dst, hipStream_t s);
 hipError_t launch_finalize(const double* partial, const int* ntiles, const double* wtab, const double* dd,
                            int64_t B, double* logl, hipStream_t s);
-hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, int stage, hipStream_t s);
+hipError_t launch_probe(const ResponseArgs& a, int64_t B, bool long_sinc, bool kep, int stage, hipStream_t s);
 hipError_t launch_response(const ResponseArgs& a, int64_t B, bool long_sinc, bool f32, bool kep, hipStream_t s);
 int loglike_blocks_per_cu(int bpl, bool long_sinc, bool f32, bool kep);
 

@@ -70,8 +70,9 @@ enum : int {
 // ---- exact Keplerian heliocentric orbits (detector option).  Every
 // orbit-dependent vector is a periodic function of the revolution phase alpha,
 // kept as a Fourier series to harmonic kKepH (the Kepler ellipses' series
-// converge as e^k; e ~ 5e-3): term 0 the constant, 2k - 1 the cos(k alpha)
-// and 2k the sin(k alpha) coefficient.
+// converge roughly as e^k; e ~ 5e-3; the inverse arm lengths, truncated here,
+// keep a relative 4e-11, the separations 3e-14 s): term 0 the constant,
+// 2k - 1 the cos(k alpha) and 2k the sin(k alpha) coefficient.
 constexpr int kKepH = 6;
 constexpr int kKepT = 2 * kKepH + 1;   // 13 terms
 // Per detector (host-computed, walker-independent), light-seconds: the arm

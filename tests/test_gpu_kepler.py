@@ -6,9 +6,9 @@ LISA alone, on the three-detector network (TianQin stays geocentric), on the
 paper's 32703-bin grid (long sinc fits) and with TDI 1.5; both bin-per-lane
 kernel variants.  Gradients (forward mode, whichever method is set) and Fisher
 matrices against the oracle's dual numbers on the same orbits, at the
-tolerances of the first-order orbit's derivative tests.  The stage probes,
-which evaluate the first-order orbit only, refuse these contexts (single
-precision on these orbits is tested with the other FP32 cases)."""
+tolerances of the first-order orbit's derivative tests.  Single precision and
+the stage probes on these orbits are tested with the other FP32 cases and
+stage tests."""
 import numpy as np
 import pytest
 
@@ -237,15 +237,10 @@ def test_kepler_fisher_differs_from_first_order(orc, torch_dev, pes):
     assert np.abs((Fs[0] - Fs[1] - F_or) / dg).max() <= 2e-6
 
 
-def test_kepler_refusals(torch_dev, pes):
-    torch = torch_dev
-    cfg = _cfg("cfg0")
-    ctx = pes.Context(cfg)
-    ctx.set_data(torch.zeros((1, 3, cfg["n_bins"], 2), dtype=torch.float64, device="cuda"))
-    th = torch.from_numpy(W.draw_walkers(4, stream=3)).to("cuda")
-    with pytest.raises(pes.PesError):
-        ctx.probe(th, "mode")
-    ctx.close()
+def test_kepler_refusals(pes):
+    """Configurations the orbit option does not define: heliocentric detectors
+    on different orbit models in one context, and a geocentric detector on
+    Kepler ellipses."""
     mixed = dict(W.config("cfg2", n_bins=1000))
     mixed["detectors"] = [dict(W.LISA, orbit="kepler"), W.TAIJI, W.TIANQIN]
     with pytest.raises(pes.PesError):
