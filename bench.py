@@ -460,7 +460,8 @@ def kepler_leg(torch, pes, steps):
     ellipses (arms flexing at order e^2 AU) instead of the first-order
     triangle: evals/s at the autotuned tuning and the cost relative to the
     first-order orbit in the same run, in FP64 and with the single-precision
-    kernels (and their deviation from FP64 relative to max(|L|, <d|d>/2));
+    kernels (and their deviation from FP64 relative to max(|L|, <d|d>/2)),
+    each also at the context's default tuning (the autotuner's gain);
     then the derivatives on both orbits (Fisher matrices at 256 points,
     forward- and reverse-mode gradients at 1024 walkers)."""
     out = {}
@@ -478,14 +479,18 @@ def kepler_leg(torch, pes, steps):
         far = th0.clone()
         far[0, 4] = 1e12
         sigma = -float(ctx.loglike(far)[0])           # <d|d>/2
+        default_ms = _time_ms(torch, lambda: ctx.loglike(theta, o), steps)   # the context's default tuning
         _, tuning = ctx.autotune(theta)
         out[orbit] = dict(ms_per_call=round(_time_ms(torch, lambda: ctx.loglike(theta, o), steps), 3),
-                          tuning=tuning)
+                          tuning=tuning, default_tuning_ms=round(default_ms, 3))
         L64 = o.cpu().numpy().copy()
         ctx.set_precision(32)
+        ctx.set_tuning(1, 16, 0)
+        default32_ms = _time_ms(torch, lambda: ctx.loglike(theta, o), steps)
         _, tuning32 = ctx.autotune(theta)
         out[orbit]["fp32_ms_per_call"] = round(_time_ms(torch, lambda: ctx.loglike(theta, o), steps), 3)
         out[orbit]["fp32_tuning"] = tuning32
+        out[orbit]["fp32_default_tuning_ms"] = round(default32_ms, 3)
         rel = np.abs(o.cpu().numpy() - L64) / np.maximum(np.abs(L64), sigma)
         out[orbit]["fp32_max_rel_dev_from_fp64"] = float(f"{rel.max():.3e}")
         ctx.set_precision(64)
@@ -503,6 +508,10 @@ def kepler_leg(torch, pes, steps):
                 ms_per_call=k["ms_per_call"], evals_per_s=round(4096 / (k["ms_per_call"] * 1e-3), 1),
                 tuning=k["tuning"], first_order_ms_per_call_same_run=f["ms_per_call"],
                 cost_over_first_order=round(k["ms_per_call"] / f["ms_per_call"], 3),
+                default_tuning_ms=k["default_tuning_ms"],
+                autotune_gain=round(k["default_tuning_ms"] / k["ms_per_call"], 3),
+                fp32_default_tuning_ms=k["fp32_default_tuning_ms"],
+                fp32_autotune_gain=round(k["fp32_default_tuning_ms"] / k["fp32_ms_per_call"], 3),
                 fp32_ms_per_call=k["fp32_ms_per_call"], fp32_evals_per_s=round(4096 / (k["fp32_ms_per_call"] * 1e-3), 1),
                 fp32_tuning=k["fp32_tuning"], fp32_first_order_ms_per_call=f["fp32_ms_per_call"],
                 fp32_speedup_over_fp64=round(k["ms_per_call"] / k["fp32_ms_per_call"], 3),
