@@ -154,7 +154,9 @@ def test_loglike_fp32(orc, torch_dev, pes, case):
     for bpl in (1, 2):
         ctx.set_tuning(bpl, 16, 0)
         Ls.append(ctx.loglike(tht).cpu().numpy())
+    Ln = ctx.loglike_noalloc(tht).cpu().numpy()   # the same kernels in the library's scratch array
     ctx.close()
+    assert np.array_equal(Ln, Ls[1])
     L_or = orc.loglike(cfg, d, th)
     sigma = 0.5 * orc.inner(cfg, d, d)
     bound = 2.0 * _loglike_bound(orc, cfg, d, th) + 1e-9 * np.maximum(np.abs(L_or), sigma)
