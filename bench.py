@@ -604,6 +604,38 @@ def _fisher_start(ctx, torch, B, seed):
     return np.clip(x, lo + eps, hi - eps)
 
 
+def flow_leg(torch, pes, fit_steps=200, batch=4096, rows=1 << 17, n_eval=16384):
+    """The learned proposal's network on its own: Adam steps of the NLL fit at
+    the ESS leg's minibatch (4096 rows), and one normalizing (log q) and one
+    sampling pass over 16384 rows (the ensemble of the config-4 sampler), on
+    synthetic 11-D training rows (a correlated Gaussian bent along two
+    coordinates).  All products run on the BF16 matrix-core GEMM."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5)
+    A = rng.normal(size=(11, 11)) / 4 + np.eye(11)
+    x = rng.normal(size=(rows, 11)) @ A.T
+    x[:, 1] += 0.5 * x[:, 0] ** 2
+    x[:, 3] -= 0.3 * x[:, 2] ** 2
+    tr = torch.from_numpy(x).to(dev)
+    flow = pes.Flow(seed=11)
+    flow.fit(tr, steps=5, batch=batch, lr=1e-3, seed=1)          # warm-up (workspace, first launches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = flow.fit(tr, steps=fit_steps, batch=batch, lr=1e-3, seed=2)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    ev = tr[:n_eval].contiguous()
+    t_fwd = _time_ms(torch, lambda: flow.forward(ev), 20)
+    z = torch.randn((n_eval, 11), dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(3))
+    t_inv = _time_ms(torch, lambda: flow.inverse(z), 20)
+    flow.close()
+    first_last = [float(loss[0]), float(loss[-1])] if hasattr(loss, "__len__") else None
+    return dict(workload=f"8 coupling layers, width 256; fit minibatch {batch} rows of {rows} synthetic 11-D rows; "
+                         f"passes over {n_eval} rows",
+                fit_steps=fit_steps, ms_per_fit_step=round(t_fit / fit_steps * 1e3, 3),
+                forward_ms=round(t_fwd, 3), inverse_ms=round(t_inv, 3), fit_loss_first_last=first_last)
+
+
 def ess_leg(torch, pes, B, n_pilot, n_collect, n_run, fit_steps, tau=1.1, fit_batch=4096, ref_walkers=1024,
             n_ref=3000):
     """ESS/s of the plain DE-MC sampler against the mixture with the learned
@@ -746,7 +778,7 @@ def main():
                     help="bins_per_lane,walkers_per_group,blocks_per_cu (skips the autotuner)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline measurement (no extra legs)")
-    ap.add_argument("--extras", default="derivatives,graph,config2,fp32,kepler,fisher_sampling,paper_pe,ess",
+    ap.add_argument("--extras", default="derivatives,graph,config2,fp32,kepler,fisher_sampling,paper_pe,flow,ess",
                     help="comma list of the extra legs to run after the headline")
     ap.add_argument("--ess-walkers", type=int, default=16384)
     ap.add_argument("--ess-pilot", type=int, default=300)
@@ -857,6 +889,9 @@ def main():
     if "paper_pe" in extras:
         print("[bench] paper's PE workload", file=sys.stderr, flush=True)
         rec["paper_pe"] = paper_pe_leg(torch, pes)
+    if "flow" in extras:
+        print("[bench] learned proposal network", file=sys.stderr, flush=True)
+        rec["flow"] = flow_leg(torch, pes)
     if "ess" in extras:
         print("[bench] ESS", file=sys.stderr, flush=True)
         rec["ess"] = ess_leg(torch, pes, args.ess_walkers, args.ess_pilot, args.ess_collect, args.ess_steps,

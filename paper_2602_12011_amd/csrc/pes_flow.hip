@@ -68,11 +68,17 @@ struct Norm {
 // ------------------------------------------------------------------ GEMM
 // C[m][n] = sum_k A(m, k) B(n, k) with BF16 operands and FP32 accumulation.
 // A(m, k) = A[m lda + k] (A_ROW) or A[k lda + m]; B(n, k) = B[n ldb + k]
-// (B_ROW) or B[k ldb + n].  M, N, K are multiples of 32.  A 32 x 32 output
-// tile per block of four waves; each wave owns a 16 x 16 tile and issues one
-// 16x16x32 matrix-core operation per 32-deep slab staged through LDS (both
-// operand layouts are loaded coalesced and transposed in LDS as needed).
+// (B_ROW) or B[k ldb + n].  M, N, K are multiples of 32.  A TM x TN output
+// tile (TM, TN in {32, 64}) per block of four waves in a 2 x 2 arrangement;
+// each wave owns a (TM / 2) x (TN / 2) tile of 16 x 16 matrix-core blocks and
+// issues one 16x16x32 operation per block per 32-deep slab staged through LDS
+// (both operand layouts are loaded coalesced and transposed in LDS as needed).
+// Split over K (EPI_F32 only, for the weight gradients, whose K is the batch):
+// block z of the grid's third dimension sums its share of the slabs into
+// part[z][M][N]; split_reduce_kernel adds the shares in order (deterministic).
 enum : int { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_RELU_BF16 = 2, EPI_MASK = 3 };
+
+constexpr int kMaxSplit = 16;   // shares of K in a split product (part buffer: kMaxSplit x kHid x kHid)
 
 struct GemmArgs {
   const __bf16* A;
@@ -88,67 +94,124 @@ struct GemmArgs {
   __bf16* Cb;            // BF16 out
   int64_t ldcb;
   int m_valid, n_valid;  // EPI_F32: rows / columns written
+  float* part;           // split products: [split][M][N] (M N <= kHid kHid)
+  int split;             // shares of K (1: no split)
 };
 
-template <bool A_ROW, bool B_ROW, int EPI>
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[32][40];   // [m][k], rows padded to 80 bytes
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[32][40];   // [n][k]
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
-  const int wm = (wv >> 1) * 16, wn = (wv & 1) * 16;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  const int t = tid & 127, r = t >> 2, c = (t & 3) * 8;
-  for (int k0 = 0; k0 < g.K; k0 += 32) {
-    if (tid < 128) {
-      if (A_ROW) {
-        *(bf16x8*)&As[r][c] = *(const bf16x8*)(g.A + (int64_t)(m0 + r) * g.lda + k0 + c);
-      } else {   // r indexes k, c indexes m
-        const bf16x8 v = *(const bf16x8*)(g.A + (int64_t)(k0 + r) * g.lda + m0 + c);
+// Stages rows r0.. of a slab: R rows of 32 k-values (ROW: X[(o + r) ld + k0 + c],
+// else the transpose X[(k0 + r) ld + o + c]) into S[R][40], one bf16x8 per thread
+// for the threads t < 4 R.
+template <bool ROW, int R>
+__device__ __forceinline__ void stage_slab(__bf16 (*S)[40], const __bf16* X, int64_t ld, int o, int k0, int t) {
+  if (t >= 4 * R) return;
+  if (ROW) {
+    const int r = t >> 2, c = (t & 3) * 8;
+    *(bf16x8*)&S[r][c] = *(const bf16x8*)(X + (int64_t)(o + r) * ld + k0 + c);
+  } else {   // r indexes k (32 of them), c the R output rows
+    constexpr int PER = R / 8;
+    const int r = t / PER, c = (t % PER) * 8;
+    const bf16x8 v = *(const bf16x8*)(X + (int64_t)(k0 + r) * ld + o + c);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) As[c + e][r] = v[e];
-      }
-    } else {
-      if (B_ROW) {
-        *(bf16x8*)&Bs[r][c] = *(const bf16x8*)(g.B + (int64_t)(n0 + r) * g.ldb + k0 + c);
-      } else {
-        const bf16x8 v = *(const bf16x8*)(g.B + (int64_t)(k0 + r) * g.ldb + n0 + c);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[c + e][r] = v[e];
-      }
-    }
-    __syncthreads();
-    // operand lanes: A[i = lane % 16][k = 8 (lane / 16) + e], B likewise by column
-    const bf16x8 a = *(const bf16x8*)&As[wm + (lane & 15)][8 * (lane >> 4)];
-    const bf16x8 b = *(const bf16x8*)&Bs[wn + (lane & 15)][8 * (lane >> 4)];
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-    __syncthreads();
-  }
-  // result lanes: element e of lane l is (row 4 (l / 16) + e, column l % 16)
-  const int n = n0 + wn + (lane & 15);
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int m = m0 + wm + 4 * (lane >> 4) + e;
-    float v = acc[e];
-    if (EPI == EPI_F32) {
-      if (m < g.m_valid && n < g.n_valid) g.C[(int64_t)m * g.ldc + n] = v;
-    } else if (EPI == EPI_BIAS_F32) {
-      g.C[(int64_t)m * g.ldc + n] = v + g.bias[n];
-    } else if (EPI == EPI_BIAS_RELU_BF16) {
-      v = fmaxf(v + g.bias[n], 0.0f);
-      g.Cb[(int64_t)m * g.ldcb + n] = (__bf16)v;
-    } else {   // EPI_MASK
-      if (!((float)g.mask[(int64_t)m * g.ldm + n] > 0.0f)) v = 0.0f;
-      g.C[(int64_t)m * g.ldc + n] = v;
-      g.Cb[(int64_t)m * g.ldcb + n] = (__bf16)v;
-    }
+    for (int e = 0; e < 8; ++e) S[c + e][r] = v[e];
   }
 }
 
+template <bool A_ROW, bool B_ROW, int EPI, int TM, int TN>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+  constexpr int MI = TM / 32, NJ = TN / 32;   // 16 x 16 blocks per wave
+  __shared__ __attribute__((aligned(16))) __bf16 As[TM][40];   // [m][k], rows padded to 80 bytes
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[TN][40];   // [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int wm = (wv >> 1) * (TM / 2), wn = (wv & 1) * (TN / 2);
+  // this block's slabs of K
+  const int slabs = g.K / 32, z = blockIdx.z;
+  const int s0 = (int)((int64_t)slabs * z / g.split), s1 = (int)((int64_t)slabs * (z + 1) / g.split);
+  f32x4 acc[MI][NJ];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) acc[i][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int sl = s0; sl < s1; ++sl) {
+    const int k0 = sl * 32;
+    stage_slab<A_ROW, TM>(As, g.A, g.lda, m0, k0, tid);
+    stage_slab<B_ROW, TN>(Bs, g.B, g.ldb, n0, k0, (tid + 4 * TM) & 255);
+    __syncthreads();
+    // operand lanes: A[i = lane % 16][k = 8 (lane / 16) + e], B likewise by column
+    bf16x8 a[MI], b[NJ];
+#pragma unroll
+    for (int i = 0; i < MI; ++i) a[i] = *(const bf16x8*)&As[wm + 16 * i + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) b[jj] = *(const bf16x8*)&Bs[wn + 16 * jj + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int jj = 0; jj < NJ; ++jj) acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[jj], acc[i][jj], 0, 0, 0);
+    __syncthreads();
+  }
+  // result lanes: element e of lane l is (row 4 (l / 16) + e, column l % 16)
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const int n = n0 + wn + 16 * jj + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + e;
+        float v = acc[i][jj][e];
+        if (EPI == EPI_F32) {
+          if (g.split > 1)
+            g.part[((int64_t)z * g.M + m) * g.N + n] = v;
+          else if (m < g.m_valid && n < g.n_valid)
+            g.C[(int64_t)m * g.ldc + n] = v;
+        } else if (EPI == EPI_BIAS_F32) {
+          g.C[(int64_t)m * g.ldc + n] = v + g.bias[n];
+        } else if (EPI == EPI_BIAS_RELU_BF16) {
+          v = fmaxf(v + g.bias[n], 0.0f);
+          g.Cb[(int64_t)m * g.ldcb + n] = (__bf16)v;
+        } else {   // EPI_MASK
+          if (!((float)g.mask[(int64_t)m * g.ldm + n] > 0.0f)) v = 0.0f;
+          g.C[(int64_t)m * g.ldc + n] = v;
+          g.Cb[(int64_t)m * g.ldcb + n] = (__bf16)v;
+        }
+      }
+    }
+}
+
+// C[m][n] = sum over the shares z = 0, 1, ... of part[z][m][n], m < m_valid, n < n_valid.
+__global__ void split_reduce_kernel(GemmArgs g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)g.m_valid * g.n_valid) return;
+  const int m = (int)(i / g.n_valid), n = (int)(i % g.n_valid);
+  float v = 0.0f;
+  for (int z = 0; z < g.split; ++z) v += g.part[((int64_t)z * g.M + m) * g.N + n];
+  g.C[(int64_t)m * g.ldc + n] = v;
+}
+
+template <bool AR, bool BR, int EPI, int TM, int TN>
+static void launch_gemm(const GemmArgs& g, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_kernel<AR, BR, EPI, TM, TN>), dim3(g.N / TN, g.M / TM, g.split), dim3(256), 0, s, g);
+}
+
+// Tiles of 64 where the shape allows; products with fewer than 256 tiles and a
+// long K (the weight gradients) split K into up to kMaxSplit shares of at
+// least eight slabs.
 template <bool AR, bool BR, int EPI>
-hipError_t gemm(const GemmArgs& g, hipStream_t s) {
+hipError_t gemm(GemmArgs g, hipStream_t s) {
   if (g.M % 32 || g.N % 32 || g.K % 32 || g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_kernel<AR, BR, EPI>), dim3(g.N / 32, g.M / 32), dim3(256), 0, s, g);
+  const int TM = g.M % 64 ? 32 : 64, TN = g.N % 64 ? 32 : 64;
+  const int tiles = (g.M / TM) * (g.N / TN);
+  g.split = 1;
+  if (EPI == EPI_F32 && g.part && tiles < 256 && (int64_t)g.M * g.N <= (int64_t)kHid * kHid)
+    g.split = std::max(1, std::min({kMaxSplit, 256 / tiles, g.K / (32 * 8)}));
+  if (TM == 64 && TN == 64) launch_gemm<AR, BR, EPI, 64, 64>(g, s);
+  else if (TM == 64) launch_gemm<AR, BR, EPI, 64, 32>(g, s);
+  else if (TN == 64) launch_gemm<AR, BR, EPI, 32, 64>(g, s);
+  else launch_gemm<AR, BR, EPI, 32, 32>(g, s);
+  if (g.split > 1) {
+    const int64_t n = (int64_t)g.m_valid * g.n_valid;
+    hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+  }
   return hipGetLastError();
 }
 
@@ -467,6 +530,7 @@ struct pes_flow {
   float *gy = nullptr, *gx = nullptr, *gOf = nullptr, *dpf = nullptr, *dXc = nullptr;
   __bf16 *gOb = nullptr, *dpb = nullptr;
   double *rowv = nullptr, *batchbuf = nullptr, *mom = nullptr;
+  float* kpart = nullptr;   // shares of the split weight-gradient products [kMaxSplit][kHid][kHid]
   char err[256] = {0};
 };
 
@@ -639,7 +703,7 @@ int pass_backward(pes_flow* f, int64_t n, int64_t Mp, double* nll, hipStream_t s
     // dW3[i][o] = sum_m H2[m][i] gO[m][o]
     memset(&g, 0, sizeof(g));
     g.A = H2; g.lda = kHid; g.B = f->gOb; g.ldb = kPad; g.M = kHid; g.N = kPad; g.K = (int)Mp;
-    g.C = f->G + td[4].off; g.ldc = 2 * ls.nt; g.m_valid = kHid; g.n_valid = 2 * ls.nt;
+    g.C = f->G + td[4].off; g.ldc = 2 * ls.nt; g.m_valid = kHid; g.n_valid = 2 * ls.nt; g.part = f->kpart;
     FL_HIP(f, (gemm<false, false, EPI_F32>(g, s)));
     hipLaunchKernelGGL(colsum_kernel, dim3(2 * ls.nt), dim3(256), 0, s, f->gOf, (int64_t)kPad, Mp, f->G + td[5].off);
     // dpre2 = (gO W3^T) * [H2 > 0]: B(n = i, k = o) = W3[i][o]
@@ -650,7 +714,7 @@ int pass_backward(pes_flow* f, int64_t n, int64_t Mp, double* nll, hipStream_t s
     // dW2 = H1^T dpre2, db2
     memset(&g, 0, sizeof(g));
     g.A = H1; g.lda = kHid; g.B = dpb2; g.ldb = kHid; g.M = kHid; g.N = kHid; g.K = (int)Mp;
-    g.C = f->G + td[2].off; g.ldc = kHid; g.m_valid = kHid; g.n_valid = kHid;
+    g.C = f->G + td[2].off; g.ldc = kHid; g.m_valid = kHid; g.n_valid = kHid; g.part = f->kpart;
     FL_HIP(f, (gemm<false, false, EPI_F32>(g, s)));
     hipLaunchKernelGGL(colsum_kernel, dim3(kHid), dim3(256), 0, s, dpf2, (int64_t)kHid, Mp, f->G + td[3].off);
     // dpre1 = (dpre2 W2^T) * [H1 > 0]
@@ -661,7 +725,7 @@ int pass_backward(pes_flow* f, int64_t n, int64_t Mp, double* nll, hipStream_t s
     // dW1 = Xc^T dpre1 (rows i < n_C), db1
     memset(&g, 0, sizeof(g));
     g.A = Xc; g.lda = kPad; g.B = dpb1; g.ldb = kHid; g.M = kPad; g.N = kHid; g.K = (int)Mp;
-    g.C = f->G + td[0].off; g.ldc = kHid; g.m_valid = ls.nc; g.n_valid = kHid;
+    g.C = f->G + td[0].off; g.ldc = kHid; g.m_valid = ls.nc; g.n_valid = kHid; g.part = f->kpart;
     FL_HIP(f, (gemm<false, false, EPI_F32>(g, s)));
     hipLaunchKernelGGL(colsum_kernel, dim3(kHid), dim3(256), 0, s, dpf1, (int64_t)kHid, Mp, f->G + td[1].off);
     FL_HIP(f, hipGetLastError());
@@ -736,6 +800,7 @@ void destroy(pes_flow* f) {
   (void)hipFree(f->wb);
   (void)hipFree(f->bp);
   (void)hipFree(f->mom);
+  (void)hipFree(f->kpart);
   delete f;
 }
 
@@ -846,7 +911,8 @@ int pes_flow_create(uint64_t seed, pes_flow** out) {
       hipMalloc(&f->m1, sizeof(float) * np) != hipSuccess || hipMalloc(&f->m2, sizeof(float) * np) != hipSuccess ||
       hipMalloc(&f->wb, sizeof(__bf16) * kLayers * kLayerW) != hipSuccess ||
       hipMalloc(&f->bp, sizeof(float) * kLayers * kLayerB) != hipSuccess ||
-      hipMalloc(&f->mom, sizeof(double) * (kD + kD * kD)) != hipSuccess) {
+      hipMalloc(&f->mom, sizeof(double) * (kD + kD * kD)) != hipSuccess ||
+      hipMalloc(&f->kpart, sizeof(float) * kMaxSplit * kHid * kHid) != hipSuccess) {
     destroy(f);
     return PES_ENOMEM;
   }
