@@ -163,8 +163,9 @@ int pes_loglike(pes_ctx* ctx, const double* theta, int64_t B, double* logl, void
  * instead of the context's; it calls no allocator.  A batch needs, rounded up
  * to 256 bytes per part, 3456 B (walker tables, FP64 and FP32) + 12 B (plan)
  * per walker plus 16 B per walker per bin tile (ceil(n_bins / (256 x bins per
- * lane)) tiles): about 970 walkers at 2^20 bins and one bin per lane, about
- * 12000 at 32703 bins.  PES_ESHAPE (message in pes_last_error) for a larger batch, PES_EHIP
+ * lane)) tiles), and on exact Kepler orbits 1600 B per walker and detector
+ * (the projected orbit series; 800 B more in single precision): about 970
+ * walkers at 2^20 bins and one bin per lane, about 12000 at 32703 bins.  PES_ESHAPE (message in pes_last_error) for a larger batch, PES_EHIP
  * if the array has no address on the context's device; otherwise as
  * pes_loglike.  Every call on one GPU works in that GPU's single array: calls
  * that overlap in time on one GPU (other streams, other contexts, other
