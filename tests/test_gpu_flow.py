@@ -157,10 +157,11 @@ def test_identity_flow_is_the_standardized_gaussian(torch_dev, pes, F):
     assert np.allclose(lq.cpu().numpy(), ref, rtol=1e-6, atol=1e-6)
 
 
-def test_nll_gradient_matches_reference(torch_dev, pes, F):
+@pytest.mark.parametrize("n", [517, 4133])   # weight gradients split over K into 2 and 16 shares
+def test_nll_gradient_matches_reference(torch_dev, pes, F, n):
     torch = torch_dev
     flat = F.init_params(24, scale_out=0.3)
-    th, mu, sigma = _theta(517, 83)
+    th, mu, sigma = _theta(n, 83)
     f = _flow_with(pes, torch, flat, mu, sigma)
     nll, g = f.nll_grad(torch.from_numpy(th).to("cuda"))
     nll, g = float(nll.cpu()), g.cpu().numpy().astype(np.float64)
